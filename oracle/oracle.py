@@ -1,0 +1,326 @@
+"""Python driver of the plain C FP64 oracle (``mfm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark, never by the product path.
+
+The release paper names a Lagrangian mesh-free finite-volume Godunov method
+whose mesh moves with the fluid (abstract; "Arbitrary (Moving) Meshes").
+The pass here follows the standard meshless finite-mass formulation it refers
+to, in the readings R1-R18 listed in the design document: kernel length,
+gradient matrix and limited gradients, faces, HLLC fluxes, accumulation, and
+the kick-drift-kick step with a predicted state.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mfm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class OrParams(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("n_ngb", C.c_double), ("box", C.c_double * 3),
+                ("periodic", C.c_int32 * 3), ("beta", C.c_double), ("cond_max", C.c_double),
+                ("cell", C.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+                               "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        L.or_kernel_W.restype = C.c_double
+        L.or_kernel_W.argtypes = [C.c_double, C.c_double]
+        L.or_kernel_dWdH.restype = C.c_double
+        L.or_kernel_dWdH.argtypes = [C.c_double, C.c_double]
+        L.or_find_neighbours.restype = C.c_int
+        L.or_solve_h.restype = C.c_int
+        L.or_gradients.restype = C.c_int
+        L.or_fluxes.restype = C.c_int
+        L.or_hllc_star.restype = None
+        L.or_face.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp if a.dtype == np.float64 else (_i64p if a.dtype == np.int64 else _u8p))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"oracle {what} failed with status {rc}")
+
+
+@dataclass
+class Setup:
+    """Physical parameters of one run."""
+
+    gamma: float
+    n_ngb: float
+    box: tuple
+    periodic: tuple
+    beta: float = 1.0
+    cond_max: float = 1.0e6
+    cell: float = 0.0       # 0: brute-force neighbour search
+
+    @classmethod
+    def of(cls, w, cell=None, **kw):
+        if cell is None:
+            # a bucket grid of about two mean spacings; 0 (brute force) for tiny sets
+            vol = w.box[0] * w.box[1] * w.box[2]
+            cell = 0.0 if w.n <= 5000 else 2.0 * (vol / w.n) ** (1.0 / 3.0)
+        return cls(gamma=w.gamma, n_ngb=w.n_ngb, box=tuple(w.box), periodic=tuple(w.periodic),
+                   cell=cell, **kw)
+
+    def c(self) -> OrParams:
+        p = OrParams()
+        p.gamma = self.gamma
+        p.n_ngb = self.n_ngb
+        for a in range(3):
+            p.box[a] = self.box[a]
+            p.periodic[a] = int(self.periodic[a])
+        p.beta = self.beta
+        p.cond_max = self.cond_max
+        p.cell = self.cell
+        return p
+
+
+def kernel_W(r, H):
+    return lib().or_kernel_W(float(r), float(H))
+
+
+def kernel_dWdH(r, H):
+    return lib().or_kernel_dWdH(float(r), float(H))
+
+
+def find_neighbours(s: Setup, x, y, z, i, R, cap=100000):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    js = np.zeros(cap, dtype=np.int64)
+    cnt = C.c_int64(0)
+    p = s.c()
+    _check(lib().or_find_neighbours(C.byref(p), C.c_int64(x.size), _p(x), _p(y), _p(z),
+                                    C.c_int64(i), C.c_double(R), C.c_int64(cap), _p(js),
+                                    C.byref(cnt)), "find_neighbours")
+    return js[:cnt.value].copy()
+
+
+def solve_h(s: Setup, x, y, z, H_guess=None, mask=None):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    H = np.zeros(n) if H_guess is None else _f64(H_guess).copy()
+    nk = np.zeros(n)
+    V = np.zeros(n)
+    it = np.zeros(n, dtype=np.int64)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    p = s.c()
+    _check(lib().or_solve_h(C.byref(p), C.c_int64(n), _p(x), _p(y), _p(z), _p(mk), _p(H),
+                            _p(nk), _p(V), _p(it)), "solve_h")
+    return H, nk, V, it
+
+
+def gradients(s: Setup, st: dict, H, nk, V, mask=None):
+    n = st["x"].size
+    a = {k: _f64(st[k]) for k in ("x", "y", "z", "m", "vx", "vy", "vz", "u")}
+    H, nk, V = _f64(H), _f64(nk), _f64(V)
+    B = np.zeros(6 * n)
+    rho = np.zeros(n)
+    P = np.zeros(n)
+    grad = np.zeros(15 * n)
+    graw = np.zeros(15 * n)
+    alpha = np.zeros(5 * n)
+    cond = np.zeros(n)
+    nill = C.c_int64(0)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    p = s.c()
+    _check(lib().or_gradients(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
+                              _p(a["m"]), _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(a["u"]),
+                              _p(H), _p(nk), _p(V), _p(mk), _p(B), _p(rho), _p(P), _p(grad),
+                              _p(graw), _p(alpha), _p(cond), C.byref(nill)), "gradients")
+    return dict(B=B.reshape(6, n), rho=rho, P=P, grad=grad.reshape(15, n),
+                grad_raw=graw.reshape(15, n), alpha=alpha.reshape(5, n), cond=cond,
+                n_illcond=int(nill.value))
+
+
+def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None):
+    n = st["x"].size
+    a = {k: _f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    H, V = _f64(H), _f64(V)
+    B = _f64(g["B"]).ravel()
+    grad = _f64(g["grad"]).ravel()
+    rho, P = _f64(g["rho"]), _f64(g["P"])
+    dp = np.zeros(3 * n)
+    dE = np.zeros(n)
+    vsig = np.zeros(n)
+    counts = np.zeros(3, dtype=np.int64)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    if hmax is None:
+        hmax = float(np.max(H if mask is None else H[H > 0]))
+    p = s.c()
+    _check(lib().or_fluxes(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
+                           _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
+                           _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
+                           _p(dE), _p(vsig), _p(counts)), "fluxes")
+    return dict(dp=dp.reshape(3, n), dE=dE, vsig=vsig, pair_entries=int(counts[0]),
+                fallbacks=int(counts[1]), clamps=int(counts[2]))
+
+
+def hydro_pass(s: Setup, st: dict, H_guess=None):
+    """Full pass on every particle: kernel lengths, gradients, fluxes."""
+    H, nk, V, it = solve_h(s, st["x"], st["y"], st["z"], H_guess)
+    g = gradients(s, st, H, nk, V)
+    f = fluxes(s, st, H, V, g)
+    out = dict(H=H, nk=nk, V=V, iters=it)
+    out.update(g)
+    out.update(f)
+    out["pairs"] = f["pair_entries"] // 2
+    return out
+
+
+def hllc_star(gamma, left, right):
+    """(S*, P*) of the HLLC solver with Davis speeds for 1D states (rho, u, P)."""
+    Ss, Ps = C.c_double(0), C.c_double(0)
+    lib().or_hllc_star(C.c_double(gamma), C.c_double(left[0]), C.c_double(left[1]),
+                       C.c_double(left[2]), C.c_double(right[0]), C.c_double(right[1]),
+                       C.c_double(right[2]), C.byref(Ss), C.byref(Ps))
+    return Ss.value, Ps.value
+
+
+def face(Ha, Va, Ba6, Hb, Vb, Bb6, d):
+    A = np.zeros(3)
+    Ba6, Bb6, d = _f64(Ba6), _f64(Bb6), _f64(d)
+    lib().or_face(C.c_double(Ha), C.c_double(Va), _p(Ba6), C.c_double(Hb), C.c_double(Vb),
+                  _p(Bb6), _p(d), _p(A))
+    return A
+
+
+# --------------------------------------------------------------------------
+# Sampled evaluation: outputs for a few target particles of a large set.
+# The flux of i needs gradients on its flux set, which need kernel lengths on
+# their gather sets; the closure below walks that dependency outwards.
+# --------------------------------------------------------------------------
+def _ball_mask(s: Setup, st, seeds, radius):
+    x, y, z = st["x"], st["y"], st["z"]
+    mask = np.zeros(x.size, dtype=bool)
+    for i in np.flatnonzero(seeds):
+        mask[find_neighbours(s, x, y, z, int(i), float(radius[i]))] = True
+    return mask
+
+
+def sampled_pass(s: Setup, st: dict, targets, h_bound: float):
+    """Oracle outputs at ``targets`` only.  ``h_bound`` must bound every kernel
+    length that can matter (the closure takes kernel lengths within
+    2 h_bound of each target, gradients within h_bound)."""
+    n = st["x"].size
+    tmask = np.zeros(n, dtype=bool)
+    tmask[np.asarray(targets)] = True
+    gmask = _ball_mask(s, st, tmask, np.full(n, h_bound)) | tmask
+    hmask = _ball_mask(s, st, gmask, np.full(n, h_bound)) | gmask
+    H, nk, V, _ = solve_h(s, st["x"], st["y"], st["z"], None, mask=hmask)
+    g = gradients(s, st, H, nk, V, mask=gmask)
+    f = fluxes(s, st, H, V, g, mask=tmask, hmax=h_bound)
+    out = dict(H=H, nk=nk, V=V)
+    out.update(g)
+    out.update(f)
+    out["targets"] = np.flatnonzero(tmask)
+    return out
+
+
+# --------------------------------------------------------------------------
+# R17/R18: kick-drift-kick step with a predicted state, one pass per step.
+# --------------------------------------------------------------------------
+class Stepper:
+    """Plain FP64 time integration of the MFM gas (global time step)."""
+
+    def __init__(self, w, cell=None, u_floor=None):
+        self.s = Setup.of(w, cell=cell)
+        self.cfl = w.cfl
+        self.st = {k: _f64(getattr(w, k)).copy() for k in ("x", "y", "z", "m", "vx", "vy", "vz", "u")}
+        self.u_floor = 1e-10 * float(np.mean(self.st["u"])) if u_floor is None else u_floor
+        self.H = None
+        self.last = None
+        self.floors = 0
+
+    def _pass(self, x, y, z, vx, vy, vz, u):
+        st = dict(x=x, y=y, z=z, m=self.st["m"], vx=vx, vy=vy, vz=vz, u=u)
+        out = hydro_pass(self.s, st, self.H)
+        self.H = out["H"]
+        return out
+
+    def cfl_dt(self, out):
+        return self.cfl * float(np.min(out["H"] / out["vsig"]))
+
+    def start(self):
+        st = self.st
+        self.last = self._pass(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"])
+        return self.last
+
+    def step(self, dt=None):
+        if self.last is None:
+            self.start()
+        st, s, last = self.st, self.s, self.last
+        if dt is None or dt <= 0:
+            dt = self.cfl_dt(last)
+        m = st["m"]
+        # first half kick of momentum and total energy
+        E = m * (st["u"] + 0.5 * (st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2))
+        v = [st[k] + 0.5 * dt * last["dp"][c] / m for c, k in enumerate(("vx", "vy", "vz"))]
+        E = E + 0.5 * dt * last["dE"]
+        # drift with the half-step velocity, wrapped into the box
+        x = []
+        for c, k in enumerate(("x", "y", "z")):
+            xc = st[k] + dt * v[c]
+            if s.periodic[c]:
+                L = s.box[c]
+                xc = xc - L * np.floor(xc / L)
+                xc[xc >= L] = 0.0
+            x.append(xc)
+        # predicted state for the flux pass
+        vp = [v[c] + 0.5 * dt * last["dp"][c] / m for c in range(3)]
+        Ep = E + 0.5 * dt * last["dE"]
+        up = Ep / m - 0.5 * (vp[0] ** 2 + vp[1] ** 2 + vp[2] ** 2)
+        up = np.maximum(up, self.u_floor)
+        out = self._pass(x[0], x[1], x[2], vp[0], vp[1], vp[2], up)
+        # second half kick and recovery of u
+        v = [v[c] + 0.5 * dt * out["dp"][c] / m for c in range(3)]
+        E = E + 0.5 * dt * out["dE"]
+        u = E / m - 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+        low = u < self.u_floor
+        self.floors += int(np.count_nonzero(low))
+        u = np.where(low, self.u_floor, u)
+        st.update(x=x[0], y=x[1], z=x[2], vx=v[0], vy=v[1], vz=v[2], u=u)
+        self.last = out
+        return dt
