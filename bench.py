@@ -1,0 +1,192 @@
+"""Benchmark of the gfx950 MFM hydro pass: unordered particle-pair interactions per
+second per hydro pass (kernel length + gradients + fluxes on particles already
+in the library's spatial order), FP64 and mixed precision.
+
+    python bench.py [--steps K] [--warmup W] [--workload clustered|turbulence|...]
+
+Prints one JSON line.  Inputs are seeded synthetic particle sets resident in
+HBM before timing starts; each timed step starts the kernel-length solve cold
+(H = 0), so every step redoes the whole pass.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic work and traffic per unit (derivation in the design document)
+FLOPS_PER_PAIR_FLUX = 236          # one unordered pair through faces, reconstruction, HLLC, flux
+BYTES_PER_PARTICLE_FLUX64 = 288    # FP64 flux kernel: record in, dp/dE/vsig out, list counts
+PEAK_FP64_VALU = 78.6e12
+PEAK_FP32_VALU = 157.3e12
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered")
+    ap.add_argument("--tree-levels", type=int, default=0)
+    ap.add_argument("--max-ngb", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def timed_pass(ctx, st, steps, warmup, stream):
+    """Run warmup + steps passes; per stage HIP-event durations (ms) of the timed steps."""
+    import torch
+    stages = ("build", "solve_h", "gradients", "fluxes")
+    acc = {k: [] for k in stages}
+    for it in range(warmup + steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        st.H.zero_()
+        ev[0].record(stream)
+        ctx.build_neighbours(st)
+        ev[1].record(stream)
+        ctx.solve_h(st)
+        ev[2].record(stream)
+        ctx.gradients(st)
+        ev[3].record(stream)
+        ctx.hydro_fluxes(st)
+        ev[4].record(stream)
+        if it >= warmup:
+            torch.cuda.synchronize()
+            for k, s in enumerate(stages):
+                acc[s].append(ev[k].elapsed_time(ev[k + 1]))
+    torch.cuda.synchronize()
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload: the particles of a
+    sub-box (all their dependencies computed), pairs of the sample per second."""
+    from oracle import oracle as O
+    s = O.Setup.of(w)
+    X = np.stack([w.x, w.y, w.z], 1)
+    box = np.array(w.box)
+    order = np.argsort(((X / box) ** 2).sum(1))   # nearest the origin corner first
+
+    def run(k):
+        H, nk, V, _ = O.solve_h(s, w.x, w.y, w.z, None, mask=_mask(order[:k], w.n))
+        t0 = time.perf_counter()
+        out = O.sampled_pass(s, w.arrays(), order[:k], h_bound=_hbound(H))
+        return time.perf_counter() - t0, out
+
+    def _mask(idx, n):
+        m = np.zeros(n, dtype=bool)
+        m[idx] = True
+        return m
+
+    def _hbound(H):
+        h = H[H > 0]
+        return float(h.max()) * 1.5
+
+    t, out = run(2000)
+    k = int(min(w.n, max(2000, 2000 * budget_s / max(t, 1e-3))))
+    t, out = run(k)
+    pairs = out["pair_entries"] / 2.0
+    return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} targets nearest one box corner of the same {w.n}-particle set, with every "
+                      f"particle they depend on; {out['pair_entries']} directed flux entries in {t:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1712_01294_amd import mfm, workloads
+    assert torch.cuda.is_available(), "no GPU"
+    t0 = time.time()
+    w = workloads.by_name(args.workload)
+    log(f"workload {w.name}: n={w.n} generated in {time.time() - t0:.1f}s")
+    kw = {}
+    if args.tree_levels:
+        kw["tree_levels"] = args.tree_levels
+    if args.max_ngb:
+        kw["max_ngb"] = args.max_ngb
+    stream = torch.cuda.current_stream()
+    res = {}
+    states = {}
+    for name, prec in (("fp64", mfm.FP64), ("mixed", mfm.MIXED)):
+        if name == "mixed" and args.no_mixed:
+            continue
+        ctx = mfm.Context(mfm.config_of(w, precision=prec, **kw), w.n)
+        st = mfm.State.from_arrays(w.arrays(), ids=True)
+        ctx.build_neighbours(st)
+        ctx.hydro_pass(st)
+        ctx.check()
+        cnt = ctx.counters()
+        log(f"{name}: pairs={cnt['pairs']} list_max={cnt['list_max']} h_iters_max={cnt['h_iters_max']} "
+            f"fallbacks={cnt['fallbacks']} clamps={cnt['clamps']} illcond={cnt['illcond']}")
+        tm = timed_pass(ctx, st, args.steps, args.warmup, stream)
+        ctx.check()
+        cnt = ctx.counters()
+        pass_ms = tm["solve_h"] + tm["gradients"] + tm["fluxes"]
+        res[name] = dict(stage_ms=tm, pass_ms=pass_ms, pairs=cnt["pairs"], counters=cnt)
+        states[name] = st
+        log(f"{name}: " + " ".join(f"{k}={v:.3f}ms" for k, v in tm.items()))
+        del ctx
+    f64 = res["fp64"]
+    pairs = f64["pairs"]
+    value = pairs / (f64["pass_ms"] * 1e-3)
+    flux_ms = f64["stage_ms"]["fluxes"]
+    achieved = FLOPS_PER_PAIR_FLUX * pairs / (flux_ms * 1e-3)
+    out = {
+        "metric": "particle-pair interactions/s per hydro pass (FP64; mixed alongside)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["pass_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_particles": w.n, "unordered_pairs": pairs,
+                   "n_ngb": w.n_ngb, "gamma": w.gamma, "box": list(w.box)},
+        "stage_ms": f64["stage_ms"],
+        "build_ms": f64["stage_ms"]["build"],
+        "value_incl_build": pairs / ((f64["pass_ms"] + f64["stage_ms"]["build"]) * 1e-3),
+        "roofline": {"kernel": "hydro_fluxes (FP64)", "bound": "alu", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": None, "flops_per_pair": FLOPS_PER_PAIR_FLUX},
+    }
+    if "mixed" in res:
+        mx = res["mixed"]
+        a = {k: getattr(states["fp64"], k).cpu().numpy() for k in ("dp", "dE", "H", "grad", "B")}
+        b = {k: getattr(states["mixed"], k).cpu().numpy() for k in ("dp", "dE", "H", "grad", "B")}
+        same = np.array_equal(states["fp64"].id.cpu().numpy(), states["mixed"].id.cpu().numpy())
+        errs = {k: float(np.abs(a[k] - b[k]).max() / np.abs(a[k]).max()) for k in a} if same else None
+        out["mixed"] = {"value": mx["pairs"] / (mx["pass_ms"] * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
+                        "ms_per_step": mx["pass_ms"], "stage_ms": mx["stage_ms"],
+                        "speedup_vs_fp64": f64["pass_ms"] / mx["pass_ms"],
+                        "normwise_error_vs_fp64": errs}
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * mfm.h -- C ABI of the MI355X (gfx950) meshless finite-mass hydro pass.
+ *
+ * The method is the Lagrangian mesh-free finite-volume Godunov scheme that
+ * Hopkins (2017), "A New Public Release of the GIZMO Code", names in its
+ * abstract and in its "Arbitrary (Moving) Meshes" section: a gas sampled by
+ * particles whose kernel-defined volumes are the cells of a mesh that moves
+ * with the fluid, so mass is carried exactly and only momentum and energy
+ * cross the faces between neighbours.  The paper gives no formulas; the pass
+ * implements the standard finite-mass discretisation it refers to, in the
+ * readings listed with each call below.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All particle arrays are DEVICE memory owned by the caller (allocated,
+ *    e.g., through PyTorch).  The library never frees or reallocates them.
+ *  - Arrays are structure-of-arrays FP64.  Multi-component arrays are
+ *    component-major: component c of particle i sits at [c * n + i].
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*; NULL means the null stream).  Device-side conditions (no
+ *    convergence, ill-conditioned E, neighbour-list overflow, non-finite
+ *    results) are recorded in device counters and surface through
+ *    mfm_check() / mfm_get_counters(), which synchronise the stream.
+ *  - A call returns MFM_OK once its kernels are queued, or an error status
+ *    after validating its arguments on the host, in which case nothing was
+ *    launched.  mfm_last_error() gives a message.
+ *  - The context owns only scratch memory sized at creation for `capacity`
+ *    particles.  A call with n > capacity fails with MFM_E_CAPACITY.
+ *  - Contexts are not thread-safe; calls that overlap on one context race.
+ */
+#ifndef MFM_H
+#define MFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfm_ctx mfm_ctx;
+
+typedef enum {
+    MFM_OK = 0,
+    MFM_E_INVALID = -1,    /* bad argument or parameter                         */
+    MFM_E_HIP = -2,        /* a HIP runtime call failed                         */
+    MFM_E_NOCONV = -3,     /* kernel-length iteration did not converge          */
+    MFM_E_ILLCOND = -4,    /* gradient matrix singular or cond > cond_max       */
+    MFM_E_MINIMAGE = -5,   /* a kernel length reached half a periodic box side  */
+    MFM_E_CAPACITY = -6,   /* n > capacity, or a neighbour list overflowed      */
+    MFM_E_NONFINITE = -7,  /* a NaN/Inf appeared in an output                   */
+    MFM_E_STATE = -8       /* call order violated (e.g. pass before neighbours) */
+} mfm_status;
+
+typedef enum { MFM_FP64 = 0, MFM_MIXED = 1 } mfm_precision;
+
+typedef struct {
+    double gamma;          /* adiabatic index, > 1                                     */
+    double n_ngb;          /* effective neighbour number, > 32/3                       */
+    double cfl;            /* Courant factor of mfm_step when dt <= 0                  */
+    double box[3];         /* box sides; positions must lie in [0, box)               */
+    int32_t periodic[3];   /* 1: periodic (minimum image), 0: open                     */
+    int32_t precision;     /* mfm_precision                                            */
+    double beta;           /* slope-limiter constant (1 = Barth-Jespersen)             */
+    double cond_max;       /* flag E when ||E||_F ||E^-1||_F exceeds this              */
+    double u_floor;        /* floor on specific internal energy in mfm_step            */
+    int32_t h_maxit;       /* cap on kernel-length iterations (<= 0: 64)               */
+    int32_t max_ngb;       /* flux-list slots per particle (<= 0: 256)                 */
+    int32_t tree_levels;   /* cell-table depth (<= 0: from n)                          */
+    int32_t reserved;
+} mfm_params;
+
+/*
+ * One particle set, all device pointers, length n.  Inputs of the pass are
+ * x, y, z, m, vx, vy, vz, u (and H as a guess).  Outputs are written by the
+ * call named in brackets.  Pointers marked "nullable" may be NULL.
+ */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;       /* positions in [0, box)                               */
+    double *m;               /* masses (constant: zero mass flux)                   */
+    double *vx, *vy, *vz;    /* velocities                                          */
+    double *u;               /* specific internal energy                            */
+    double *H;               /* kernel support radius: in guess (<=0: cold), out root [solve_h] */
+    double *nk;              /* kernel number density n_i           [solve_h]       */
+    double *V;               /* volume 1/n_i                        [solve_h]       */
+    double *B;               /* 6 x n: E^-1 as xx, xy, xz, yy, yz, zz  [gradients]  */
+    double *rho, *P;         /* density m n, pressure (gamma-1) rho u  [gradients]  */
+    double *grad;            /* 15 x n: limited gradients of rho, vx, vy, vz, P,
+                                component-major (row 3 f + c)     [gradients]      */
+    double *alpha;           /* nullable, 5 x n: limiter factors    [gradients]      */
+    double *dp;              /* 3 x n: momentum rate dp/dt          [hydro_fluxes]   */
+    double *dE;              /* total-energy rate dE/dt             [hydro_fluxes]   */
+    double *vsig;            /* signal speed                        [hydro_fluxes]   */
+    int64_t *id;             /* nullable: carried along every reordering            */
+} mfm_particles;
+
+typedef struct {
+    int64_t pairs;           /* unordered flux pairs of the last hydro_fluxes       */
+    int64_t list_entries;    /* directed flux-list entries (= 2 pairs)              */
+    int64_t list_max;        /* longest flux list                                   */
+    int64_t h_iters;         /* kernel-length iterations, summed                    */
+    int64_t h_iters_max;     /* longest kernel-length iteration                     */
+    int64_t noconv;          /* particles without a converged kernel length         */
+    int64_t minimage;        /* particles whose radius reached half a periodic side */
+    int64_t overflow;        /* particles whose flux list exceeded max_ngb          */
+    int64_t illcond;         /* particles with det E <= 0 or cond > cond_max        */
+    int64_t fallbacks;       /* directed pair evaluations that fell to first order  */
+    int64_t clamps;          /* directed pair evaluations with P* clamped to 0      */
+    int64_t nonfinite;       /* non-finite outputs                                  */
+    int64_t floors;          /* u floors applied by mfm_step                        */
+    int64_t first_bad;       /* lowest particle index flagged by any of the above   */
+    double cond_max_seen;    /* largest ||E||_F ||B||_F                             */
+} mfm_counters;
+
+/* Create a context for up to `capacity` particles.  Validates params:
+ * gamma > 1, n_ngb > 32/3, box > 0, beta > 0.  Allocates scratch on the
+ * current HIP device.  *out is NULL on failure. */
+mfm_status mfm_create(const mfm_params *params, int64_t capacity, mfm_ctx **out);
+
+/* Free the context's scratch (synchronises its device).  NULL is a no-op. */
+void mfm_destroy(mfm_ctx *ctx);
+
+/* Neighbour structure (reading R2: gather set r < H_i, flux set
+ * r < max(H_i, H_j); the search is the library's own choice).
+ * Quantises positions to a per-axis Morton key, sorts particles by key
+ * (stable LSD radix sort), REORDERS IN PLACE every non-NULL array among
+ * x, y, z, m, vx, vy, vz, u, H, dp, dE, vsig, id into that order, and
+ * builds the per-level cell tables of the implicit octree.  Other output
+ * arrays are left stale and are rewritten by the next pass. */
+mfm_status mfm_build_neighbours(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
+/* Kernel length (readings R1, R3-R5): H_i is the unique root of
+ * (4 pi/3) H^3 n_i(H) = n_ngb, n_i(H) = sum_{r_ij < H} W(r_ij, H) with the
+ * cubic spline of support H; nk = n_i(H_i), V = 1/nk.  FP64 in both
+ * precisions.  H in: a guess (<= 0: from the local cell density).
+ * Requires mfm_build_neighbours on the current positions.  Also builds the
+ * flux lists (r < max(H_i, H_j)) used by the next two calls. */
+mfm_status mfm_solve_h(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
+/* Gradients (readings R5-R8, R10): rho = m nk, P = (gamma-1) rho u;
+ * E_i = sum_j d_ij d_ij^T W(r_ij, H_i) V_i over the gather set;
+ * B = E^-1 (FP64 adjugate); least-squares gradients of rho, v, P limited per
+ * particle by alpha = min(1, beta min((max-phi)/(|g| d), (phi-min)/(|g| d))),
+ * d = half the largest gather distance.  Requires mfm_solve_h. */
+mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
+/* Fluxes (readings R9, R11-R16, R18): per unordered pair in canonical order
+ * (lower index is the left state): face A_ij = (V_i^2 W_i B_i + V_j^2 W_j B_j) d_ij,
+ * midpoint linear reconstruction (first order if not positive), face frame
+ * moving with the mean particle velocity, HLLC star state with Davis speeds,
+ * zero mass flux, momentum P* A, energy P* (S* + w.n)|A|, applied with
+ * opposite signs to both particles.  vsig_i = max_j [c_i + c_j
+ * - min(0, (v_i - v_j).(x_i - x_j)/r)].  Requires mfm_gradients. */
+mfm_status mfm_hydro_fluxes(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
+/* solve_h + gradients + hydro_fluxes on already-ordered particles. */
+mfm_status mfm_hydro_pass(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
+/* One kick-drift-kick step (reading R17) with a predicted state:
+ * half kick of v and total energy with the current dp, dE; drift x with the
+ * half-step velocity (wrapped on periodic axes); rebuild neighbours (which
+ * REORDERS the arrays as mfm_build_neighbours does); one pass on the
+ * predicted velocity and energy; second half kick; u = E/m - |v|^2/2 floored
+ * at u_floor (the predicted u is floored too).  dp, dE, vsig must hold the
+ * pass of the current state (mfm_hydro_pass or a previous mfm_step), and
+ * hold the new state's pass on return.  dt > 0: fixed step; dt <= 0: CFL
+ * step cfl * min_i H_i / vsig_i from the current vsig (reading R18), which
+ * synchronises the stream.  *dt_used (nullable, host) receives the step. */
+mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, void *stream);
+
+/* Synchronise the stream of the last call and report device counters. */
+mfm_status mfm_get_counters(mfm_ctx *ctx, mfm_counters *out);
+
+/* Synchronise and turn device counters into a status: MFM_E_NOCONV,
+ * MFM_E_MINIMAGE, MFM_E_CAPACITY (list overflow), MFM_E_NONFINITE, or
+ * MFM_E_ILLCOND, in that order of precedence; MFM_OK otherwise. */
+mfm_status mfm_check(mfm_ctx *ctx);
+
+/* Copy the flux lists of the last mfm_solve_h into caller device buffers:
+ * counts[i] (int32, n) and list[k * n + i] (int32, max_ngb x n) = index j of
+ * the k-th entry of particle i, in the current particle order. */
+mfm_status mfm_copy_flux_lists(mfm_ctx *ctx, int32_t *counts, int32_t *list, void *stream);
+
+/* Flux-list slot count chosen at creation (max_ngb). */
+int32_t mfm_max_ngb(const mfm_ctx *ctx);
+
+const char *mfm_status_str(mfm_status s);
+const char *mfm_last_error(const mfm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFM_H */

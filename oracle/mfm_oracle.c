@@ -257,6 +257,25 @@ int or_find_neighbours(const or_params *p, int64_t n, const double *x, const dou
     return rc;
 }
 
+/* Exported for the tests: mark[j] = 1 for every j within R of any seed i (mark[i] != 0 on input
+ * selects the seeds; seeds stay marked).  One bucket grid for all seeds. */
+int or_mark_within(const or_params *p, int64_t n, const double *x, const double *y, const double *z,
+                   const uint8_t *seeds, double R, uint8_t *mark)
+{
+    grid_t g;
+    nbr_list L = {0};
+    int rc = grid_build(&g, p, n, x, y, z);
+    for (int64_t i = 0; i < n && !rc; i++) {
+        if (!seeds[i]) continue;
+        mark[i] = 1;
+        rc = grid_find(&g, i, R, &L);
+        for (int64_t k = 0; k < L.n && !rc; k++) mark[L.a[k].j] = 1;
+    }
+    free(L.a);
+    grid_free(&g);
+    return rc;
+}
+
 /* ------------------------------------------------------------------ */
 /* R3/R4: kernel length.  f(H) = (4 pi/3) H^3 n(H) - N_ngb, n(H) the   */
 /* kernel-weighted number density at H; f is non-decreasing in H, so   */

@@ -57,6 +57,7 @@ def lib():
         L.or_kernel_dWdH.restype = C.c_double
         L.or_kernel_dWdH.argtypes = [C.c_double, C.c_double]
         L.or_find_neighbours.restype = C.c_int
+        L.or_mark_within.restype = C.c_int
         L.or_solve_h.restype = C.c_int
         L.or_gradients.restype = C.c_int
         L.or_fluxes.restype = C.c_int
@@ -232,12 +233,14 @@ def face(Ha, Va, Ba6, Hb, Vb, Bb6, d):
 # The flux of i needs gradients on its flux set, which need kernel lengths on
 # their gather sets; the closure below walks that dependency outwards.
 # --------------------------------------------------------------------------
-def _ball_mask(s: Setup, st, seeds, radius):
-    x, y, z = st["x"], st["y"], st["z"]
-    mask = np.zeros(x.size, dtype=bool)
-    for i in np.flatnonzero(seeds):
-        mask[find_neighbours(s, x, y, z, int(i), float(radius[i]))] = True
-    return mask
+def _ball_mask(s: Setup, st, seeds, radius: float):
+    x, y, z = (_f64(st[k]) for k in ("x", "y", "z"))
+    sd = np.ascontiguousarray(seeds, dtype=np.uint8)
+    mark = np.zeros(x.size, dtype=np.uint8)
+    p = s.c()
+    _check(lib().or_mark_within(C.byref(p), C.c_int64(x.size), _p(x), _p(y), _p(z), _p(sd),
+                                C.c_double(radius), _p(mark)), "mark_within")
+    return mark.astype(bool)
 
 
 def sampled_pass(s: Setup, st: dict, targets, h_bound: float):
@@ -247,8 +250,8 @@ def sampled_pass(s: Setup, st: dict, targets, h_bound: float):
     n = st["x"].size
     tmask = np.zeros(n, dtype=bool)
     tmask[np.asarray(targets)] = True
-    gmask = _ball_mask(s, st, tmask, np.full(n, h_bound)) | tmask
-    hmask = _ball_mask(s, st, gmask, np.full(n, h_bound)) | gmask
+    gmask = _ball_mask(s, st, tmask, h_bound) | tmask
+    hmask = _ball_mask(s, st, gmask, h_bound) | gmask
     H, nk, V, _ = solve_h(s, st["x"], st["y"], st["z"], None, mask=hmask)
     g = gradients(s, st, H, nk, V, mask=gmask)
     f = fluxes(s, st, H, V, g, mask=tmask, hmax=h_bound)

@@ -1,0 +1,470 @@
+// C ABI of the gfx950 MFM hydro pass (declared in include/mfm.h).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/mfm.h"
+#include "device.h"
+#include "kernels.h"
+
+using namespace mfm;
+
+struct mfm_ctx {
+    mfm_params p;
+    int64_t cap = 0;
+    int device = 0;
+    TreeDesc td;
+    Phys ph;
+    long long tab_len = 0, hmax_len = 0;
+    unsigned long long *keys = nullptr, *ktmp = nullptr;
+    int *idx = nullptr, *vtmp = nullptr, *hist = nullptr, *scan_tmp = nullptr;
+    unsigned long long* gtmp = nullptr;   // kGatherMax x cap staging for in-place reordering
+    int2* tab = nullptr;
+    float* hmax = nullptr;
+    int *counts = nullptr, *list = nullptr;
+    void* rec = nullptr;                  // 32 x 8 B per particle
+    double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
+    double *dt_part = nullptr, *dt_out = nullptr;
+    Counters* cnt = nullptr;
+    int64_t n_tree = -1;
+    int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
+    hipStream_t last = nullptr;
+    std::string err;
+};
+
+static mfm_status fail(mfm_ctx* c, mfm_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+static mfm_status hip_check(mfm_ctx* c, hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(c, MFM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MFM_OK;
+}
+
+static mfm_status launched(mfm_ctx* c, const char* what) {
+    return hip_check(c, hipGetLastError(), what);
+}
+
+static int ceil_log2(double v) {
+    int b = 0;
+    while ((double)(1ll << b) < v) b++;
+    return b;
+}
+
+// Per-axis Morton layout: the longest axis gets bmax bits, shorter axes start
+// refining once the cells along the longest axis are no longer than them.
+static void setup_tree(mfm_ctx* c) {
+    TreeDesc& td = c->td;
+    memset(&td, 0, sizeof(td));
+    int bmax = c->p.tree_levels;
+    if (bmax <= 0) bmax = ceil_log2(cbrt((double)c->cap)) + 1;
+    if (bmax < 2) bmax = 2;
+    if (bmax > kMaxLevels - 1) bmax = kMaxLevels - 1;
+    double Lmax = fmax(c->p.box[0], fmax(c->p.box[1], c->p.box[2]));
+    for (int d = 0; d < 3; d++) {
+        int drop = (int)lround(log2(Lmax / c->p.box[d]));
+        int q = bmax - (drop > 0 ? drop : 0);
+        td.qbits[d] = q > 0 ? q : 0;
+        td.box[d] = c->p.box[d];
+        td.periodic[d] = c->p.periodic[d];
+    }
+    td.bmax = bmax;
+    td.leaf = 8;
+    long long off = 0, hoff = 0;
+    int k = 0;
+    for (int l = 0; l <= bmax; l++) {
+        int m = 0, nb = 0;
+        for (int d = 0; d < 3; d++)
+            if (l >= 1 && l > bmax - td.qbits[d]) {
+                m |= 1 << d;
+                nb++;
+            }
+        k += nb;
+        td.actmask[l] = m;
+        td.nact[l] = nb;
+        td.kbits[l] = k;
+        td.tab_off[l] = off;
+        td.hmax_off[l] = hoff;
+        off += 1ll << k;
+        hoff += 1ll << k;
+        for (int d = 0; d < 3; d++) {
+            int act = l - (bmax - td.qbits[d]);
+            if (act < 0) act = 0;
+            td.cs[l][d] = c->p.box[d] / (double)(1ll << act);
+        }
+    }
+    td.ktot = k;
+    c->tab_len = off;
+    c->hmax_len = hoff;
+}
+
+extern "C" {
+
+const char* mfm_status_str(mfm_status s) {
+    switch (s) {
+        case MFM_OK: return "ok";
+        case MFM_E_INVALID: return "invalid argument";
+        case MFM_E_HIP: return "HIP runtime error";
+        case MFM_E_NOCONV: return "kernel length did not converge";
+        case MFM_E_ILLCOND: return "ill-conditioned gradient matrix";
+        case MFM_E_MINIMAGE: return "kernel length reached half a periodic box side";
+        case MFM_E_CAPACITY: return "capacity exceeded";
+        case MFM_E_NONFINITE: return "non-finite result";
+        case MFM_E_STATE: return "call order violated";
+    }
+    return "unknown status";
+}
+
+const char* mfm_last_error(const mfm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int32_t mfm_max_ngb(const mfm_ctx* c) { return c ? c->ph.max_ngb : 0; }
+
+void mfm_destroy(mfm_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->hmax,
+                    c->counts, c->list, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    delete c;
+}
+
+mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out) {
+    if (!out) return MFM_E_INVALID;
+    *out = nullptr;
+    if (!params) return MFM_E_INVALID;
+    const mfm_params& p = *params;
+    if (!(p.gamma > 1.0) || !(p.n_ngb > 32.0 / 3.0) || !(p.beta > 0.0) || !(p.cond_max > 0.0)) return MFM_E_INVALID;
+    for (int d = 0; d < 3; d++)
+        if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return MFM_E_INVALID;
+    if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return MFM_E_INVALID;
+    if (capacity < 1 || capacity > (1ll << 30)) return MFM_E_INVALID;
+    mfm_ctx* c = new mfm_ctx();
+    c->p = p;
+    c->cap = capacity;
+    hipGetDevice(&c->device);
+    c->ph.gamma = p.gamma;
+    c->ph.n_ngb = p.n_ngb;
+    c->ph.beta = p.beta;
+    c->ph.cond_max = p.cond_max;
+    for (int d = 0; d < 3; d++) {
+        c->ph.box[d] = p.box[d];
+        c->ph.periodic[d] = p.periodic[d];
+    }
+    c->ph.h_maxit = p.h_maxit > 0 ? p.h_maxit : 64;
+    c->ph.max_ngb = p.max_ngb > 0 ? p.max_ngb : 256;
+    setup_tree(c);
+    const long long n = capacity;
+    const int nblocks = (int)((n + 2047) / 2048);
+    const long long hist_len = 256ll * nblocks;
+    mfm_status st = MFM_OK;
+    auto alloc = [&](void** ptr, size_t bytes, const char* what) {
+        if (st != MFM_OK) return;
+        st = hip_check(c, hipMalloc(ptr, bytes < 16 ? 16 : bytes), what);
+    };
+    alloc((void**)&c->keys, sizeof(unsigned long long) * n, "keys");
+    alloc((void**)&c->ktmp, sizeof(unsigned long long) * n, "keys tmp");
+    alloc((void**)&c->idx, sizeof(int) * n, "idx");
+    alloc((void**)&c->vtmp, sizeof(int) * n, "idx tmp");
+    alloc((void**)&c->hist, sizeof(int) * hist_len, "hist");
+    alloc((void**)&c->scan_tmp, sizeof(int) * scan_tmp_ints(hist_len > n ? hist_len : n), "scan tmp");
+    alloc((void**)&c->gtmp, sizeof(unsigned long long) * n * kGatherMax, "gather staging");
+    alloc((void**)&c->tab, sizeof(int2) * c->tab_len, "cell tables");
+    alloc((void**)&c->hmax, sizeof(float) * c->hmax_len, "cell hmax");
+    alloc((void**)&c->counts, sizeof(int) * n, "list counts");
+    alloc((void**)&c->list, sizeof(int) * n * c->ph.max_ngb, "flux lists");
+    alloc((void**)&c->rec, sizeof(double) * 32 * n, "records");
+    alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
+    alloc((void**)&c->up, sizeof(double) * n, "predicted u");
+    alloc((void**)&c->Ehalf, sizeof(double) * n, "half-step energy");
+    alloc((void**)&c->dt_part, sizeof(double) * 1024, "dt partials");
+    alloc((void**)&c->dt_out, sizeof(double) * 2, "dt");
+    alloc((void**)&c->cnt, sizeof(Counters), "counters");
+    if (st != MFM_OK) {
+        fprintf(stderr, "mfm_create: %s\n", c->err.c_str());
+        mfm_destroy(c);
+        return st;
+    }
+    *out = c;
+    return MFM_OK;
+}
+
+static void reset_counters(mfm_ctx* c, hipStream_t s) {
+    const int words = sizeof(Counters) / 8;
+    launch_fill_u64(words, (unsigned long long*)c->cnt, 0ull, s);
+    // first_bad starts at "none"
+    launch_fill_u64(1, &c->cnt->first_bad, ~0ull, s);
+}
+
+static mfm_status check_particles(mfm_ctx* c, const mfm_particles* p) {
+    if (!c) return MFM_E_INVALID;
+    if (!p) return fail(c, MFM_E_INVALID, "null particle struct");
+    if (p->n < 1) return fail(c, MFM_E_INVALID, "n must be >= 1");
+    if (p->n > c->cap) return fail(c, MFM_E_CAPACITY, "n exceeds the context capacity");
+    if (!p->x || !p->y || !p->z || !p->m || !p->vx || !p->vy || !p->vz || !p->u || !p->H)
+        return fail(c, MFM_E_INVALID, "x, y, z, m, vx, vy, vz, u and H are required");
+    return MFM_OK;
+}
+
+static PassArrays arrays_of(const mfm_particles* p) {
+    PassArrays a;
+    a.n = (int)p->n;
+    a.x = p->x;
+    a.y = p->y;
+    a.z = p->z;
+    a.m = p->m;
+    a.vx = p->vx;
+    a.vy = p->vy;
+    a.vz = p->vz;
+    a.u = p->u;
+    a.H = p->H;
+    a.nk = p->nk;
+    a.V = p->V;
+    a.B = p->B;
+    a.rho = p->rho;
+    a.P = p->P;
+    a.grad = p->grad;
+    a.alpha = p->alpha;
+    a.dp = p->dp;
+    a.dE = p->dE;
+    a.vsig = p->vsig;
+    return a;
+}
+
+// order by key and reorder `extra` arrays too (step scratch)
+static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* const* extra, int nextra) {
+    const int n = (int)p->n;
+    hipSetDevice(c->device);
+    launch_keys(n, p->x, p->y, p->z, c->td, c->keys, c->idx, s);
+    radix_sort(n, c->td.ktot, c->keys, c->idx, c->ktmp, c->vtmp, c->hist, c->scan_tmp, s);
+    GatherBatch gb;
+    gb.count = 0;
+    auto add = [&](void* ptr) {
+        if (!ptr) return;
+        unsigned long long* stage = c->gtmp + (long long)gb.count * n;
+        hipMemcpyAsync(stage, ptr, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        gb.src[gb.count] = stage;
+        gb.dst[gb.count] = (unsigned long long*)ptr;
+        gb.count++;
+    };
+    add(p->x);
+    add(p->y);
+    add(p->z);
+    add(p->m);
+    add(p->vx);
+    add(p->vy);
+    add(p->vz);
+    add(p->u);
+    add(p->H);
+    if (p->dp) {
+        add(p->dp);
+        add(p->dp + n);
+        add(p->dp + 2 * (long long)n);
+    }
+    add(p->dE);
+    add(p->vsig);
+    add(p->id);
+    for (int k = 0; k < nextra; k++) add(extra[k]);
+    launch_gather(n, gb, c->idx, s);
+    launch_fill_u64(c->tab_len, (unsigned long long*)c->tab, 0ull, s);
+    launch_tables(n, c->keys, c->td, c->tab, s);
+    c->n_tree = n;
+    c->have_h = c->have_grad = 0;
+    c->last = s;
+    return launched(c, "build_neighbours");
+}
+
+mfm_status mfm_build_neighbours(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    return build(c, p, (hipStream_t)stream, nullptr, 0);
+}
+
+static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
+    if (!p->nk || !p->V) return fail(c, MFM_E_INVALID, "nk and V are required");
+    if (c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_build_neighbours must run on these particles first");
+    PassArrays a = arrays_of(p);
+    launch_solve_h(a, c->td, c->tab, c->keys, c->ph, c->cnt, s);
+    launch_hmax(a.n, c->keys, c->td, c->tab, p->H, c->hmax, s);
+    launch_flux_lists(a, c->td, c->tab, c->hmax, c->ph, c->counts, c->list, c->cnt, s);
+    c->have_h = 1;
+    c->have_grad = 0;
+    c->last = s;
+    return launched(c, "solve_h");
+}
+
+static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
+    if (!p->B || !p->rho || !p->P || !p->grad || !p->nk || !p->V)
+        return fail(c, MFM_E_INVALID, "B, rho, P, grad, nk and V are required");
+    if (!c->have_h || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_solve_h must run first");
+    PassArrays a = arrays_of(p);
+    c->rec_mixed = c->p.precision == MFM_MIXED;
+    launch_gradients(a, c->ph, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    c->have_grad = 1;
+    c->last = s;
+    return launched(c, "gradients");
+}
+
+static mfm_status do_fluxes(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
+    if (!p->dp || !p->dE || !p->vsig) return fail(c, MFM_E_INVALID, "dp, dE and vsig are required");
+    if (!c->have_grad || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_gradients must run first");
+    PassArrays a = arrays_of(p);
+    launch_fluxes(a, c->ph, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    c->have_flux = 1;
+    c->last = s;
+    return launched(c, "hydro_fluxes");
+}
+
+mfm_status mfm_solve_h(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    hipSetDevice(c->device);
+    reset_counters(c, (hipStream_t)stream);
+    return do_solve_h(c, p, (hipStream_t)stream);
+}
+
+mfm_status mfm_gradients(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    hipSetDevice(c->device);
+    return do_gradients(c, p, (hipStream_t)stream);
+}
+
+mfm_status mfm_hydro_fluxes(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    hipSetDevice(c->device);
+    return do_fluxes(c, p, (hipStream_t)stream);
+}
+
+mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    reset_counters(c, s);
+    if ((st = do_solve_h(c, p, s))) return st;
+    if ((st = do_gradients(c, p, s))) return st;
+    return do_fluxes(c, p, s);
+}
+
+mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
+        return fail(c, MFM_E_INVALID, "mfm_step needs every pass output array");
+    if (!c->have_flux || c->n_tree != p->n)
+        return fail(c, MFM_E_STATE, "mfm_step needs a pass on the current state (mfm_hydro_pass)");
+    hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)p->n;
+    if (!(dt > 0.0)) {
+        const int parts = dt_min_parts(n);
+        launch_dt_min(n, p->H, p->vsig, c->dt_part, parts, c->dt_out, s);
+        double h = 0.0;
+        if ((st = hip_check(c, hipMemcpyAsync(&h, c->dt_out, sizeof(double), hipMemcpyDeviceToHost, s), "dt copy")))
+            return st;
+        if ((st = hip_check(c, hipStreamSynchronize(s), "dt sync"))) return st;
+        dt = c->p.cfl * h;
+        if (!(dt > 0.0) || !isfinite(dt)) return fail(c, MFM_E_NONFINITE, "Courant step is not positive and finite");
+    }
+    if (dt_used) *dt_used = dt;
+    reset_counters(c, s);
+    PassArrays a = arrays_of(p);
+    launch_kick_drift(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, s);
+    double* extra[5] = {c->vp, c->vp + n, c->vp + 2 * (long long)n, c->up, c->Ehalf};
+    if ((st = build(c, p, s, extra, 5))) return st;
+    // pass on the predicted state
+    mfm_particles q = *p;
+    q.vx = c->vp;
+    q.vy = c->vp + n;
+    q.vz = c->vp + 2 * (long long)n;
+    q.u = c->up;
+    if ((st = do_solve_h(c, &q, s))) return st;
+    if ((st = do_gradients(c, &q, s))) return st;
+    if ((st = do_fluxes(c, &q, s))) return st;
+    a = arrays_of(p);
+    launch_kick2(a, dt, c->p.u_floor, c->Ehalf, p->u, c->cnt, s);
+    c->last = s;
+    return launched(c, "step");
+}
+
+mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
+    if (!c || !out) return MFM_E_INVALID;
+    hipSetDevice(c->device);
+    mfm_status st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->last), "sync"))) return st;
+    Counters h;
+    if ((st = hip_check(c, hipMemcpy(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost), "counter copy"))) return st;
+    out->list_entries = (int64_t)h.list_entries;
+    out->pairs = (int64_t)(h.list_entries / 2);
+    out->list_max = (int64_t)h.list_max;
+    out->h_iters = (int64_t)h.h_iters;
+    out->h_iters_max = (int64_t)h.h_iters_max;
+    out->noconv = (int64_t)h.noconv;
+    out->minimage = (int64_t)h.minimage;
+    out->overflow = (int64_t)h.overflow;
+    out->illcond = (int64_t)h.illcond;
+    out->fallbacks = (int64_t)h.fallbacks;
+    out->clamps = (int64_t)h.clamps;
+    out->nonfinite = (int64_t)h.nonfinite;
+    out->floors = (int64_t)h.floors;
+    out->first_bad = h.first_bad == ~0ull ? -1 : (int64_t)h.first_bad;
+    double cm;
+    memcpy(&cm, &h.cond_bits, sizeof(cm));
+    out->cond_max_seen = cm;
+    return MFM_OK;
+}
+
+mfm_status mfm_check(mfm_ctx* c) {
+    mfm_counters k;
+    mfm_status st = mfm_get_counters(c, &k);
+    if (st) return st;
+    char buf[160];
+    if (k.noconv) {
+        snprintf(buf, sizeof buf, "%lld particles without a converged kernel length (first %lld)",
+                 (long long)k.noconv, (long long)k.first_bad);
+        return fail(c, MFM_E_NOCONV, buf);
+    }
+    if (k.minimage) {
+        snprintf(buf, sizeof buf, "%lld kernel lengths reached half a periodic side (first %lld)",
+                 (long long)k.minimage, (long long)k.first_bad);
+        return fail(c, MFM_E_MINIMAGE, buf);
+    }
+    if (k.overflow) {
+        snprintf(buf, sizeof buf, "%lld flux lists exceeded max_ngb=%d (longest %lld)", (long long)k.overflow,
+                 c->ph.max_ngb, (long long)k.list_max);
+        return fail(c, MFM_E_CAPACITY, buf);
+    }
+    if (k.nonfinite) {
+        snprintf(buf, sizeof buf, "%lld non-finite outputs (first %lld)", (long long)k.nonfinite,
+                 (long long)k.first_bad);
+        return fail(c, MFM_E_NONFINITE, buf);
+    }
+    if (k.illcond) {
+        snprintf(buf, sizeof buf, "%lld ill-conditioned gradient matrices (first %lld)", (long long)k.illcond,
+                 (long long)k.first_bad);
+        return fail(c, MFM_E_ILLCOND, buf);
+    }
+    return MFM_OK;
+}
+
+mfm_status mfm_copy_flux_lists(mfm_ctx* c, int32_t* counts, int32_t* list, void* stream) {
+    if (!c || !counts || !list) return MFM_E_INVALID;
+    if (!c->have_h) return fail(c, MFM_E_STATE, "no flux lists yet");
+    hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = c->n_tree;
+    mfm_status st;
+    if ((st = hip_check(c, hipMemcpyAsync(counts, c->counts, sizeof(int) * n, hipMemcpyDeviceToDevice, s),
+                        "copy counts")))
+        return st;
+    return hip_check(c, hipMemcpyAsync(list, c->list, sizeof(int) * n * c->ph.max_ngb, hipMemcpyDeviceToDevice, s),
+                     "copy lists");
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Host-side launchers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mfm {
+
+constexpr int kGatherMax = 20;
+
+// up to kGatherMax arrays of 8-byte elements reordered by one launch: dst[i] = src[idx[i]]
+struct GatherBatch {
+    int count;
+    const unsigned long long* src[kGatherMax];
+    unsigned long long* dst[kGatherMax];
+};
+
+// particle arrays seen by the pass kernels (sorted order)
+struct PassArrays {
+    int n;
+    const double *x, *y, *z, *m, *vx, *vy, *vz, *u;
+    double *H, *nk, *V;
+    double *B, *rho, *P, *grad, *alpha;
+    double *dp, *dE, *vsig;
+};
+
+// tree.hip
+long long scan_tmp_ints(long long m);
+void exclusive_scan(int m, const int* in, int* out, int* tmp, hipStream_t s);
+void radix_sort(int n, int bits, unsigned long long* keys, int* vals, unsigned long long* ktmp,
+                int* vtmp, int* hist, int* scan_tmp, hipStream_t s);
+void launch_keys(int n, const double* x, const double* y, const double* z, const TreeDesc& td,
+                 unsigned long long* keys, int* idx, hipStream_t s);
+void launch_gather(int n, const GatherBatch& gb, const int* idx, hipStream_t s);
+void launch_fill_u64(long long m, unsigned long long* p, unsigned long long v, hipStream_t s);
+void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s);
+void launch_hmax(int n, const unsigned long long* keys, const TreeDesc& td, const int2* tab,
+                 const double* H, float* hmax, hipStream_t s);
+
+// pass.hip
+void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
+                    const unsigned long long* keys, const Phys& ph, Counters* cnt, hipStream_t s);
+void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
+                       const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s);
+void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
+                      int mixed, void* rec, Counters* cnt, hipStream_t s);
+void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
+                   int mixed, const void* rec, Counters* cnt, hipStream_t s);
+
+// step.hip
+void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor,
+                       double* vp, double* up, double* Ehalf, hipStream_t s);
+void launch_kick2(const PassArrays& a, double dt, double u_floor, const double* Ehalf,
+                  double* u, Counters* cnt, hipStream_t s);
+void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts,
+                   double* out, hipStream_t s);
+int dt_min_parts(int n);
+
+}  // namespace mfm

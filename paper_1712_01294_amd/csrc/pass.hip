@@ -1,0 +1,647 @@
+// The gfx950 MFM hydro pass: kernel length, flux lists, gradients, fluxes.
+//
+// One thread per (Morton-ordered) particle; blocks are remapped so that each
+// XCD works on one contiguous run of particles and keeps its neighbours in
+// its own L2.  The flux kernel evaluates every unordered pair on both of its
+// particles with the lower index as the left state, so both copies are
+// bitwise equal and the accumulated momentum and energy cancel exactly pair
+// by pair; there are no atomics on outputs and results are deterministic.
+#include <math.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace mfm {
+
+// blockIdx -> logical block so that XCD x (blocks x, x+8, ...) gets one contiguous range
+__device__ __forceinline__ int xcd_block() {
+    int G = gridDim.x, b = blockIdx.x;
+    int x = b & 7, slot = b >> 3;
+    int q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void count_add(unsigned long long* c, unsigned long long v) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(c, v);
+}
+
+__device__ __forceinline__ void count_max(unsigned long long* c, unsigned long long v) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(c, v);
+}
+
+__device__ __forceinline__ void flag_index(Counters* cnt, int i) {
+    atomicMin(&cnt->first_bad, (unsigned long long)i);
+}
+
+__device__ __forceinline__ void displacement(const Phys& ph, const double xi[3], double xj0, double xj1,
+                                             double xj2, double d[3]) {
+    d[0] = min_image(xj0 - xi[0], ph.box[0], ph.periodic[0]);
+    d[1] = min_image(xj1 - xi[1], ph.box[1], ph.periodic[1]);
+    d[2] = min_image(xj2 - xi[2], ph.box[2], ph.periodic[2]);
+}
+
+// ------------------------------------------------------------ kernel length
+constexpr int kHCap = 64;   // LDS slots per particle for the radii inside the bracket
+
+__device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, unsigned long long key,
+                             double n_ngb) {
+    if (key >> td.ktot) key = 0;
+    for (int l = td.bmax; l >= 0; l--) {
+        unsigned long long c = key >> (td.ktot - td.kbits[l]);
+        int2 se = tab[td.tab_off[l] + (long long)c];
+        double cntp = (double)(se.y - se.x);
+        if (cntp >= n_ngb || l == 0) {
+            double vol = td.cs[l][0] * td.cs[l][1] * td.cs[l][2];
+            return cbrt(3.0 * n_ngb * vol / (4.0 * M_PI * cntp));
+        }
+    }
+    return 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                 const unsigned long long* __restrict__ keys, Phys ph,
+                                                 Counters* cnt) {
+    __shared__ double lst[kHCap * 64];
+    const int lane = threadIdx.x;
+    const int i = xcd_block() * 64 + lane;
+    const bool act = i < a.n;
+    unsigned long long iters = 0, noconv = 0, noimg = 0;
+    if (act) {
+        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
+        double half = INFINITY;
+        for (int d = 0; d < 3; d++)
+            if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+        double guess = a.H[i];
+        const bool warm = guess > 0.0;
+        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
+        double lo = 0.0, hi = INFINITY;
+        double R = (warm ? 1.2 : 1.6) * guess;
+        int m = 0;
+        double neff_hi = 0.0;
+        bool ok = false;
+        const double c32 = 32.0 / 3.0;
+        for (int att = 0; att < 80; att++) {
+            iters++;
+            if (!(R < half)) {
+                R = half * (1.0 - 1e-12);
+                if (!(R > lo)) break;   // the root lies beyond half a periodic side
+            }
+            const double R2 = R * R;
+            const double iR = 1.0 / R;
+            m = 0;
+            double sw = 0.0;
+            tree_walk(
+                td, tab,
+                [&](int, unsigned long long, const double* nlo, const double* nhi) {
+                    return node_dist2(td, xi, nlo, nhi) < R2;
+                },
+                [&](int s, int e) {
+                    for (int j = s; j < e; j++) {
+                        double d[3];
+                        displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
+                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        if (r2 < R2) {
+                            double r = sqrt(r2);
+                            if (r < R) {
+                                if (m < kHCap) lst[m * 64 + lane] = r;
+                                m++;
+                                sw += spline_w(r * iR);
+                            }
+                        }
+                    }
+                });
+            double f = c32 * sw - ph.n_ngb;
+            if (f < 0.0) {
+                lo = R;
+                R = (hi < INFINITY) ? 0.5 * (lo + hi) : 1.5 * R;
+                continue;
+            }
+            hi = R;
+            if (m > kHCap) {
+                R = 0.5 * (lo + hi);
+                continue;
+            }
+            neff_hi = c32 * sw;
+            ok = true;
+            break;
+        }
+        double Hc = 0.0;
+        bool conv = false;
+        if (ok) {
+            // Newton on the stored radii, safeguarded by the bracket (lo, hi]
+            Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
+            if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
+            for (int it = 0; it < ph.h_maxit; it++) {
+                iters++;
+                const double iH = 1.0 / Hc;
+                double s = 0.0, sq = 0.0;
+                for (int k = 0; k < m; k++) {
+                    double q = lst[k * 64 + lane] * iH;
+                    s += spline_w(q);
+                    sq += spline_qdw(q);
+                }
+                double f = c32 * s - ph.n_ngb;
+                if (f == 0.0) {
+                    conv = true;
+                    break;
+                }
+                if (f < 0.0) lo = Hc;
+                else hi = Hc;
+                double fp = -c32 * sq * iH;
+                double Hn = Hc - f / fp;
+                if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
+                double dH = fabs(Hn - Hc);
+                Hc = Hn;
+                if (dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi)) {
+                    conv = true;
+                    break;
+                }
+            }
+        }
+        if (!ok) {
+            noimg = 1;
+            Hc = lo;
+        } else if (!conv) {
+            noconv = 1;
+        }
+        if (!ok || !conv) flag_index(cnt, i);
+        double s = 0.0;
+        const double iH = 1.0 / Hc;
+        for (int k = 0; k < (m < kHCap ? m : kHCap); k++) s += spline_w(lst[k * 64 + lane] * iH);
+        double nk = kernel_norm(Hc) * s;
+        a.H[i] = Hc;
+        a.nk[i] = nk;
+        a.V[i] = 1.0 / nk;
+    }
+    count_add(&cnt->h_iters, iters);
+    count_max(&cnt->h_iters_max, iters);
+    count_add(&cnt->noconv, noconv);
+    count_add(&cnt->minimage, noimg);
+}
+
+// --------------------------------------------------------------- flux lists
+// list[k * n + i] = k-th j (walk order) with j != i and r_ij < max(H_i, H_j)
+__global__ __launch_bounds__(256) void k_flux_lists(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                     const float* __restrict__ hmax, Phys ph,
+                                                     int* __restrict__ counts, int* __restrict__ list,
+                                                     Counters* cnt) {
+    const int i = xcd_block() * 256 + threadIdx.x;
+    const bool act = i < a.n;
+    unsigned long long c = 0, over = 0;
+    if (act) {
+        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
+        const double Hi = a.H[i];
+        const long long n = a.n;
+        const int cap = ph.max_ngb;
+        tree_walk(
+            td, tab,
+            [&](int l, unsigned long long cc, const double* nlo, const double* nhi) {
+                double h = fmax(Hi, (double)hmax[td.hmax_off[l] + (long long)cc]);
+                return node_dist2(td, xi, nlo, nhi) < h * h;
+            },
+            [&](int s, int e) {
+                for (int j = s; j < e; j++) {
+                    if (j == i) continue;
+                    double d[3];
+                    displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
+                    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    if (r < Hi || r < a.H[j]) {
+                        if (c < (unsigned long long)cap) list[(long long)c * n + i] = j;
+                        c++;
+                    }
+                }
+            });
+        if (c > (unsigned long long)cap) {
+            over = 1;
+            flag_index(cnt, i);
+        }
+        counts[i] = (int)(c < (unsigned long long)cap ? c : cap);
+    }
+    count_add(&cnt->list_entries, c);
+    count_max(&cnt->list_max, c);
+    count_add(&cnt->overflow, over);
+}
+
+// ---------------------------------------------------------------- gradients
+// Record of one particle for the flux kernel (32 slots, one or two cache lines):
+// 0-2 x, y, z (FP64 record only) | 3 H | 4 V | 5 rho | 6 P | 7-9 v | 10-15 B | 16-30 grad | 31 c
+enum { R_X = 0, R_H = 3, R_V = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                    const int* __restrict__ list, void* __restrict__ recp,
+                                                    Counters* cnt) {
+    const int i = xcd_block() * 256 + threadIdx.x;
+    const bool act = i < a.n;
+    unsigned long long ill = 0, nonfin = 0, condbits = 0;
+    if (act) {
+        const long long n = a.n;
+        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
+        const double Hi = a.H[i], Vi = a.V[i];
+        const double rho_i = a.m[i] * a.nk[i];
+        const double P_i = (ph.gamma - 1.0) * rho_i * a.u[i];
+        const double phi_i[5] = {rho_i, a.vx[i], a.vy[i], a.vz[i], P_i};
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        double S[15];
+        double pmax[5], pmin[5];
+#pragma unroll
+        for (int k = 0; k < 15; k++) S[k] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 5; f++) pmax[f] = pmin[f] = phi_i[f];
+        double rmax = 0.0;
+        const double norm = kernel_norm(Hi), iH = 1.0 / Hi;
+        const float normf = (float)norm, iHf = (float)iH, Vif = (float)Vi;
+        const int cnum = counts[i];
+        for (int k = 0; k < cnum; k++) {
+            const int j = list[(long long)k * n + i];
+            double d[3];
+            displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < Hi)) continue;   // flux-only neighbour: outside the gather set
+            const double rho_j = a.m[j] * a.nk[j];
+            const double phi_j[5] = {rho_j, a.vx[j], a.vy[j], a.vz[j], (ph.gamma - 1.0) * rho_j * a.u[j]};
+            if (!MIXED) {
+                const double psi = norm * spline_w(r * iH) * Vi;
+                E[0] += d[0] * d[0] * psi;
+                E[1] += d[0] * d[1] * psi;
+                E[2] += d[0] * d[2] * psi;
+                E[3] += d[1] * d[1] * psi;
+                E[4] += d[1] * d[2] * psi;
+                E[5] += d[2] * d[2] * psi;
+#pragma unroll
+                for (int f = 0; f < 5; f++) {
+                    const double df = (phi_j[f] - phi_i[f]) * psi;
+                    S[3 * f + 0] += df * d[0];
+                    S[3 * f + 1] += df * d[1];
+                    S[3 * f + 2] += df * d[2];
+                }
+            } else {
+                const float df3[3] = {(float)d[0], (float)d[1], (float)d[2]};
+                const float psi = normf * spline_w((float)r * iHf) * Vif;
+                E[0] += (double)(df3[0] * df3[0] * psi);
+                E[1] += (double)(df3[0] * df3[1] * psi);
+                E[2] += (double)(df3[0] * df3[2] * psi);
+                E[3] += (double)(df3[1] * df3[1] * psi);
+                E[4] += (double)(df3[1] * df3[2] * psi);
+                E[5] += (double)(df3[2] * df3[2] * psi);
+#pragma unroll
+                for (int f = 0; f < 5; f++) {
+                    const float df = (float)(phi_j[f] - phi_i[f]) * psi;
+                    S[3 * f + 0] += (double)(df * df3[0]);
+                    S[3 * f + 1] += (double)(df * df3[1]);
+                    S[3 * f + 2] += (double)(df * df3[2]);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 5; f++) {
+                pmax[f] = fmax(pmax[f], phi_j[f]);
+                pmin[f] = fmin(pmin[f], phi_j[f]);
+            }
+            rmax = fmax(rmax, r);
+        }
+        // B = E^-1 by cofactors (E symmetric: xx xy xz yy yz zz)
+        const double c00 = E[3] * E[5] - E[4] * E[4];
+        const double c01 = E[2] * E[4] - E[1] * E[5];
+        const double c02 = E[1] * E[4] - E[2] * E[3];
+        const double c11 = E[0] * E[5] - E[2] * E[2];
+        const double c12 = E[1] * E[2] - E[0] * E[4];
+        const double c22 = E[0] * E[3] - E[1] * E[1];
+        const double det = E[0] * c00 + E[1] * c01 + E[2] * c02;
+        const double idet = 1.0 / det;
+        const double B[6] = {c00 * idet, c01 * idet, c02 * idet, c11 * idet, c12 * idet, c22 * idet};
+        const double fe = E[0] * E[0] + E[3] * E[3] + E[5] * E[5] + 2.0 * (E[1] * E[1] + E[2] * E[2] + E[4] * E[4]);
+        const double fb = B[0] * B[0] + B[3] * B[3] + B[5] * B[5] + 2.0 * (B[1] * B[1] + B[2] * B[2] + B[4] * B[4]);
+        const double cond = sqrt(fe) * sqrt(fb);
+        if (!(det > 0.0) || !(cond <= ph.cond_max)) {
+            ill = 1;
+            flag_index(cnt, i);
+        }
+        if (cond > 0.0) condbits = __double_as_longlong(cond);
+        double g[15];
+        double al[5];
+        const double half = 0.5 * rmax;
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+            const double* s = S + 3 * f;
+            const double g0 = B[0] * s[0] + B[1] * s[1] + B[2] * s[2];
+            const double g1 = B[1] * s[0] + B[3] * s[1] + B[4] * s[2];
+            const double g2 = B[2] * s[0] + B[4] * s[1] + B[5] * s[2];
+            double alpha;
+            if (!MIXED) {
+                const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+                alpha = 1.0;
+                if (gn > 0.0) {
+                    const double up = (pmax[f] - phi_i[f]) / (gn * half);
+                    const double dn = (phi_i[f] - pmin[f]) / (gn * half);
+                    alpha = fmin(1.0, ph.beta * fmin(up, dn));
+                }
+            } else {
+                const float h0 = (float)g0, h1 = (float)g1, h2 = (float)g2;
+                const float gn = sqrtf(h0 * h0 + h1 * h1 + h2 * h2);
+                float af = 1.0f;
+                if (gn > 0.0f) {
+                    const float hf = (float)half;
+                    const float up = (float)(pmax[f] - phi_i[f]) / (gn * hf);
+                    const float dn = (float)(phi_i[f] - pmin[f]) / (gn * hf);
+                    af = fminf(1.0f, (float)ph.beta * fminf(up, dn));
+                }
+                alpha = (double)af;
+            }
+            al[f] = alpha;
+            g[3 * f + 0] = alpha * g0;
+            g[3 * f + 1] = alpha * g1;
+            g[3 * f + 2] = alpha * g2;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) a.B[k * n + i] = B[k];
+#pragma unroll
+        for (int k = 0; k < 15; k++) {
+            a.grad[k * n + i] = g[k];
+            if (!isfinite(g[k])) nonfin = 1;
+        }
+        if (a.alpha) {
+#pragma unroll
+            for (int f = 0; f < 5; f++) a.alpha[f * n + i] = al[f];
+        }
+        a.rho[i] = rho_i;
+        a.P[i] = P_i;
+        const double c_i = sqrt(ph.gamma * P_i / rho_i);
+        if (!MIXED) {
+            double* rec = (double*)recp + (long long)i * 32;
+            double v[32];
+            v[0] = xi[0];
+            v[1] = xi[1];
+            v[2] = xi[2];
+            v[R_H] = Hi;
+            v[R_V] = Vi;
+            v[R_RHO] = rho_i;
+            v[R_P] = P_i;
+            v[R_V0 + 0] = phi_i[1];
+            v[R_V0 + 1] = phi_i[2];
+            v[R_V0 + 2] = phi_i[3];
+#pragma unroll
+            for (int k = 0; k < 6; k++) v[R_B + k] = B[k];
+#pragma unroll
+            for (int k = 0; k < 15; k++) v[R_G + k] = g[k];
+            v[R_C] = c_i;
+            double2* r2 = (double2*)rec;
+#pragma unroll
+            for (int k = 0; k < 16; k++) r2[k] = make_double2(v[2 * k], v[2 * k + 1]);
+        } else {
+            float* rec = (float*)recp + (long long)i * 32;
+            float v[32];
+            v[0] = v[1] = v[2] = 0.0f;
+            v[R_H] = (float)Hi;
+            v[R_V] = (float)Vi;
+            v[R_RHO] = (float)rho_i;
+            v[R_P] = (float)P_i;
+            v[R_V0 + 0] = (float)phi_i[1];
+            v[R_V0 + 1] = (float)phi_i[2];
+            v[R_V0 + 2] = (float)phi_i[3];
+#pragma unroll
+            for (int k = 0; k < 6; k++) v[R_B + k] = (float)B[k];
+#pragma unroll
+            for (int k = 0; k < 15; k++) v[R_G + k] = (float)g[k];
+            v[R_C] = (float)c_i;
+            float4* r4 = (float4*)rec;
+#pragma unroll
+            for (int k = 0; k < 8; k++) r4[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        }
+    }
+    count_add(&cnt->illcond, ill);
+    count_add(&cnt->nonfinite, nonfin);
+    count_max(&cnt->cond_bits, condbits);
+}
+
+// ------------------------------------------------------------------- fluxes
+template <typename T>
+struct PairOut {
+    T Fp[3];
+    T FE;
+    int fallback, clamp;
+};
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T v);
+template <>
+__device__ __forceinline__ double tsqrt<double>(double v) { return sqrt(v); }
+template <>
+__device__ __forceinline__ float tsqrt<float>(float v) { return sqrtf(v); }
+
+// One unordered pair, left state a (lower index), right state b, d = x_b - x_a.
+template <typename T>
+__device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ a, const T* __restrict__ b, const T d[3],
+                                                T r, T gamma) {
+    PairOut<T> o;
+    o.Fp[0] = o.Fp[1] = o.Fp[2] = o.FE = T(0);
+    o.fallback = o.clamp = 0;
+    const T Ha = a[R_H], Hb = b[R_H];
+    const T Wa = kernel_norm(Ha) * spline_w(r / Ha);
+    const T Wb = kernel_norm(Hb) * spline_w(r / Hb);
+    const T* Ba = a + R_B;
+    const T* Bb = b + R_B;
+    const T ta[3] = {Ba[0] * d[0] + Ba[1] * d[1] + Ba[2] * d[2], Ba[1] * d[0] + Ba[3] * d[1] + Ba[4] * d[2],
+                     Ba[2] * d[0] + Ba[4] * d[1] + Ba[5] * d[2]};
+    const T tb[3] = {Bb[0] * d[0] + Bb[1] * d[1] + Bb[2] * d[2], Bb[1] * d[0] + Bb[3] * d[1] + Bb[4] * d[2],
+                     Bb[2] * d[0] + Bb[4] * d[1] + Bb[5] * d[2]};
+    const T ka = a[R_V] * a[R_V] * Wa, kb = b[R_V] * b[R_V] * Wb;
+    T A[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) A[c] = ka * ta[c] + kb * tb[c];
+    const T Amag = tsqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+    if (!(Amag > T(0))) return o;
+    const T nh[3] = {A[0] / Amag, A[1] / Amag, A[2] / Amag};
+
+    // midpoint reconstruction of rho, vx, vy, vz, P
+    const int slot[5] = {R_RHO, R_V0, R_V0 + 1, R_V0 + 2, R_P};
+    T qL[5], qR[5];
+#pragma unroll
+    for (int f = 0; f < 5; f++) {
+        const T* ga = a + R_G + 3 * f;
+        const T* gb = b + R_G + 3 * f;
+        qL[f] = a[slot[f]] + T(0.5) * (ga[0] * d[0] + ga[1] * d[1] + ga[2] * d[2]);
+        qR[f] = b[slot[f]] - T(0.5) * (gb[0] * d[0] + gb[1] * d[1] + gb[2] * d[2]);
+    }
+    if (!(qL[0] > T(0)) || !(qL[4] > T(0)) || !(qR[0] > T(0)) || !(qR[4] > T(0))) {
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+            qL[f] = a[slot[f]];
+            qR[f] = b[slot[f]];
+        }
+        o.fallback = 1;
+    }
+    const T w[3] = {T(0.5) * (a[R_V0] + b[R_V0]), T(0.5) * (a[R_V0 + 1] + b[R_V0 + 1]),
+                    T(0.5) * (a[R_V0 + 2] + b[R_V0 + 2])};
+    const T uL = (qL[1] - w[0]) * nh[0] + (qL[2] - w[1]) * nh[1] + (qL[3] - w[2]) * nh[2];
+    const T uR = (qR[1] - w[0]) * nh[0] + (qR[2] - w[1]) * nh[1] + (qR[3] - w[2]) * nh[2];
+    const T rL = qL[0], pL = qL[4], rR = qR[0], pR = qR[4];
+    const T cL = tsqrt(gamma * pL / rL), cR = tsqrt(gamma * pR / rR);
+    const T SL = (uL - cL < uR - cR) ? uL - cL : uR - cR;
+    const T SR = (uL + cL > uR + cR) ? uL + cL : uR + cR;
+    const T mL = rL * (SL - uL), mR = rR * (SR - uR);
+    const T Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
+    T Ps = T(0.5) * (pL + pR + mL * (Ss - uL) + mR * (Ss - uR));
+    if (Ps < T(0)) {
+        Ps = T(0);
+        o.clamp = 1;
+    }
+    const T wn = w[0] * nh[0] + w[1] * nh[1] + w[2] * nh[2];
+#pragma unroll
+    for (int c = 0; c < 3; c++) o.Fp[c] = Ps * A[c];
+    o.FE = Ps * (Ss + wn) * Amag;
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rec(const T* __restrict__ rec, long long i, T v[32]);
+template <>
+__device__ __forceinline__ void load_rec<double>(const double* __restrict__ rec, long long i, double v[32]) {
+    const double2* p = (const double2*)(rec + i * 32);
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        double2 t = p[k];
+        v[2 * k] = t.x;
+        v[2 * k + 1] = t.y;
+    }
+}
+template <>
+__device__ __forceinline__ void load_rec<float>(const float* __restrict__ rec, long long i, float v[32]) {
+    const float4* p = (const float4*)(rec + i * 32);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        float4 t = p[k];
+        v[4 * k] = t.x;
+        v[4 * k + 1] = t.y;
+        v[4 * k + 2] = t.z;
+        v[4 * k + 3] = t.w;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                 const int* __restrict__ list, const T* __restrict__ rec,
+                                                 Counters* cnt) {
+    const int i = xcd_block() * 256 + threadIdx.x;
+    const bool act = i < a.n;
+    unsigned long long nfall = 0, nclamp = 0, nonfin = 0;
+    if (act) {
+        const long long n = a.n;
+        T ri[32];
+        load_rec<T>(rec, i, ri);
+        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
+        const double vi[3] = {(double)ri[R_V0], (double)ri[R_V0 + 1], (double)ri[R_V0 + 2]};
+        const double ci = (double)ri[R_C];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double vs = 0.0;
+        const T gam = (T)ph.gamma;
+        const int cnum = counts[i];
+        for (int k = 0; k < cnum; k++) {
+            const int j = list[(long long)k * n + i];
+            T rj[32];
+            load_rec<T>(rec, j, rj);
+            double xj[3];
+            if (sizeof(T) == 8) {
+                xj[0] = (double)rj[0];
+                xj[1] = (double)rj[1];
+                xj[2] = (double)rj[2];
+            } else {
+                xj[0] = a.x[j];
+                xj[1] = a.y[j];
+                xj[2] = a.z[j];
+            }
+            double dij[3];
+            displacement(ph, xi, xj[0], xj[1], xj[2], dij);   // x_j - x_i
+            const double r = sqrt(dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2]);
+            const bool iL = i < j;
+            T L[32], R[32];
+#pragma unroll
+            for (int f = 0; f < 32; f++) {
+                L[f] = iL ? ri[f] : rj[f];
+                R[f] = iL ? rj[f] : ri[f];
+            }
+            // canonical displacement x_R - x_L, computed from the canonical pair
+            double dLR[3];
+            if (iL) {
+                dLR[0] = dij[0];
+                dLR[1] = dij[1];
+                dLR[2] = dij[2];
+            } else {
+                displacement(ph, xj, xi[0], xi[1], xi[2], dLR);
+            }
+            const double rLR = sqrt(dLR[0] * dLR[0] + dLR[1] * dLR[1] + dLR[2] * dLR[2]);
+            const T dT[3] = {(T)dLR[0], (T)dLR[1], (T)dLR[2]};
+            PairOut<T> o = pair_flux<T>(L, R, dT, (T)rLR, gam);
+            const double s = iL ? 1.0 : -1.0;
+            acc[0] -= s * (double)o.Fp[0];
+            acc[1] -= s * (double)o.Fp[1];
+            acc[2] -= s * (double)o.Fp[2];
+            acc[3] -= s * (double)o.FE;
+            nfall += o.fallback;
+            nclamp += o.clamp;
+            const double cj = (double)rj[R_C];
+            const double proj = -((vi[0] - (double)rj[R_V0]) * dij[0] + (vi[1] - (double)rj[R_V0 + 1]) * dij[1] +
+                                  (vi[2] - (double)rj[R_V0 + 2]) * dij[2]) / r;
+            vs = fmax(vs, ci + cj - fmin(proj, 0.0));
+        }
+        a.dp[i] = acc[0];
+        a.dp[n + i] = acc[1];
+        a.dp[2 * n + i] = acc[2];
+        a.dE[i] = acc[3];
+        a.vsig[i] = vs;
+        if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(acc[3])) {
+            nonfin = 1;
+            flag_index(cnt, i);
+        }
+    }
+    count_add(&cnt->fallbacks, nfall);
+    count_add(&cnt->clamps, nclamp);
+    count_add(&cnt->nonfinite, nonfin);
+}
+
+// ------------------------------------------------------------------ launchers
+static int blocks_of(int n, int b) { return (n + b - 1) / b; }
+
+void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
+                    const Phys& ph, Counters* cnt, hipStream_t s) {
+    k_solve_h<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, keys, ph, cnt);
+}
+
+void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
+                       const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s) {
+    k_flux_lists<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, hmax, ph, counts, list, cnt);
+}
+
+void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
+                      void* rec, Counters* cnt, hipStream_t s) {
+    if (mixed)
+        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, rec, cnt);
+    else
+        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, rec, cnt);
+}
+
+void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
+                   const void* rec, Counters* cnt, hipStream_t s) {
+    if (mixed)
+        k_fluxes<float><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+    else
+        k_fluxes<double><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+}
+
+}  // namespace mfm

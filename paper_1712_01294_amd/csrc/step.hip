@@ -1,0 +1,124 @@
+// Kick-drift-kick update of the MFM gas and the Courant time-step reduction.
+#include <math.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace mfm {
+
+// first half kick (momentum and total energy), drift with the half-step
+// velocity and wrap, predicted velocity and energy for the flux pass
+__global__ void k_kick_drift(PassArrays a, Phys ph, double dt, double u_floor, double* __restrict__ vp,
+                             double* __restrict__ up, double* __restrict__ Ehalf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const long long n = a.n;
+    const double m = a.m[i];
+    double v[3] = {a.vx[i], a.vy[i], a.vz[i]};
+    double E = m * (a.u[i] + 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * a.dp[c * n + i] / m;
+    E = E + 0.5 * dt * a.dE[i];
+    double* xs[3] = {(double*)a.x, (double*)a.y, (double*)a.z};
+    for (int c = 0; c < 3; c++) {
+        double xc = xs[c][i] + dt * v[c];
+        if (ph.periodic[c]) {
+            const double L = ph.box[c];
+            xc = xc - L * floor(xc / L);
+            if (xc >= L) xc = 0.0;
+        }
+        xs[c][i] = xc;
+    }
+    double q[3];
+    for (int c = 0; c < 3; c++) q[c] = v[c] + 0.5 * dt * a.dp[c * n + i] / m;
+    const double Ep = E + 0.5 * dt * a.dE[i];
+    double uu = Ep / m - 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    uu = fmax(uu, u_floor);
+    ((double*)a.vx)[i] = v[0];
+    ((double*)a.vy)[i] = v[1];
+    ((double*)a.vz)[i] = v[2];
+    vp[i] = q[0];
+    vp[n + i] = q[1];
+    vp[2 * n + i] = q[2];
+    up[i] = uu;
+    Ehalf[i] = E;
+}
+
+// second half kick and recovery of u = E/m - |v|^2/2, floored
+__global__ void k_kick2(PassArrays a, double dt, double u_floor, const double* __restrict__ Ehalf,
+                        double* __restrict__ u, Counters* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long fl = 0;
+    if (i < a.n) {
+        const long long n = a.n;
+        const double m = a.m[i];
+        double v[3] = {a.vx[i], a.vy[i], a.vz[i]};
+        for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * a.dp[c * n + i] / m;
+        const double E = Ehalf[i] + 0.5 * dt * a.dE[i];
+        double uu = E / m - 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (uu < u_floor) {
+            uu = u_floor;
+            fl = 1;
+        }
+        ((double*)a.vx)[i] = v[0];
+        ((double*)a.vy)[i] = v[1];
+        ((double*)a.vz)[i] = v[2];
+        u[i] = uu;
+    }
+    unsigned long long s = fl;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt->floors, s);
+}
+
+// min_i H_i / vsig_i: per-block partial minima, then one block over the partials
+__global__ __launch_bounds__(256) void k_dt_partial(int n, const double* __restrict__ H,
+                                                     const double* __restrict__ vsig, double* __restrict__ part) {
+    __shared__ double sm[256];
+    double v = INFINITY;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        double t = H[i] / vsig[i];
+        v = fmin(v, t);
+    }
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_dt_final(int m, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sm[256];
+    double v = INFINITY;
+    for (int i = threadIdx.x; i < m; i += 256) v = fmin(v, part[i]);
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+int dt_min_parts(int n) {
+    int b = (n + 255) / 256;
+    return b < 1024 ? (b < 1 ? 1 : b) : 1024;
+}
+
+void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor, double* vp, double* up,
+                       double* Ehalf, hipStream_t s) {
+    k_kick_drift<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt, u_floor, vp, up, Ehalf);
+}
+
+void launch_kick2(const PassArrays& a, double dt, double u_floor, const double* Ehalf, double* u, Counters* cnt,
+                  hipStream_t s) {
+    k_kick2<<<(a.n + 255) / 256, 256, 0, s>>>(a, dt, u_floor, Ehalf, u, cnt);
+}
+
+void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts, double* out,
+                   hipStream_t s) {
+    k_dt_partial<<<nparts, 256, 0, s>>>(n, H, vsig, partial);
+    k_dt_final<<<1, 256, 0, s>>>(nparts, partial, out);
+}
+
+}  // namespace mfm

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libmfm.so (include/mfm.h): argument marshalling only.
+
+Every step of the pass runs in the HIP library; PyTorch only provides device
+memory and the stream.  Loading fails loudly when the library is missing or
+no GPU is present: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfm.so")
+
+FP64, MIXED = 0, 1
+
+STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV", -4: "MFM_E_ILLCOND",
+          -5: "MFM_E_MINIMAGE", -6: "MFM_E_CAPACITY", -7: "MFM_E_NONFINITE", -8: "MFM_E_STATE"}
+
+EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "mfm_gradients",
+           "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
+           "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
+           "mfm_hydro_fluxes_adjoint", "mfm_step_adjoint")
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("n_ngb", C.c_double), ("cfl", C.c_double),
+                ("box", C.c_double * 3), ("periodic", C.c_int32 * 3), ("precision", C.c_int32),
+                ("beta", C.c_double), ("cond_max", C.c_double), ("u_floor", C.c_double),
+                ("h_maxit", C.c_int32), ("max_ngb", C.c_int32), ("tree_levels", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", _dp), ("y", _dp), ("z", _dp), ("m", _dp), ("vx", _dp),
+                ("vy", _dp), ("vz", _dp), ("u", _dp), ("H", _dp), ("nk", _dp), ("V", _dp),
+                ("B", _dp), ("rho", _dp), ("P", _dp), ("grad", _dp), ("alpha", _dp), ("dp", _dp),
+                ("dE", _dp), ("vsig", _dp), ("id", C.POINTER(C.c_int64))]
+
+
+class Counters(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("pairs", "list_entries", "list_max", "h_iters", "h_iters_max",
+                                         "noconv", "minimage", "overflow", "illcond", "fallbacks",
+                                         "clamps", "nonfinite", "floors", "first_bad")] + \
+               [("cond_max_seen", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MFMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmfm.so; raise if it is missing (build it with paper_1712_01294_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1712_01294_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.mfm_create.argtypes = [C.POINTER(Params), C.c_int64, C.POINTER(vp)]
+        L.mfm_destroy.argtypes = [vp]
+        L.mfm_destroy.restype = None
+        for f in ("mfm_build_neighbours", "mfm_solve_h", "mfm_gradients", "mfm_hydro_fluxes",
+                  "mfm_hydro_pass"):
+            getattr(L, f).argtypes = [vp, C.POINTER(Particles), vp]
+        L.mfm_step.argtypes = [vp, C.POINTER(Particles), C.c_double, C.POINTER(C.c_double), vp]
+        L.mfm_get_counters.argtypes = [vp, C.POINTER(Counters)]
+        L.mfm_check.argtypes = [vp]
+        L.mfm_copy_flux_lists.argtypes = [vp, vp, vp, vp]
+        L.mfm_max_ngb.argtypes = [vp]
+        L.mfm_max_ngb.restype = C.c_int32
+        L.mfm_status_str.argtypes = [C.c_int]
+        L.mfm_status_str.restype = C.c_char_p
+        L.mfm_last_error.argtypes = [vp]
+        L.mfm_last_error.restype = C.c_char_p
+        if hasattr(L, "mfm_hydro_fluxes_adjoint"):
+            L.mfm_hydro_fluxes_adjoint.argtypes = [vp, C.POINTER(Particles), vp, vp, vp, vp, vp, vp]
+            L.mfm_step_adjoint.argtypes = [vp, C.POINTER(Particles), C.c_double, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("particle arrays must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("particle arrays must be contiguous")
+    return C.cast(C.c_void_p(t.data_ptr()), _dp)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Config:
+    gamma: float
+    box: tuple
+    periodic: tuple = (1, 1, 1)
+    n_ngb: float = 32.0
+    cfl: float = 0.25
+    precision: int = FP64
+    beta: float = 1.0
+    cond_max: float = 1.0e6
+    u_floor: float = 0.0
+    h_maxit: int = 64
+    max_ngb: int = 256
+    tree_levels: int = 0
+
+    def c(self) -> Params:
+        p = Params()
+        p.gamma = self.gamma
+        p.n_ngb = self.n_ngb
+        p.cfl = self.cfl
+        for a in range(3):
+            p.box[a] = self.box[a]
+            p.periodic[a] = int(self.periodic[a])
+        p.precision = int(self.precision)
+        p.beta = self.beta
+        p.cond_max = self.cond_max
+        p.u_floor = self.u_floor
+        p.h_maxit = self.h_maxit
+        p.max_ngb = self.max_ngb
+        p.tree_levels = self.tree_levels
+        return p
+
+
+class State:
+    """Device-resident SoA particle arrays (float64) in the layout of mfm_particles."""
+
+    INPUTS = ("x", "y", "z", "m", "vx", "vy", "vz", "u")
+
+    def __init__(self, n: int, device="cuda", alpha: bool = False, ids: bool = True):
+        f = dict(dtype=torch.float64, device=device)
+        self.n = n
+        for k in self.INPUTS + ("H", "nk", "V", "rho", "P", "dE", "vsig"):
+            setattr(self, k, torch.zeros(n, **f))
+        self.B = torch.zeros(6, n, **f)
+        self.grad = torch.zeros(15, n, **f)
+        self.dp = torch.zeros(3, n, **f)
+        self.alpha = torch.zeros(5, n, **f) if alpha else None
+        self.id = torch.arange(n, dtype=torch.int64, device=device) if ids else None
+
+    @classmethod
+    def from_arrays(cls, arrays: dict, device="cuda", **kw) -> "State":
+        n = int(arrays["x"].shape[0])
+        st = cls(n, device=device, **kw)
+        for k in cls.INPUTS:
+            getattr(st, k).copy_(torch.as_tensor(arrays[k], dtype=torch.float64))
+        return st
+
+    def struct(self) -> Particles:
+        p = Particles()
+        p.n = self.n
+        for k in ("x", "y", "z", "m", "vx", "vy", "vz", "u", "H", "nk", "V", "B", "rho", "P", "grad",
+                  "alpha", "dp", "dE", "vsig"):
+            setattr(p, k, _ptr(getattr(self, k)))
+        p.id = C.cast(C.c_void_p(self.id.data_ptr()), C.POINTER(C.c_int64)) if self.id is not None else None
+        return p
+
+
+class Context:
+    """One library context (scratch for up to `capacity` particles)."""
+
+    def __init__(self, cfg: Config, capacity: int):
+        self.cfg = cfg
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.mfm_create(C.byref(cfg.c()), C.c_int64(capacity), C.byref(h))
+        if rc != 0:
+            raise MFMError(rc, "mfm_create failed (bad parameters or out of device memory)")
+        self.h = h
+        self.capacity = capacity
+
+    def close(self):
+        if self.h:
+            self._L.mfm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc):
+        if rc != 0:
+            raise MFMError(rc, self._L.mfm_last_error(self.h).decode())
+
+    def _call(self, name, st: State, stream=None):
+        p = st.struct()
+        self._rc(getattr(self._L, name)(self.h, C.byref(p), _stream(stream)))
+
+    def build_neighbours(self, st: State, stream=None):
+        self._call("mfm_build_neighbours", st, stream)
+
+    def solve_h(self, st: State, stream=None):
+        self._call("mfm_solve_h", st, stream)
+
+    def gradients(self, st: State, stream=None):
+        self._call("mfm_gradients", st, stream)
+
+    def hydro_fluxes(self, st: State, stream=None):
+        self._call("mfm_hydro_fluxes", st, stream)
+
+    def hydro_pass(self, st: State, stream=None):
+        self._call("mfm_hydro_pass", st, stream)
+
+    def step(self, st: State, dt: float = 0.0, stream=None) -> float:
+        p = st.struct()
+        used = C.c_double(0.0)
+        self._rc(self._L.mfm_step(self.h, C.byref(p), C.c_double(dt), C.byref(used), _stream(stream)))
+        return used.value
+
+    def counters(self) -> dict:
+        c = Counters()
+        self._rc(self._L.mfm_get_counters(self.h, C.byref(c)))
+        return c.as_dict()
+
+    def check(self):
+        self._rc(self._L.mfm_check(self.h))
+
+    def flux_lists(self, n: int, stream=None):
+        mx = int(self._L.mfm_max_ngb(self.h))
+        counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+        lst = torch.zeros(mx, n, dtype=torch.int32, device="cuda")
+        self._rc(self._L.mfm_copy_flux_lists(self.h, C.c_void_p(counts.data_ptr()),
+                                             C.c_void_p(lst.data_ptr()), _stream(stream)))
+        return counts, lst
+
+
+def config_of(w, precision=FP64, **kw) -> Config:
+    """Context configuration for a workload from ``workloads``."""
+    u_floor = kw.pop("u_floor", 1e-10 * float(sum(w.u) / len(w.u)))
+    return Config(gamma=w.gamma, box=tuple(w.box), periodic=tuple(w.periodic), n_ngb=w.n_ngb,
+                  cfl=w.cfl, precision=precision, u_floor=u_floor, **kw)

@@ -163,7 +163,7 @@ def gaussian_field(n: int, power, rng: np.random.Generator, kmin: float, kmax: f
     filt = np.zeros_like(kk)
     band = (kk >= kmin) & (kk <= kmax)
     filt[band] = np.sqrt(power(kk[band]))
-    f = np.fft.irfftn(wk * filt, s=(n, n, n))
+    f = np.fft.irfftn(wk * filt, s=(n, n, n), axes=(0, 1, 2))
     return f
 
 

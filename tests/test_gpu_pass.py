@@ -1,0 +1,190 @@
+"""Parity of the HIP hydro pass (through the C ABI) with the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1712_01294_amd import workloads as W
+
+from .gpu_util import compare_pass, elem_rel, in_input_order, nerr, run_pass
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12     # normwise per field, FP64 path against the FP64 oracle
+TOL_MIXED = 1e-5     # normwise on fluxes, mixed path against the FP64 oracle
+
+
+@pytest.fixture(scope="module")
+def sine16():
+    w = W.jittered_sine(n_side=16)
+    ref = O.hydro_pass(O.Setup.of(w), w.arrays())
+    return w, ref
+
+
+def _print(tag, errs):
+    print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+
+
+def test_fp64_pass_matches_oracle(sine16):
+    w, ref = sine16
+    ctx, st = run_pass(w)
+    ctx.check()
+    errs = compare_pass(st, ref)
+    _print("fp64", errs)
+    for k, e in errs.items():
+        assert e <= TOL_FP64, (k, e)
+    for k in ("H", "nk", "V"):
+        assert elem_rel(in_input_order(st, k), ref[k]) <= TOL_FP64
+    assert ctx.counters()["pairs"] == ref["pairs"]
+
+
+def test_flux_lists_equal_brute_force(sine16):
+    """Integer sets: every particle's flux list equals the O(N^2) set r < max(H_i, H_j)."""
+    w, ref = sine16
+    ctx, st = run_pass(w)
+    counts, lst = ctx.flux_lists(w.n)
+    counts = counts.cpu().numpy()
+    lst = lst.cpu().numpy()
+    ids = st.id.cpu().numpy()
+    X = np.stack([w.x, w.y, w.z], 1)
+    H = ref["H"]
+    for k in range(w.n):
+        i = ids[k]
+        got = np.sort(ids[lst[: counts[k], k]])
+        d = X - X[i]
+        d -= np.round(d)
+        r = np.sqrt((d * d).sum(1))
+        want = np.flatnonzero((r < np.maximum(H[i], H)) & (np.arange(w.n) != i))
+        assert np.array_equal(got, want), i
+
+
+def test_reorder_is_a_permutation(sine16):
+    w, _ = sine16
+    ctx, st = run_pass(w)
+    ids = st.id.cpu().numpy()
+    assert np.array_equal(np.sort(ids), np.arange(w.n))
+    for k in ("x", "y", "z", "m", "vx", "u"):
+        assert np.array_equal(getattr(st, k).cpu().numpy(), getattr(w, k)[ids])
+
+
+def test_deterministic_bitwise(sine16):
+    w, _ = sine16
+    _, a = run_pass(w)
+    _, b = run_pass(w)
+    for k in ("H", "B", "grad", "dp", "dE", "vsig"):
+        assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
+
+
+def test_conservation_roundoff(sine16):
+    w, _ = sine16
+    _, st = run_pass(w)
+    dp = st.dp.cpu().numpy()
+    dE = st.dE.cpu().numpy()
+    eps = np.finfo(np.float64).eps
+    for c in range(3):
+        assert abs(dp[c].sum()) <= 10 * eps * np.abs(dp).sum()
+    assert abs(dE.sum()) <= 10 * eps * np.abs(dE).sum()
+
+
+def test_mixed_precision_error_and_conservation(sine16):
+    w, ref = sine16
+    ctx, st = run_pass(w, precision=1)
+    ctx.check()
+    errs = compare_pass(st, ref)
+    _print("mixed", errs)
+    for k in ("H", "nk", "V"):
+        assert errs[k] <= TOL_FP64
+    for k in ("dp", "dE"):
+        assert errs[k] <= TOL_MIXED, (k, errs[k])
+    dp = st.dp.cpu().numpy()
+    eps = np.finfo(np.float64).eps
+    for c in range(3):
+        assert abs(dp[c].sum()) <= 10 * eps * np.abs(dp).sum()
+
+
+@pytest.mark.parametrize("n_side,jitter", [(8, 0.0), (21, 0.2)])
+def test_lattices_ragged_and_perfect(n_side, jitter):
+    """21^3 = 9261 particles: several tiles and a ragged last block; 8^3 unjittered:
+    27-site shells, 13 pairs per particle, faces close exactly."""
+    w = W.jittered_sine(n_side=n_side, jitter=jitter, seed=W.SEED_BASE + 40 + n_side)
+    ref = O.hydro_pass(O.Setup.of(w), w.arrays())
+    ctx, st = run_pass(w)
+    ctx.check()
+    errs = compare_pass(st, ref)
+    _print(f"lattice{n_side}", errs)
+    for k, e in errs.items():
+        assert e <= TOL_FP64, (k, e)
+    assert ctx.counters()["pairs"] == ref["pairs"]
+    if jitter == 0.0:
+        assert ctx.counters()["pairs"] == 13 * w.n
+
+
+def test_open_box_random_set():
+    rng = np.random.default_rng(21)
+    n = 3000
+    w = W.Workload(name="open", x=rng.uniform(0, 1, n), y=rng.uniform(0, 0.5, n), z=rng.uniform(0, 1, n),
+                   m=rng.uniform(0.5, 1.5, n) / n, vx=rng.normal(0, 0.2, n), vy=rng.normal(0, 0.2, n),
+                   vz=rng.normal(0, 0.2, n), u=rng.uniform(1, 2, n), gamma=1.4, box=(1.0, 0.5, 1.0),
+                   periodic=(0, 0, 0))
+    ref = O.hydro_pass(O.Setup.of(w), w.arrays())
+    ctx, st = run_pass(w)
+    errs = compare_pass(st, ref)
+    _print("open", errs)
+    for k, e in errs.items():
+        assert e <= TOL_FP64, (k, e)
+
+
+def test_error_paths_forced_from_host(sine16):
+    import torch
+
+    from paper_1712_01294_amd import mfm
+    w, _ = sine16
+    cfg = mfm.config_of(w)
+    ctx = mfm.Context(cfg, 100)
+    st = mfm.State.from_arrays(w.arrays())
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.build_neighbours(st)
+    assert e.value.status == -6
+    ctx = mfm.Context(cfg, w.n)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.gradients(st)
+    assert e.value.status == -8
+    # neighbour-list overflow reported as a capacity error
+    ctx = mfm.Context(mfm.config_of(w, max_ngb=8), w.n)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.check()
+    assert e.value.status == -6
+    # one Newton iteration is not enough to converge
+    st = mfm.State.from_arrays(w.arrays())
+    ctx = mfm.Context(mfm.config_of(w, h_maxit=1), w.n)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.check()
+    assert e.value.status == -3
+    torch.cuda.synchronize()
+
+
+def test_turbulence_full_size_sampled():
+    """2,097,152 particles (128^3 Mach-2 turbulence): sampled oracle outputs at 24
+    particles, and conservation over the whole set."""
+    w = W.turbulence()
+    ctx, st = run_pass(w)
+    ctx.check()
+    c = ctx.counters()
+    print("turbulence pairs/particle", c["pairs"] / w.n, "list max", c["list_max"], flush=True)
+    H = in_input_order(st, "H")
+    rng = np.random.default_rng(5)
+    targets = rng.choice(w.n, 24, replace=False)
+    ref = O.sampled_pass(O.Setup.of(w), w.arrays(), targets, h_bound=float(H.max()) * 1.0001)
+    for k in ("H", "nk"):
+        assert elem_rel(H[targets] if k == "H" else in_input_order(st, k)[targets], ref[k][targets]) <= TOL_FP64
+    for k in ("dp", "grad", "B"):
+        got = in_input_order(st, k)[:, targets]
+        assert nerr(got, ref[k][:, targets]) <= TOL_FP64, k
+    assert nerr(in_input_order(st, "dE")[targets], ref["dE"][targets]) <= TOL_FP64
+    dp = st.dp.cpu().numpy()
+    eps = np.finfo(np.float64).eps
+    for comp in range(3):
+        assert abs(dp[comp].sum()) <= 10 * eps * np.abs(dp).sum()
