@@ -110,6 +110,8 @@ typedef struct {
     int64_t floors;          /* u floors applied by mfm_step                        */
     int64_t first_bad;       /* lowest particle index flagged by any of the above   */
     double cond_max_seen;    /* largest ||E||_F ||B||_F                             */
+    int64_t h_rounds_max;    /* most neighbour scans one kernel-length solve needed */
+    int64_t h_fallback;      /* particles solved one by one (very long gather sets) */
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:

@@ -24,6 +24,8 @@ struct mfm_ctx {
     int2* tab = nullptr;
     float* hmax = nullptr;
     int *counts = nullptr, *list = nullptr;
+    int* fb_list = nullptr;               // particles handed to the per-particle kernel-length solve
+    unsigned long long* fb_count = nullptr;
     void* rec = nullptr;                  // 32 x 8 B per particle
     double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
     double *dt_part = nullptr, *dt_out = nullptr;
@@ -60,7 +62,7 @@ static void setup_tree(mfm_ctx* c) {
     TreeDesc& td = c->td;
     memset(&td, 0, sizeof(td));
     int bmax = c->p.tree_levels;
-    if (bmax <= 0) bmax = ceil_log2(cbrt((double)c->cap)) + 1;
+    if (bmax <= 0) bmax = ceil_log2(cbrt((double)c->cap)) + 2;   // ~1/64 particle per finest cell
     if (bmax < 2) bmax = 2;
     if (bmax > kMaxLevels - 1) bmax = kMaxLevels - 1;
     double Lmax = fmax(c->p.box[0], fmax(c->p.box[1], c->p.box[2]));
@@ -127,7 +129,7 @@ void mfm_destroy(mfm_ctx* c) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->hmax,
-                    c->counts, c->list, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
+                    c->counts, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -177,6 +179,8 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->hmax, sizeof(float) * c->hmax_len, "cell hmax");
     alloc((void**)&c->counts, sizeof(int) * n, "list counts");
     alloc((void**)&c->list, sizeof(int) * n * c->ph.max_ngb, "flux lists");
+    alloc((void**)&c->fb_list, sizeof(int) * n, "fallback list");
+    alloc((void**)&c->fb_count, sizeof(unsigned long long), "fallback count");
     alloc((void**)&c->rec, sizeof(double) * 32 * n, "records");
     alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
     alloc((void**)&c->up, sizeof(double) * n, "predicted u");
@@ -288,7 +292,10 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->nk || !p->V) return fail(c, MFM_E_INVALID, "nk and V are required");
     if (c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_build_neighbours must run on these particles first");
     PassArrays a = arrays_of(p);
-    launch_solve_h(a, c->td, c->tab, c->keys, c->ph, c->cnt, s);
+    // the radius lists of the kernel-length solve live in the flux-list buffer,
+    // which is rebuilt right after: max_ngb int slots hold max_ngb / 2 doubles
+    launch_solve_h(a, c->td, c->tab, c->keys, c->ph, c->cnt, (double*)c->list, c->ph.max_ngb / 2, c->fb_list,
+                   c->fb_count, s);
     launch_hmax(a.n, c->keys, c->td, c->tab, p->H, c->hmax, s);
     launch_flux_lists(a, c->td, c->tab, c->hmax, c->ph, c->counts, c->list, c->cnt, s);
     c->have_h = 1;
@@ -417,6 +424,8 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     double cm;
     memcpy(&cm, &h.cond_bits, sizeof(cm));
     out->cond_max_seen = cm;
+    out->h_rounds_max = (int64_t)h.h_rounds_max;
+    out->h_fallback = (int64_t)h.h_fallback;
     return MFM_OK;
 }
 

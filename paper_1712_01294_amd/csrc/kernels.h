@@ -40,7 +40,8 @@ void launch_hmax(int n, const unsigned long long* keys, const TreeDesc& td, cons
 
 // pass.hip
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
-                    const unsigned long long* keys, const Phys& ph, Counters* cnt, hipStream_t s);
+                    const unsigned long long* keys, const Phys& ph, Counters* cnt, double* rl, int cap,
+                    int* fb_list, unsigned long long* fb_count, hipStream_t s);
 void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
                        const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s);
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list,

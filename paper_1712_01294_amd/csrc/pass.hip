@@ -58,7 +58,14 @@ __device__ __forceinline__ void displacement(const Phys& ph, const double xi[3],
 }
 
 // ------------------------------------------------------------ kernel length
-constexpr int kHCap = 64;   // LDS slots per particle for the radii inside the bracket
+// The root of (32/3) sum_j w(r_ij / H) = n_ngb is found per particle by
+// safeguarded Newton iterations on the radii r_ij < hi of a bracket (lo, hi].
+// The radii come from one group scan of the wave's 64 particles and are kept
+// in a global scratch list (rl[k * n + i], coalesced across the wave, resident
+// in L2 while the same wave iterates on it).  A lane whose trial radius holds
+// too few or too many neighbours adjusts it and the wave scans again; lanes
+// still without a bracket after a few rounds go to the per-particle fallback.
+constexpr int kGroupLeaf = 32;  // group walks stop descending at <= 32 particles
 
 __device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, unsigned long long key,
                              double n_ngb) {
@@ -75,99 +82,263 @@ __device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, u
     return 0.0;
 }
 
+// safeguarded Newton on the m radii rl[k * n + i]; returns converged
+__device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int m, double n_ngb, int maxit,
+                         double& lo, double& hi, double& Hc, unsigned long long& iters) {
+    const double c32 = 32.0 / 3.0;
+    for (int it = 0; it < maxit; it++) {
+        iters++;
+        const double iH = 1.0 / Hc;
+        double s = 0.0, sq = 0.0;
+        for (int k = 0; k < m; k++) {
+            const double q = rl[(long long)k * n + i] * iH;
+            s += spline_w(q);
+            sq += spline_qdw(q);
+        }
+        const double f = c32 * s - n_ngb;
+        if (f == 0.0) return true;
+        if (f < 0.0) lo = Hc;
+        else hi = Hc;
+        const double fp = -c32 * sq * iH;
+        double Hn = Hc - f / fp;
+        // a converged step is taken even at a bracket edge: an earlier iterate
+        // can land on the root and become lo or hi
+        if (fabs(Hn - Hc) <= 1e-14 * Hc) {
+            Hc = fmin(hi, fmax(lo, Hn));
+            return true;
+        }
+        if (!(Hn > lo && Hn <= hi)) Hn = 0.5 * (lo + hi);
+        const double dH = fabs(Hn - Hc);
+        Hc = Hn;
+        if (dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi)) return true;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                  const unsigned long long* __restrict__ keys, Phys ph,
-                                                 Counters* cnt) {
-    __shared__ double lst[kHCap * 64];
+                                                 Counters* cnt, double* __restrict__ rl, int cap,
+                                                 int* __restrict__ fb_list,
+                                                 unsigned long long* __restrict__ fb_count) {
+    __shared__ double tx[64], ty[64], tz[64];
+    __shared__ unsigned int tm[64];
+    __shared__ GroupWalk gw;
+    __shared__ SubGroups sg;
     const int lane = threadIdx.x;
+    const unsigned int mysub = 1u << (lane >> 3);
     const int i = xcd_block() * 64 + lane;
     const bool act = i < a.n;
-    unsigned long long iters = 0, noconv = 0, noimg = 0;
+    const long long n = a.n;
+    const double c32 = 32.0 / 3.0;
+    double xi[3] = {0.0, 0.0, 0.0};
+    double half = INFINITY;
+    for (int d = 0; d < 3; d++)
+        if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+    double guess = 0.0;
+    bool warm = false;
     if (act) {
+        xi[0] = a.x[i];
+        xi[1] = a.y[i];
+        xi[2] = a.z[i];
+        guess = a.H[i];
+        warm = guess > 0.0;
+        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
+    }
+    // per-lane bracket state
+    double lo = 0.0, hi = INFINITY;
+    double R = (warm ? 1.1 : 1.4) * guess;
+    bool done = !act, ok = false;
+    int m = 0;
+    double neff_hi = 0.0;
+    unsigned long long iters = 0, rounds = 0;
+    for (int round = 0; round < 12; round++) {
+        bool need = !done;
+        if (need && !(R < half)) {
+            R = half * (1.0 - 1e-12);
+            if (!(R > lo)) {   // the root lies beyond half a periodic side
+                need = false;
+                done = true;
+            }
+        }
+        if (!__any(need)) break;
+        set_subgroups(sg, act, xi, need ? R : -1.0);
+        const double R2 = R * R, iR = 1.0 / R;
+        double sw = 0.0;
+        if (need) {   // lanes already done keep their stored radii and count
+            m = 0;
+            rounds++;
+        }
+        group_walk(
+            td, tab, a.n, kGroupLeaf, gw,
+            [&](int, unsigned long long, const double* nlo, const double* nhi, unsigned int pm) {
+                return subgroup_hits(td, sg, pm, nlo, nhi, 0.0);
+            },
+            [&](int rs0, int nb, int total) {
+                for (int base = 0; base < total; base += 64) {
+                    const int t = base + lane;
+                    if (t < total) {
+                        int k;
+                        const int j = batch_candidate(gw, rs0, nb, t, k);
+                        tx[lane] = a.x[j];
+                        ty[lane] = a.y[j];
+                        tz[lane] = a.z[j];
+                        tm[lane] = gw.rm[k];
+                    }
+                    __syncthreads();
+                    const int cnum = min(64, total - base);
+                    if (need) {
+                        for (int u = 0; u < cnum; u++) {
+                            if (!(tm[u] & mysub)) continue;
+                            double d[3];
+                            displacement(ph, xi, tx[u], ty[u], tz[u], d);
+                            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                            if (r2 < R2) {
+                                const double r = sqrt(r2);
+                                if (r < R) {
+                                    if (m < cap) rl[(long long)m * n + i] = r;
+                                    m++;
+                                    sw += spline_w(r * iR);
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            });
+        if (need) {
+            const double neff = c32 * sw;
+            if (neff < ph.n_ngb) {
+                lo = R;
+                if (hi < INFINITY) {
+                    R = 0.5 * (lo + hi);
+                } else {
+                    // grow by the density estimate, at least 1.15x, at most 2x
+                    const double g = 1.1 * cbrt(ph.n_ngb / neff);
+                    R *= fmin(2.0, fmax(1.15, g));
+                }
+            } else {
+                hi = R;
+                if (m > cap) {
+                    // too many radii to keep: shrink towards the estimated root
+                    const double est = R * cbrt(ph.n_ngb / neff);
+                    const double fit = R * cbrt(0.8 * cap / (double)m);
+                    R = fmax(lo + 0.25 * (hi - lo), fmax(1.02 * est, fit));
+                    if (!(R < hi)) R = 0.5 * (lo + hi);
+                } else {
+                    neff_hi = neff;
+                    ok = true;
+                    done = true;
+                }
+            }
+        }
+    }
+    if (act) {
+        bool conv = false;
+        double Hc = 0.0;
+        if (ok) {
+            Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
+            if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
+            conv = newton_h(rl, n, i, m, ph.n_ngb, ph.h_maxit, lo, hi, Hc, iters);
+        }
+        if (ok && conv) {
+            double s = 0.0;
+            const double iH = 1.0 / Hc;
+            for (int k = 0; k < m; k++) s += spline_w(rl[(long long)k * n + i] * iH);
+            const double nk = kernel_norm(Hc) * s;
+            a.H[i] = Hc;
+            a.nk[i] = nk;
+            a.V[i] = 1.0 / nk;
+        } else {
+            // hand over to the per-particle solver, which starts from this bracket
+            const unsigned long long slot = atomicAdd(fb_count, 1ull);
+            if (slot < (unsigned long long)a.n) fb_list[slot] = i;
+            a.H[i] = (hi < INFINITY) ? hi : (lo > 0.0 ? lo : guess);
+        }
+    }
+    count_add(&cnt->h_iters, iters + rounds);
+    count_max(&cnt->h_iters_max, iters + rounds);
+    count_max(&cnt->h_rounds_max, rounds);
+}
+
+// Per-particle solve for the few particles the group solve handed over: every
+// residual evaluation walks the tree again, so there is no limit on the number
+// of neighbours.  Bracket grows from H until it holds the root, then Newton
+// with bisection safeguard.
+__global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                          Phys ph, Counters* cnt, const int* __restrict__ fb_list,
+                                                          const unsigned long long* __restrict__ fb_count) {
+    const unsigned long long nfb = *fb_count;
+    const unsigned long long t = (unsigned long long)blockIdx.x * 64 + threadIdx.x;
+    if (t == 0) cnt->h_fallback = nfb;
+    unsigned long long iters = 0, noconv = 0, noimg = 0;
+    if (t < nfb && t < (unsigned long long)a.n) {
+        const int i = fb_list[t];
         const double xi[3] = {a.x[i], a.y[i], a.z[i]};
         double half = INFINITY;
         for (int d = 0; d < 3; d++)
             if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
-        double guess = a.H[i];
-        const bool warm = guess > 0.0;
-        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
-        double lo = 0.0, hi = INFINITY;
-        double R = (warm ? 1.2 : 1.6) * guess;
-        int m = 0;
-        double neff_hi = 0.0;
-        bool ok = false;
         const double c32 = 32.0 / 3.0;
-        for (int att = 0; att < 80; att++) {
-            iters++;
-            if (!(R < half)) {
-                R = half * (1.0 - 1e-12);
-                if (!(R > lo)) break;   // the root lies beyond half a periodic side
-            }
-            const double R2 = R * R;
-            const double iR = 1.0 / R;
-            m = 0;
-            double sw = 0.0;
+        // residual and slope at H, summing over r < H
+        auto eval = [&](double H, double& f, double& fp, double& nk) {
+            const double H2 = H * H, iH = 1.0 / H;
+            double s = 0.0, sq = 0.0;
             tree_walk(
                 td, tab,
                 [&](int, unsigned long long, const double* nlo, const double* nhi) {
-                    return node_dist2(td, xi, nlo, nhi) < R2;
+                    return node_dist2(td, xi, nlo, nhi) < H2;
                 },
-                [&](int s, int e) {
-                    for (int j = s; j < e; j++) {
+                [&](int s0, int e0) {
+                    for (int j = s0; j < e0; j++) {
                         double d[3];
                         displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
-                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        if (r2 < R2) {
-                            double r = sqrt(r2);
-                            if (r < R) {
-                                if (m < kHCap) lst[m * 64 + lane] = r;
-                                m++;
-                                sw += spline_w(r * iR);
-                            }
+                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        if (r2 < H2) {
+                            const double q = sqrt(r2) * iH;
+                            s += spline_w(q);
+                            sq += spline_qdw(q);
                         }
                     }
                 });
-            double f = c32 * sw - ph.n_ngb;
-            if (f < 0.0) {
-                lo = R;
-                R = (hi < INFINITY) ? 0.5 * (lo + hi) : 1.5 * R;
-                continue;
+            f = c32 * s - ph.n_ngb;
+            fp = -c32 * sq * iH;
+            nk = kernel_norm(H) * s;
+        };
+        double lo = 0.0, hi = a.H[i];
+        double f, fp, nk;
+        bool ok = false;
+        for (int k = 0; k < 64; k++) {
+            iters++;
+            if (!(hi < half)) hi = half * (1.0 - 1e-12);
+            eval(hi, f, fp, nk);
+            if (f >= 0.0) {
+                ok = true;
+                break;
             }
-            hi = R;
-            if (m > kHCap) {
-                R = 0.5 * (lo + hi);
-                continue;
-            }
-            neff_hi = c32 * sw;
-            ok = true;
-            break;
+            if (!(hi < half * (1.0 - 1e-13))) break;
+            lo = hi;
+            hi *= 1.3;
         }
-        double Hc = 0.0;
         bool conv = false;
+        double Hc = hi;
         if (ok) {
-            // Newton on the stored radii, safeguarded by the bracket (lo, hi]
-            Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
-            if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
+            Hc = 0.5 * (lo + hi);
             for (int it = 0; it < ph.h_maxit; it++) {
                 iters++;
-                const double iH = 1.0 / Hc;
-                double s = 0.0, sq = 0.0;
-                for (int k = 0; k < m; k++) {
-                    double q = lst[k * 64 + lane] * iH;
-                    s += spline_w(q);
-                    sq += spline_qdw(q);
-                }
-                double f = c32 * s - ph.n_ngb;
+                eval(Hc, f, fp, nk);
                 if (f == 0.0) {
                     conv = true;
                     break;
                 }
                 if (f < 0.0) lo = Hc;
                 else hi = Hc;
-                double fp = -c32 * sq * iH;
                 double Hn = Hc - f / fp;
-                if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
-                double dH = fabs(Hn - Hc);
+                if (fabs(Hn - Hc) <= 1e-14 * Hc) {
+                    Hc = fmin(hi, fmax(lo, Hn));
+                    conv = true;
+                    break;
+                }
+                if (!(Hn > lo && Hn <= hi)) Hn = 0.5 * (lo + hi);
+                const double dH = fabs(Hn - Hc);
                 Hc = Hn;
                 if (dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi)) {
                     conv = true;
@@ -175,17 +346,13 @@ __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const
                 }
             }
         }
-        if (!ok) {
-            noimg = 1;
-            Hc = lo;
-        } else if (!conv) {
-            noconv = 1;
+        if (ok && conv) eval(Hc, f, fp, nk);
+        else {
+            nk = 0.0;
+            if (!ok) noimg = 1;
+            else noconv = 1;
+            flag_index(cnt, i);
         }
-        if (!ok || !conv) flag_index(cnt, i);
-        double s = 0.0;
-        const double iH = 1.0 / Hc;
-        for (int k = 0; k < (m < kHCap ? m : kHCap); k++) s += spline_w(lst[k * 64 + lane] * iH);
-        double nk = kernel_norm(Hc) * s;
         a.H[i] = Hc;
         a.nk[i] = nk;
         a.V[i] = 1.0 / nk;
@@ -197,37 +364,75 @@ __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const
 }
 
 // --------------------------------------------------------------- flux lists
-// list[k * n + i] = k-th j (walk order) with j != i and r_ij < max(H_i, H_j)
-__global__ __launch_bounds__(256) void k_flux_lists(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
-                                                     const float* __restrict__ hmax, Phys ph,
-                                                     int* __restrict__ counts, int* __restrict__ list,
-                                                     Counters* cnt) {
-    const int i = xcd_block() * 256 + threadIdx.x;
+// list[k * n + i] = k-th j (walk order) with j != i and r_ij < max(H_i, H_j).
+// One group walk per wave; a node is opened when it is closer to the group box
+// than max(largest H of the group, largest H in the node).
+__global__ __launch_bounds__(64) void k_flux_lists(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                    const float* __restrict__ hmax, Phys ph,
+                                                    int* __restrict__ counts, int* __restrict__ list,
+                                                    Counters* cnt) {
+    __shared__ double tx[64], ty[64], tz[64], th[64];
+    __shared__ int tj[64];
+    __shared__ unsigned int tm[64];
+    __shared__ GroupWalk gw;
+    __shared__ SubGroups sg;
+    const int lane = threadIdx.x;
+    const unsigned int mysub = 1u << (lane >> 3);
+    const int i = xcd_block() * 64 + lane;
     const bool act = i < a.n;
-    unsigned long long c = 0, over = 0;
+    double xi[3] = {0.0, 0.0, 0.0};
+    double Hi = 0.0;
     if (act) {
-        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
-        const double Hi = a.H[i];
-        const long long n = a.n;
-        const int cap = ph.max_ngb;
-        tree_walk(
-            td, tab,
-            [&](int l, unsigned long long cc, const double* nlo, const double* nhi) {
-                double h = fmax(Hi, (double)hmax[td.hmax_off[l] + (long long)cc]);
-                return node_dist2(td, xi, nlo, nhi) < h * h;
-            },
-            [&](int s, int e) {
-                for (int j = s; j < e; j++) {
-                    if (j == i) continue;
-                    double d[3];
-                    displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
-                    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                    if (r < Hi || r < a.H[j]) {
-                        if (c < (unsigned long long)cap) list[(long long)c * n + i] = j;
-                        c++;
+        xi[0] = a.x[i];
+        xi[1] = a.y[i];
+        xi[2] = a.z[i];
+        Hi = a.H[i];
+    }
+    set_subgroups(sg, act, xi, act ? Hi : -1.0);
+    const long long n = a.n;
+    const int cap = ph.max_ngb;
+    unsigned long long c = 0, over = 0;
+    group_walk(
+        td, tab, a.n, kGroupLeaf, gw,
+        [&](int l, unsigned long long cc, const double* nlo, const double* nhi, unsigned int pm) {
+            return subgroup_hits(td, sg, pm, nlo, nhi, (double)hmax[td.hmax_off[l] + (long long)cc]);
+        },
+        [&](int rs0, int nb, int total) {
+            for (int base = 0; base < total; base += 64) {
+                const int t = base + lane;
+                if (t < total) {
+                    int k;
+                    const int j = batch_candidate(gw, rs0, nb, t, k);
+                    tx[lane] = a.x[j];
+                    ty[lane] = a.y[j];
+                    tz[lane] = a.z[j];
+                    th[lane] = a.H[j];
+                    tj[lane] = j;
+                    tm[lane] = gw.rm[k];
+                }
+                __syncthreads();
+                const int cnum = min(64, total - base);
+                if (act) {
+                    for (int u = 0; u < cnum; u++) {
+                        if (!(tm[u] & mysub)) continue;
+                        const int j = tj[u];
+                        double d[3];
+                        displacement(ph, xi, tx[u], ty[u], tz[u], d);
+                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        const double hm = fmax(Hi, th[u]);
+                        if (r2 < 1.0000001 * hm * hm && j != i) {
+                            const double r = sqrt(r2);
+                            if (r < Hi || r < th[u]) {
+                                if (c < (unsigned long long)cap) list[(long long)c * n + i] = j;
+                                c++;
+                            }
+                        }
                     }
                 }
-            });
+                __syncthreads();
+            }
+        });
+    if (act) {
         if (c > (unsigned long long)cap) {
             over = 1;
             flag_index(cnt, i);
@@ -619,13 +824,17 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
 static int blocks_of(int n, int b) { return (n + b - 1) / b; }
 
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
-                    const Phys& ph, Counters* cnt, hipStream_t s) {
-    k_solve_h<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, keys, ph, cnt);
+                    const Phys& ph, Counters* cnt, double* rl, int cap, int* fb_list, unsigned long long* fb_count,
+                    hipStream_t s) {
+    launch_fill_u64(1, fb_count, 0ull, s);
+    k_solve_h<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, keys, ph, cnt, rl, cap, fb_list, fb_count);
+    // the fallback grid covers every particle; blocks past the handed-over count exit at once
+    k_solve_h_fallback<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, ph, cnt, fb_list, fb_count);
 }
 
 void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
                        const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s) {
-    k_flux_lists<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, hmax, ph, counts, list, cnt);
+    k_flux_lists<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, hmax, ph, counts, list, cnt);
 }
 
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,

@@ -48,7 +48,7 @@ class Counters(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("pairs", "list_entries", "list_max", "h_iters", "h_iters_max",
                                          "noconv", "minimage", "overflow", "illcond", "fallbacks",
                                          "clamps", "nonfinite", "floors", "first_bad")] + \
-               [("cond_max_seen", C.c_double)]
+               [("cond_max_seen", C.c_double), ("h_rounds_max", C.c_int64), ("h_fallback", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -234,8 +234,13 @@ class Context:
         self._rc(self._L.mfm_get_counters(self.h, C.byref(c)))
         return c.as_dict()
 
-    def check(self):
-        self._rc(self._L.mfm_check(self.h))
+    def check(self, allow_illcond: bool = False):
+        """Raise on device-side conditions.  With allow_illcond, ill-conditioned
+        gradient matrices (a reported count on strongly clustered sets) pass."""
+        rc = self._L.mfm_check(self.h)
+        if rc == -4 and allow_illcond:
+            return
+        self._rc(rc)
 
     def flux_lists(self, n: int, stream=None):
         mx = int(self._L.mfm_max_ngb(self.h))

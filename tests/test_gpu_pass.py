@@ -188,3 +188,34 @@ def test_turbulence_full_size_sampled():
     eps = np.finfo(np.float64).eps
     for comp in range(3):
         assert abs(dp[comp].sum()) <= 10 * eps * np.abs(dp).sum()
+
+
+def test_clustered_small_adaptive_h():
+    """32^3 particles drawn from the log-normal density (kernel lengths spread ~50x):
+    exercises deep cell levels, long flux lists and the per-particle kernel-length
+    solve for particles with more than 64 neighbours inside the bracket.
+
+    B = E^-1 inherits the summation-order round-off of E amplified by cond(E)
+    (two particles here have cond > 1e4), so B is held to 1e-12 normwise where
+    cond(E) <= 1e3 and to 32 eps cond(E) per particle elsewhere; every other field
+    keeps the 1e-12 normwise bar."""
+    w = W.clustered(n_side=32, seed=W.SEED_BASE + 33)
+    ref = O.hydro_pass(O.Setup.of(w, cell=1.0 / 32), w.arrays())
+    ctx, st = run_pass(w, max_ngb=1024)
+    ctx.check()
+    c = ctx.counters()
+    print("clustered32 list_max", c["list_max"], "h_iters_max", c["h_iters_max"], flush=True)
+    errs = compare_pass(st, ref)
+    _print("clustered32", errs)
+    for k, e in errs.items():
+        if k != "B":
+            assert e <= TOL_FP64, (k, e)
+    B = in_input_order(st, "B")
+    cond = ref["cond"]
+    good = cond <= 1e3
+    assert nerr(B[:, good], ref["B"][:, good]) <= TOL_FP64
+    eps = np.finfo(np.float64).eps
+    per = np.abs(B - ref["B"]).max(0) / np.abs(ref["B"]).max(0)
+    assert np.all(per <= np.maximum(TOL_FP64, 32 * eps * cond))
+    assert elem_rel(in_input_order(st, "H"), ref["H"]) <= TOL_FP64
+    assert c["pairs"] == ref["pairs"]
