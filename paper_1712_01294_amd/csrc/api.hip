@@ -17,13 +17,14 @@ struct mfm_ctx {
     int device = 0;
     TreeDesc td;
     Phys ph;
-    long long tab_len = 0, hmax_len = 0;
+    long long tab_len = 0;
     unsigned long long *keys = nullptr, *ktmp = nullptr;
     int *idx = nullptr, *vtmp = nullptr, *hist = nullptr, *scan_tmp = nullptr;
     unsigned long long* gtmp = nullptr;   // kGatherMax x cap staging for in-place reordering
     int2* tab = nullptr;
-    float* hmax = nullptr;
-    int *counts = nullptr, *list = nullptr;
+    double4* pos = nullptr;               // packed positions of the current order
+    double* rl = nullptr;                 // radii scratch of the kernel-length solve
+    int *counts = nullptr, *gcount = nullptr, *list = nullptr;
     int* fb_list = nullptr;               // particles handed to the per-particle kernel-length solve
     unsigned long long* fb_count = nullptr;
     void* rec = nullptr;                  // 32 x 8 B per particle
@@ -75,7 +76,7 @@ static void setup_tree(mfm_ctx* c) {
     }
     td.bmax = bmax;
     td.leaf = 8;
-    long long off = 0, hoff = 0;
+    long long off = 0;
     int k = 0;
     for (int l = 0; l <= bmax; l++) {
         int m = 0, nb = 0;
@@ -89,18 +90,25 @@ static void setup_tree(mfm_ctx* c) {
         td.nact[l] = nb;
         td.kbits[l] = k;
         td.tab_off[l] = off;
-        td.hmax_off[l] = hoff;
         off += 1ll << k;
-        hoff += 1ll << k;
         for (int d = 0; d < 3; d++) {
             int act = l - (bmax - td.qbits[d]);
             if (act < 0) act = 0;
             td.cs[l][d] = c->p.box[d] / (double)(1ll << act);
+            td.ncell[l][d] = 1 << act;
         }
+        // bit positions of each axis in the level-l key prefix: bits appended
+        // level by level, axes x, y, z in that order, the last one lowest
+        int pos = k;
+        for (int lev = 1; lev <= l; lev++)
+            for (int d = 0; d < 3; d++)
+                if (td.actmask[lev] & (1 << d)) {
+                    pos--;
+                    td.mask[l][d] |= 1ull << pos;
+                }
     }
     td.ktot = k;
     c->tab_len = off;
-    c->hmax_len = hoff;
 }
 
 extern "C" {
@@ -128,8 +136,8 @@ void mfm_destroy(mfm_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->hmax,
-                    c->counts, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
+    void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -176,8 +184,10 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->scan_tmp, sizeof(int) * scan_tmp_ints(hist_len > n ? hist_len : n), "scan tmp");
     alloc((void**)&c->gtmp, sizeof(unsigned long long) * n * kGatherMax, "gather staging");
     alloc((void**)&c->tab, sizeof(int2) * c->tab_len, "cell tables");
-    alloc((void**)&c->hmax, sizeof(float) * c->hmax_len, "cell hmax");
+    alloc((void**)&c->pos, sizeof(double4) * n, "packed positions");
+    alloc((void**)&c->rl, sizeof(double) * n * kRCap, "radius lists");
     alloc((void**)&c->counts, sizeof(int) * n, "list counts");
+    alloc((void**)&c->gcount, sizeof(int) * n, "gather counts");
     alloc((void**)&c->list, sizeof(int) * n * c->ph.max_ngb, "flux lists");
     alloc((void**)&c->fb_list, sizeof(int) * n, "fallback list");
     alloc((void**)&c->fb_count, sizeof(unsigned long long), "fallback count");
@@ -276,6 +286,7 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     launch_gather(n, gb, c->idx, s);
     launch_fill_u64(c->tab_len, (unsigned long long*)c->tab, 0ull, s);
     launch_tables(n, c->keys, c->td, c->tab, s);
+    launch_pos4(n, p->x, p->y, p->z, c->pos, s);
     c->n_tree = n;
     c->have_h = c->have_grad = 0;
     c->last = s;
@@ -292,12 +303,8 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->nk || !p->V) return fail(c, MFM_E_INVALID, "nk and V are required");
     if (c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_build_neighbours must run on these particles first");
     PassArrays a = arrays_of(p);
-    // the radius lists of the kernel-length solve live in the flux-list buffer,
-    // which is rebuilt right after: max_ngb int slots hold max_ngb / 2 doubles
-    launch_solve_h(a, c->td, c->tab, c->keys, c->ph, c->cnt, (double*)c->list, c->ph.max_ngb / 2, c->fb_list,
-                   c->fb_count, s);
-    launch_hmax(a.n, c->keys, c->td, c->tab, p->H, c->hmax, s);
-    launch_flux_lists(a, c->td, c->tab, c->hmax, c->ph, c->counts, c->list, c->cnt, s);
+    launch_solve_h(a, c->td, c->tab, c->keys, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
+                   c->fb_list, c->fb_count, s);
     c->have_h = 1;
     c->have_grad = 0;
     c->last = s;
@@ -310,7 +317,7 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!c->have_h || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_solve_h must run first");
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
-    launch_gradients(a, c->ph, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    launch_gradients(a, c->ph, c->gcount, c->list, c->rec_mixed, c->rec, c->cnt, s);
     c->have_grad = 1;
     c->last = s;
     return launched(c, "gradients");

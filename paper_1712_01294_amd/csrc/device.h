@@ -20,8 +20,9 @@ struct TreeDesc {
     int actmask[kMaxLevels];         // bit d set when axis d refines at level l
     int kbits[kMaxLevels];           // key-prefix bits of a level-l cell
     long long tab_off[kMaxLevels];   // offset of level l in the (start, end) table
-    long long hmax_off[kMaxLevels];  // offset of level l in the hmax table (l < bmax)
     double cs[kMaxLevels][3];        // cell side per axis at level l
+    int ncell[kMaxLevels][3];        // cells per axis at level l (a power of two)
+    unsigned long long mask[kMaxLevels][3];  // key-prefix bits of axis d at level l
     double box[3];
     int periodic[3];
     int qbits[3];                    // quantisation bits per axis
@@ -209,234 +210,79 @@ __device__ __forceinline__ double box_dist2(const TreeDesc& td, const double glo
     return s;
 }
 
-// ------------------------------------------------- wave-cooperative group walk
-// One wave (a block of 64 threads) walks the tree ONCE for its 64 Morton-
-// consecutive particles, split into kSub sub-groups of 8 consecutive lanes,
-// each with its own bounding box and search radius.  The walk goes level by
-// level: the lanes test up to 64 children of the current frontier in parallel
-// (one table load each) against every sub-group; a node carries the mask of
-// sub-groups that can reach it, accepted inner nodes form the next frontier,
-// accepted leaves become candidate ranges with their mask.  Pending ranges are
-// handed to `chunk` in batches; a lane tests only candidates whose mask holds
-// its own sub-group, so a sub-group with a large radius does not make the
-// other 56 lanes test its far candidates.
-constexpr int kSub = 8;         // sub-groups of 8 lanes per wave
-constexpr int kFront = 128;     // frontier nodes per level (more are scanned as ranges)
-constexpr int kRanges = 128;    // pending candidate ranges
+// ------------------------------------------------------- cell stencil scan
+// Each particle scans, on its own, the cells of one table level that overlap
+// the cube [x - R, x + R]: the finest level whose cells are at least
+// kStencilScale R wide, so a scan touches about (2 / kStencilScale + 1)^3
+// cells.  Lanes of a wave (Morton neighbours) run the same loop shape on
+// nearby cells, so there is no tree-shaped divergence.  Cell keys are stepped
+// with dilated-integer increments on the per-axis bit masks of the key; on a
+// periodic axis the increment past the last cell wraps to cell 0 by itself
+// (cells per axis are a power of two).
+constexpr double kStencilScale = 0.5;
 
-struct SubGroups {
-    double lo[kSub][3], hi[kSub][3];
-    double R[kSub];             // < 0: sub-group inactive
-};
-
-struct GroupWalk {
-    unsigned long long front[2][kFront];
-    unsigned int fmask[2][kFront];
-    int rs[kRanges], re[kRanges];
-    unsigned int rm[kRanges];
-    int pre[64];
-};
-
-// integer cell coordinates of the level-l cell with key prefix c
-__device__ __forceinline__ void coords_of(const TreeDesc& td, int l, unsigned long long c, int cc[3]) {
-    cc[0] = cc[1] = cc[2] = 0;
-    for (int lev = l; lev >= 1; lev--) {
-        const int m = td.actmask[lev];
-        const int bit = l - lev;
-        if (m & 4) {
-            cc[2] |= (int)(c & 1) << bit;
-            c >>= 1;
-        }
-        if (m & 2) {
-            cc[1] |= (int)(c & 1) << bit;
-            c >>= 1;
-        }
-        if (m & 1) {
-            cc[0] |= (int)(c & 1) << bit;
-            c >>= 1;
-        }
+// scatter the low bits of v into the set bits of mask (lowest first)
+__device__ __forceinline__ unsigned long long deposit_bits(unsigned v, unsigned long long mask) {
+    unsigned long long r = 0;
+    while (mask) {
+        const unsigned long long low = mask & (~mask + 1);
+        if (v & 1u) r |= low;
+        v >>= 1;
+        mask &= mask - 1;
     }
+    return r;
 }
 
-__device__ __forceinline__ unsigned long long lanes_below() {
-    const int lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+// key with the axis coordinate held in `mask` incremented by one
+__device__ __forceinline__ unsigned long long dilated_inc(unsigned long long k, unsigned long long mask) {
+    return (((k | ~mask) + 1) & mask) | (k & ~mask);
 }
 
-// min / max over the 8 lanes of a sub-group
-__device__ __forceinline__ double sub_min_d(double v) {
-#pragma unroll
-    for (int o = 4; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double sub_max_d(double v) {
-#pragma unroll
-    for (int o = 4; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Fill the sub-group boxes from the lanes' positions (inactive lanes pass
-// act = false) and radii R (lanes that need no candidates pass R < 0).
-__device__ __forceinline__ void set_subgroups(SubGroups& sg, bool act, const double xi[3], double R) {
-    const int lane = threadIdx.x & 63;
-    double lo[3], hi[3];
+template <typename Visit>
+__device__ __forceinline__ void stencil_scan(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3],
+                                             double R, Visit&& visit) {
+    int L = td.bmax;
+    while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < kStencilScale * R) L--;
+    int lo[3], cnt[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        lo[d] = sub_min_d(act ? xi[d] : INFINITY);
-        hi[d] = sub_max_d(act ? xi[d] : -INFINITY);
-    }
-    const double r = sub_max_d(act ? R : -1.0);
-    __syncthreads();
-    if ((lane & 7) == 0) {
-        const int s = lane >> 3;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            sg.lo[s][d] = lo[d];
-            sg.hi[s][d] = hi[d];
-        }
-        sg.R[s] = r;
-    }
-    __syncthreads();
-}
-
-// sub-groups whose box lies within their radius (or within `rnode` when that
-// is larger) of the node box [lo, hi); parent restricts the candidates
-__device__ __forceinline__ unsigned int subgroup_hits(const TreeDesc& td, const SubGroups& sg, unsigned int parent,
-                                                      const double lo[3], const double hi[3], double rnode) {
-    unsigned int m = 0;
-#pragma unroll
-    for (int s = 0; s < kSub; s++) {
-        if (!((parent >> s) & 1) || !(sg.R[s] >= 0.0)) continue;
-        const double r = fmax(sg.R[s], rnode);
-        if (box_dist2(td, sg.lo[s], sg.hi[s], lo, hi) < r * r) m |= 1u << s;
-    }
-    return m;
-}
-
-// Range of flattened position t in the current batch (pre[] = exclusive prefix
-// of the batch's range lengths); returns the particle index, sets the range.
-__device__ __forceinline__ int batch_candidate(const GroupWalk& g, int rs0, int nb, int t, int& k) {
-    int lo = 0, hi = nb - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (g.pre[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    k = rs0 + lo;
-    return g.rs[k] + (t - g.pre[lo]);
-}
-
-template <typename Chunk>
-__device__ __forceinline__ void group_flush(GroupWalk& g, int nr, Chunk&& chunk) {
-    const int lane = threadIdx.x & 63;
-    for (int b = 0; b < nr; b += 64) {
-        const int k = b + lane;
-        const int len = k < nr ? g.re[k] - g.rs[k] : 0;
-        int inc = len;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += t;
-        }
-        const int total = __shfl(inc, 63, 64);
-        const int nb = min(64, nr - b);
-        __syncthreads();
-        g.pre[lane] = inc - len;
-        __syncthreads();
-        chunk(b, nb, total);
-    }
-}
-
-// accept(l, c, lo, hi, parent_mask) -> mask of sub-groups that need the node
-template <typename Accept, typename Chunk>
-__device__ __forceinline__ void group_walk(const TreeDesc& td, const int2* __restrict__ tab, int n, int leaf,
-                                           GroupWalk& g, Accept&& accept, Chunk&& chunk) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lt = lanes_below();
-    const unsigned int all = (1u << kSub) - 1;
-    int nr = 0;
-    int cur = 0, nf = 0;
-    __syncthreads();
-    if (n <= leaf) {
-        if (lane == 0) {
-            g.rs[0] = 0;
-            g.re[0] = n;
-            g.rm[0] = all;
-        }
-        nr = 1;
-    } else {
-        if (lane == 0) {
-            g.front[0][0] = 0ull;
-            g.fmask[0][0] = all;
-        }
-        nf = 1;
-    }
-    __syncthreads();
-    for (int l = 0; l < td.bmax && nf > 0; l++) {
-        const int nb = td.nact[l + 1];
-        const int nch = nf << nb;
-        int nf2 = 0;
-        for (int base = 0; base < nch; base += 64) {
-            const int t = base + lane;
-            bool leaf_hit = false, inner_hit = false;
-            int2 se = make_int2(0, 0);
-            unsigned long long cchild = 0;
-            unsigned int mk = 0;
-            if (t < nch) {
-                const unsigned long long cp = g.front[cur][t >> nb];
-                const unsigned int pm = g.fmask[cur][t >> nb];
-                cchild = (cp << nb) | (unsigned long long)(t & ((1 << nb) - 1));
-                se = tab[td.tab_off[l + 1] + (long long)cchild];
-                if (se.y > se.x) {
-                    int cc[3];
-                    coords_of(td, l + 1, cchild, cc);
-                    double lo[3], hi[3];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) {
-                        lo[d] = cc[d] * td.cs[l + 1][d];
-                        hi[d] = lo[d] + td.cs[l + 1][d];
-                    }
-                    mk = accept(l + 1, cchild, lo, hi, pm);
-                    if (mk) {
-                        if (l + 1 == td.bmax || se.y - se.x <= leaf) leaf_hit = true;
-                        else inner_hit = true;
-                    }
-                }
+        const double s = td.cs[L][d];
+        const int nc = td.ncell[L][d];
+        int a = (int)floor((xi[d] - R) / s);
+        int b = (int)floor((xi[d] + R) / s);
+        if (td.periodic[d]) {
+            if (b - a + 1 >= nc) {
+                a = 0;
+                b = nc - 1;
             }
-            const unsigned long long mi = __ballot(inner_hit);
-            if (inner_hit) {
-                const int pos = nf2 + __popcll(mi & lt);
-                if (pos < kFront) {
-                    g.front[cur ^ 1][pos] = cchild;
-                    g.fmask[cur ^ 1][pos] = mk;
-                } else {
-                    leaf_hit = true;   // frontier full: scan the whole node
-                }
-            }
-            nf2 = min(kFront, nf2 + __popcll(mi));
-            const unsigned long long ml = __ballot(leaf_hit);
-            if (leaf_hit) {
-                const int pos = nr + __popcll(ml & lt);
-                g.rs[pos] = se.x;
-                g.re[pos] = se.y;
-                g.rm[pos] = mk;
-            }
-            nr += __popcll(ml);
-            if (nr >= 64) {
-                __syncthreads();
-                group_flush(g, nr, chunk);
-                nr = 0;
-            }
+            cnt[d] = b - a + 1;
+            a %= nc;
+            if (a < 0) a += nc;
+        } else {
+            if (a < 0) a = 0;
+            if (b > nc - 1) b = nc - 1;
+            cnt[d] = b - a + 1;
         }
-        __syncthreads();
-        cur ^= 1;
-        nf = nf2;
+        lo[d] = a;
     }
-    if (nr > 0) {
-        __syncthreads();
-        group_flush(g, nr, chunk);
+    if (cnt[0] <= 0 || cnt[1] <= 0 || cnt[2] <= 0) return;
+    const unsigned long long m0 = td.mask[L][0], m1 = td.mask[L][1], m2 = td.mask[L][2];
+    const long long off = td.tab_off[L];
+    unsigned long long kx = deposit_bits((unsigned)lo[0], m0) | deposit_bits((unsigned)lo[1], m1) |
+                            deposit_bits((unsigned)lo[2], m2);
+    for (int ix = 0; ix < cnt[0]; ix++) {
+        unsigned long long ky = kx;
+        for (int iy = 0; iy < cnt[1]; iy++) {
+            unsigned long long kz = ky;
+            for (int iz = 0; iz < cnt[2]; iz++) {
+                const int2 se = tab[off + (long long)kz];
+                for (int j = se.x; j < se.y; j++) visit(j);
+                kz = dilated_inc(kz, m2);
+            }
+            ky = dilated_inc(ky, m1);
+        }
+        kx = dilated_inc(kx, m0);
     }
-    __syncthreads();
 }
 
 // wave-wide min / max of doubles (all 64 lanes participate)

@@ -8,6 +8,7 @@
 namespace mfm {
 
 constexpr int kGatherMax = 20;
+constexpr int kRCap = 96;        // radii slots per particle in the kernel-length solve
 
 // up to kGatherMax arrays of 8-byte elements reordered by one launch: dst[i] = src[idx[i]]
 struct GatherBatch {
@@ -35,15 +36,12 @@ void launch_keys(int n, const double* x, const double* y, const double* z, const
 void launch_gather(int n, const GatherBatch& gb, const int* idx, hipStream_t s);
 void launch_fill_u64(long long m, unsigned long long* p, unsigned long long v, hipStream_t s);
 void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s);
-void launch_hmax(int n, const unsigned long long* keys, const TreeDesc& td, const int2* tab,
-                 const double* H, float* hmax, hipStream_t s);
+void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s);
 
 // pass.hip
-void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
-                    const unsigned long long* keys, const Phys& ph, Counters* cnt, double* rl, int cap,
-                    int* fb_list, unsigned long long* fb_count, hipStream_t s);
-void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
-                       const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s);
+void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
+                    const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
+                    int* counts, int* fb_list, unsigned long long* fb_count, hipStream_t s);
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
                       int mixed, void* rec, Counters* cnt, hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,

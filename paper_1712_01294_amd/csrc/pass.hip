@@ -60,12 +60,12 @@ __device__ __forceinline__ void displacement(const Phys& ph, const double xi[3],
 // ------------------------------------------------------------ kernel length
 // The root of (32/3) sum_j w(r_ij / H) = n_ngb is found per particle by
 // safeguarded Newton iterations on the radii r_ij < hi of a bracket (lo, hi].
-// The radii come from one group scan of the wave's 64 particles and are kept
-// in a global scratch list (rl[k * n + i], coalesced across the wave, resident
-// in L2 while the same wave iterates on it).  A lane whose trial radius holds
-// too few or too many neighbours adjusts it and the wave scans again; lanes
-// still without a bracket after a few rounds go to the per-particle fallback.
-constexpr int kGroupLeaf = 32;  // group walks stop descending at <= 32 particles
+// One stencil scan at a trial radius R collects the radii (rl) and indices
+// (jl) into interleaved global lists (rl[k * n + i], coalesced across a wave);
+// a lane whose R holds too few neighbours, or more than the list holds,
+// adjusts R and scans again.  Particles still without a bracket go to the
+// per-particle fallback.  After the root, the indices with r < H (self
+// excluded) are compacted in place: that is the gather part of the flux list.
 
 __device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, unsigned long long key,
                              double n_ngb) {
@@ -115,97 +115,58 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
     return false;
 }
 
-__global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
-                                                 const unsigned long long* __restrict__ keys, Phys ph,
-                                                 Counters* cnt, double* __restrict__ rl, int cap,
-                                                 int* __restrict__ fb_list,
-                                                 unsigned long long* __restrict__ fb_count) {
-    __shared__ double tx[64], ty[64], tz[64];
-    __shared__ unsigned int tm[64];
-    __shared__ GroupWalk gw;
-    __shared__ SubGroups sg;
-    const int lane = threadIdx.x;
-    const unsigned int mysub = 1u << (lane >> 3);
-    const int i = xcd_block() * 64 + lane;
+__global__ __launch_bounds__(256) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                  const unsigned long long* __restrict__ keys,
+                                                  const double4* __restrict__ pos, Phys ph, Counters* cnt,
+                                                  double* __restrict__ rl, int* __restrict__ jl,
+                                                  int* __restrict__ gcount, int* __restrict__ counts,
+                                                  int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count) {
+    const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
-    const long long n = a.n;
-    const double c32 = 32.0 / 3.0;
-    double xi[3] = {0.0, 0.0, 0.0};
-    double half = INFINITY;
-    for (int d = 0; d < 3; d++)
-        if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
-    double guess = 0.0;
-    bool warm = false;
-    if (act) {
-        xi[0] = a.x[i];
-        xi[1] = a.y[i];
-        xi[2] = a.z[i];
-        guess = a.H[i];
-        warm = guess > 0.0;
-        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
-    }
-    // per-lane bracket state
-    double lo = 0.0, hi = INFINITY;
-    double R = (warm ? 1.1 : 1.4) * guess;
-    bool done = !act, ok = false;
-    int m = 0;
-    double neff_hi = 0.0;
     unsigned long long iters = 0, rounds = 0;
-    for (int round = 0; round < 12; round++) {
-        bool need = !done;
-        if (need && !(R < half)) {
-            R = half * (1.0 - 1e-12);
-            if (!(R > lo)) {   // the root lies beyond half a periodic side
-                need = false;
-                done = true;
+    if (act) {
+        const long long n = a.n;
+        const int cap = min(kRCap, ph.max_ngb);
+        const double c32 = 32.0 / 3.0;
+        const double4 pi = pos[i];
+        const double xi[3] = {pi.x, pi.y, pi.z};
+        double half = INFINITY;
+        for (int d = 0; d < 3; d++)
+            if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+        double guess = a.H[i];
+        const bool warm = guess > 0.0;
+        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
+        double lo = 0.0, hi = INFINITY;
+        double R = (warm ? 1.1 : 1.4) * guess;
+        int m = 0;
+        double neff_hi = 0.0;
+        bool ok = false;
+        for (int round = 0; round < 12; round++) {
+            if (!(R < half)) {
+                R = half * (1.0 - 1e-12);
+                if (!(R > lo)) break;   // the root lies beyond half a periodic side
             }
-        }
-        if (!__any(need)) break;
-        set_subgroups(sg, act, xi, need ? R : -1.0);
-        const double R2 = R * R, iR = 1.0 / R;
-        double sw = 0.0;
-        if (need) {   // lanes already done keep their stored radii and count
-            m = 0;
             rounds++;
-        }
-        group_walk(
-            td, tab, a.n, kGroupLeaf, gw,
-            [&](int, unsigned long long, const double* nlo, const double* nhi, unsigned int pm) {
-                return subgroup_hits(td, sg, pm, nlo, nhi, 0.0);
-            },
-            [&](int rs0, int nb, int total) {
-                for (int base = 0; base < total; base += 64) {
-                    const int t = base + lane;
-                    if (t < total) {
-                        int k;
-                        const int j = batch_candidate(gw, rs0, nb, t, k);
-                        tx[lane] = a.x[j];
-                        ty[lane] = a.y[j];
-                        tz[lane] = a.z[j];
-                        tm[lane] = gw.rm[k];
-                    }
-                    __syncthreads();
-                    const int cnum = min(64, total - base);
-                    if (need) {
-                        for (int u = 0; u < cnum; u++) {
-                            if (!(tm[u] & mysub)) continue;
-                            double d[3];
-                            displacement(ph, xi, tx[u], ty[u], tz[u], d);
-                            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                            if (r2 < R2) {
-                                const double r = sqrt(r2);
-                                if (r < R) {
-                                    if (m < cap) rl[(long long)m * n + i] = r;
-                                    m++;
-                                    sw += spline_w(r * iR);
-                                }
-                            }
+            const double R2 = R * R, iR = 1.0 / R;
+            double sw = 0.0;
+            m = 0;
+            stencil_scan(td, tab, xi, R, [&](int j) {
+                const double4 pj = pos[j];
+                double d[3];
+                displacement(ph, xi, pj.x, pj.y, pj.z, d);
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 < R2) {
+                    const double r = sqrt(r2);
+                    if (r < R) {
+                        if (m < cap) {
+                            rl[(long long)m * n + i] = r;
+                            jl[(long long)m * n + i] = j;
                         }
+                        m++;
+                        sw += spline_w(r * iR);
                     }
-                    __syncthreads();
                 }
             });
-        if (need) {
             const double neff = c32 * sw;
             if (neff < ph.n_ngb) {
                 lo = R;
@@ -227,12 +188,10 @@ __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const
                 } else {
                     neff_hi = neff;
                     ok = true;
-                    done = true;
+                    break;
                 }
             }
         }
-    }
-    if (act) {
         bool conv = false;
         double Hc = 0.0;
         if (ok) {
@@ -243,11 +202,22 @@ __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const
         if (ok && conv) {
             double s = 0.0;
             const double iH = 1.0 / Hc;
-            for (int k = 0; k < m; k++) s += spline_w(rl[(long long)k * n + i] * iH);
+            int c = 0;
+            for (int k = 0; k < m; k++) {
+                const double r = rl[(long long)k * n + i];
+                s += spline_w(r * iH);
+                const int j = jl[(long long)k * n + i];
+                if (r < Hc && j != i) {
+                    jl[(long long)c * n + i] = j;
+                    c++;
+                }
+            }
             const double nk = kernel_norm(Hc) * s;
             a.H[i] = Hc;
             a.nk[i] = nk;
             a.V[i] = 1.0 / nk;
+            gcount[i] = c;
+            counts[i] = c;
         } else {
             // hand over to the per-particle solver, which starts from this bracket
             const unsigned long long slot = atomicAdd(fb_count, 1ull);
@@ -260,18 +230,21 @@ __global__ __launch_bounds__(64) void k_solve_h(PassArrays a, TreeDesc td, const
     count_max(&cnt->h_rounds_max, rounds);
 }
 
-// Per-particle solve for the few particles the group solve handed over: every
-// residual evaluation walks the tree again, so there is no limit on the number
-// of neighbours.  Bracket grows from H until it holds the root, then Newton
-// with bisection safeguard.
+// Per-particle solve for the few particles the stencil solve handed over:
+// every residual evaluation walks the tree again, so there is no limit on the
+// number of neighbours.  The bracket grows from H until it holds the root,
+// then Newton with bisection safeguard; a last walk writes the gather list.
 __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                           Phys ph, Counters* cnt, const int* __restrict__ fb_list,
-                                                          const unsigned long long* __restrict__ fb_count) {
+                                                          const unsigned long long* __restrict__ fb_count,
+                                                          int* __restrict__ jl, int* __restrict__ gcount,
+                                                          int* __restrict__ counts) {
     const unsigned long long nfb = *fb_count;
     const unsigned long long t = (unsigned long long)blockIdx.x * 64 + threadIdx.x;
     if (t == 0) cnt->h_fallback = nfb;
-    unsigned long long iters = 0, noconv = 0, noimg = 0;
+    unsigned long long iters = 0, noconv = 0, noimg = 0, over = 0;
     if (t < nfb && t < (unsigned long long)a.n) {
+        const long long n = a.n;
         const int i = fb_list[t];
         const double xi[3] = {a.x[i], a.y[i], a.z[i]};
         double half = INFINITY;
@@ -346,8 +319,34 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
                 }
             }
         }
-        if (ok && conv) eval(Hc, f, fp, nk);
-        else {
+        int c = 0;
+        if (ok && conv) {
+            eval(Hc, f, fp, nk);
+            const double H2 = Hc * Hc;
+            const int cap = ph.max_ngb;
+            tree_walk(
+                td, tab,
+                [&](int, unsigned long long, const double* nlo, const double* nhi) {
+                    return node_dist2(td, xi, nlo, nhi) < H2;
+                },
+                [&](int s0, int e0) {
+                    for (int j = s0; j < e0; j++) {
+                        if (j == i) continue;
+                        double d[3];
+                        displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
+                        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                        if (r < Hc) {
+                            if (c < cap) jl[(long long)c * n + i] = j;
+                            c++;
+                        }
+                    }
+                });
+            if (c > cap) {
+                c = cap;
+                over = 1;
+                flag_index(cnt, i);
+            }
+        } else {
             nk = 0.0;
             if (!ok) noimg = 1;
             else noconv = 1;
@@ -356,88 +355,68 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
         a.H[i] = Hc;
         a.nk[i] = nk;
         a.V[i] = 1.0 / nk;
+        gcount[i] = c;
+        counts[i] = c;
     }
     count_add(&cnt->h_iters, iters);
     count_max(&cnt->h_iters_max, iters);
     count_add(&cnt->noconv, noconv);
     count_add(&cnt->minimage, noimg);
+    count_add(&cnt->overflow, over);
 }
 
 // --------------------------------------------------------------- flux lists
-// list[k * n + i] = k-th j (walk order) with j != i and r_ij < max(H_i, H_j).
-// One group walk per wave; a node is opened when it is closer to the group box
-// than max(largest H of the group, largest H in the node).
-__global__ __launch_bounds__(64) void k_flux_lists(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
-                                                    const float* __restrict__ hmax, Phys ph,
-                                                    int* __restrict__ counts, int* __restrict__ list,
-                                                    Counters* cnt) {
-    __shared__ double tx[64], ty[64], tz[64], th[64];
-    __shared__ int tj[64];
-    __shared__ unsigned int tm[64];
-    __shared__ GroupWalk gw;
-    __shared__ SubGroups sg;
-    const int lane = threadIdx.x;
-    const unsigned int mysub = 1u << (lane >> 3);
-    const int i = xcd_block() * 64 + lane;
-    const bool act = i < a.n;
-    double xi[3] = {0.0, 0.0, 0.0};
-    double Hi = 0.0;
-    if (act) {
-        xi[0] = a.x[i];
-        xi[1] = a.y[i];
-        xi[2] = a.z[i];
-        Hi = a.H[i];
-    }
-    set_subgroups(sg, act, xi, act ? Hi : -1.0);
+// The flux set r < max(H_i, H_j) is the gather set of i plus every j that has
+// i in its gather set with r >= H_i.  Each j walks its own gather list and
+// appends itself to such i (atomic slot), then each list sorts its appended
+// tail by index so the list, and every sum over it, is deterministic.
+__global__ __launch_bounds__(256) void k_scatter_lists(PassArrays a, Phys ph, const double4* __restrict__ pos,
+                                                        const int* __restrict__ gcount, int* __restrict__ counts,
+                                                        int* __restrict__ list) {
+    const int j = xcd_block() * 256 + threadIdx.x;
+    if (j >= a.n) return;
     const long long n = a.n;
     const int cap = ph.max_ngb;
+    const double4 pj = pos[j];
+    const double xj[3] = {pj.x, pj.y, pj.z};
+    const int g = gcount[j];
+    for (int k = 0; k < g; k++) {
+        const int i = list[(long long)k * n + j];
+        const double4 p = pos[i];
+        double d[3];
+        displacement(ph, xj, p.x, p.y, p.z, d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(r < a.H[i])) {
+            const int slot = atomicAdd(&counts[i], 1);
+            if (slot < cap) list[(long long)slot * n + i] = j;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* __restrict__ gcount,
+                                                     int* __restrict__ counts, int* __restrict__ list,
+                                                     Counters* cnt) {
+    const int i = xcd_block() * 256 + threadIdx.x;
     unsigned long long c = 0, over = 0;
-    group_walk(
-        td, tab, a.n, kGroupLeaf, gw,
-        [&](int l, unsigned long long cc, const double* nlo, const double* nhi, unsigned int pm) {
-            return subgroup_hits(td, sg, pm, nlo, nhi, (double)hmax[td.hmax_off[l] + (long long)cc]);
-        },
-        [&](int rs0, int nb, int total) {
-            for (int base = 0; base < total; base += 64) {
-                const int t = base + lane;
-                if (t < total) {
-                    int k;
-                    const int j = batch_candidate(gw, rs0, nb, t, k);
-                    tx[lane] = a.x[j];
-                    ty[lane] = a.y[j];
-                    tz[lane] = a.z[j];
-                    th[lane] = a.H[j];
-                    tj[lane] = j;
-                    tm[lane] = gw.rm[k];
-                }
-                __syncthreads();
-                const int cnum = min(64, total - base);
-                if (act) {
-                    for (int u = 0; u < cnum; u++) {
-                        if (!(tm[u] & mysub)) continue;
-                        const int j = tj[u];
-                        double d[3];
-                        displacement(ph, xi, tx[u], ty[u], tz[u], d);
-                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        const double hm = fmax(Hi, th[u]);
-                        if (r2 < 1.0000001 * hm * hm && j != i) {
-                            const double r = sqrt(r2);
-                            if (r < Hi || r < th[u]) {
-                                if (c < (unsigned long long)cap) list[(long long)c * n + i] = j;
-                                c++;
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        });
-    if (act) {
-        if (c > (unsigned long long)cap) {
+    if (i < n) {
+        const int g = gcount[i];
+        int e = counts[i];
+        c = (unsigned long long)e;
+        if (e > cap) {
             over = 1;
             flag_index(cnt, i);
+            e = cap;
+            counts[i] = cap;
         }
-        counts[i] = (int)(c < (unsigned long long)cap ? c : cap);
+        for (int k = g + 1; k < e; k++) {
+            const int v = list[(long long)k * n + i];
+            int q = k - 1;
+            while (q >= g && list[(long long)q * n + i] > v) {
+                list[(long long)(q + 1) * n + i] = list[(long long)q * n + i];
+                q--;
+            }
+            list[(long long)(q + 1) * n + i] = v;
+        }
     }
     count_add(&cnt->list_entries, c);
     count_max(&cnt->list_max, c);
@@ -824,17 +803,16 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
 static int blocks_of(int n, int b) { return (n + b - 1) / b; }
 
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
-                    const Phys& ph, Counters* cnt, double* rl, int cap, int* fb_list, unsigned long long* fb_count,
-                    hipStream_t s) {
+                    const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
+                    int* counts, int* fb_list, unsigned long long* fb_count, hipStream_t s) {
     launch_fill_u64(1, fb_count, 0ull, s);
-    k_solve_h<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, keys, ph, cnt, rl, cap, fb_list, fb_count);
+    k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, keys, pos, ph, cnt, rl, list, gcount, counts,
+                                                  fb_list, fb_count);
     // the fallback grid covers every particle; blocks past the handed-over count exit at once
-    k_solve_h_fallback<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, ph, cnt, fb_list, fb_count);
-}
-
-void launch_flux_lists(const PassArrays& a, const TreeDesc& td, const int2* tab, const float* hmax,
-                       const Phys& ph, int* counts, int* list, Counters* cnt, hipStream_t s) {
-    k_flux_lists<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, hmax, ph, counts, list, cnt);
+    k_solve_h_fallback<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, ph, cnt, fb_list, fb_count, list, gcount,
+                                                          counts);
+    k_scatter_lists<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, pos, gcount, counts, list);
+    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
 }
 
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,

@@ -240,38 +240,11 @@ __global__ void k_tables(int n, const unsigned long long* __restrict__ keys, Tre
     }
 }
 
-// Max kernel length per cell, for the flux-set walk: levels bmax..0, bottom up.
-__global__ void k_hmax_leaf(int n, const unsigned long long* __restrict__ keys, TreeDesc td,
-                            const int2* __restrict__ tab, const double* __restrict__ H,
-                            float* __restrict__ hmax) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int l = td.bmax;
-    if (keys[k] >> td.ktot) return;
-    unsigned long long c = keys[k] >> (td.ktot - td.kbits[l]);
-    int2 se = tab[td.tab_off[l] + (long long)c];
-    if (se.x != k || se.y > n) return;
-    double h = 0.0;
-    for (int j = se.x; j < se.y; j++) h = fmax(h, H[j]);
-    hmax[td.hmax_off[l] + (long long)c] = __double2float_ru(h);
-}
-
-__global__ void k_hmax_level(int n, const unsigned long long* __restrict__ keys, TreeDesc td, int l,
-                             const int2* __restrict__ tab, float* __restrict__ hmax) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    if (keys[k] >> td.ktot) return;
-    unsigned long long c = keys[k] >> (td.ktot - td.kbits[l]);
-    int2 se = tab[td.tab_off[l] + (long long)c];
-    if (se.x != k) return;
-    int nb = td.nact[l + 1];
-    float h = 0.0f;
-    for (int ch = 0; ch < (1 << nb); ch++) {
-        unsigned long long cc = (c << nb) | (unsigned long long)ch;
-        int2 s2 = tab[td.tab_off[l + 1] + (long long)cc];
-        if (s2.y > s2.x) h = fmaxf(h, hmax[td.hmax_off[l + 1] + (long long)cc]);
-    }
-    hmax[td.hmax_off[l] + (long long)c] = h;
+// positions packed per particle for the neighbour scans (one 32-byte load)
+__global__ void k_pos4(int n, const double* __restrict__ x, const double* __restrict__ y,
+                       const double* __restrict__ z, double4* __restrict__ pos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos[i] = make_double4(x[i], y[i], z[i], 0.0);
 }
 
 void launch_keys(int n, const double* x, const double* y, const double* z, const TreeDesc& td,
@@ -294,11 +267,8 @@ void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, in
     k_tables<<<(n + 255) / 256, 256, 0, s>>>(n, keys, td, tab);
 }
 
-void launch_hmax(int n, const unsigned long long* keys, const TreeDesc& td, const int2* tab,
-                 const double* H, float* hmax, hipStream_t s) {
-    k_hmax_leaf<<<(n + 255) / 256, 256, 0, s>>>(n, keys, td, tab, H, hmax);
-    for (int l = td.bmax - 1; l >= 0; l--)
-        k_hmax_level<<<(n + 255) / 256, 256, 0, s>>>(n, keys, td, l, tab, hmax);
+void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s) {
+    k_pos4<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, z, pos);
 }
 
 }  // namespace mfm
