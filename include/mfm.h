@@ -170,6 +170,30 @@ mfm_status mfm_hydro_pass(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * synchronises the stream.  *dt_used (nullable, host) receives the step. */
 mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, void *stream);
 
+/* Adjoint of the pass (reading R20): given the adjoints adj_dp (3 x n) and
+ * adj_dE (n) of the pass outputs, write the adjoints of its inputs adj_x
+ * (3 x n), adj_v (3 x n) and adj_u (n) = (dF/d(x, v, u))^T (adj_dp, adj_dE),
+ * FP64, at fixed neighbour sets.  The kernel length enters by the
+ * implicit-function theorem; limiter, Davis speeds, P* clamp and first-order
+ * fallback follow the branch the forward took.  Requires that the last pass
+ * on this context ran on p (its outputs nk, V, B, rho, P, grad are read).
+ * All arrays are device memory in p's current order.  The first adjoint call
+ * on a context allocates its adjoint scratch (56 doubles per particle). */
+mfm_status mfm_hydro_pass_adjoint(mfm_ctx *ctx, const mfm_particles *p, const double *adj_dp,
+                                  const double *adj_dE, double *adj_x, double *adj_v, double *adj_u,
+                                  void *stream);
+
+/* Adjoint of one fixed-dt mfm_step (reading R17/R20).  ckpt holds the state
+ * at the start of the step (x, y, z, m, vx, vy, vz, u, H and its pass outputs
+ * dp, dE; read only); work is a scratch particle set of the same size (every
+ * array present) on which the step is recomputed.  On input the adjoint
+ * arrays hold the adjoints of the state after the step (x, v, u, dp, dE) in
+ * the order mfm_step leaves it; on output they hold the adjoints of the
+ * checkpoint's state in the checkpoint's order.  dt must be > 0. */
+mfm_status mfm_step_adjoint(mfm_ctx *ctx, const mfm_particles *ckpt, mfm_particles *work, double dt,
+                            double *adj_x, double *adj_v, double *adj_u, double *adj_dp, double *adj_dE,
+                            void *stream);
+
 /* Synchronise the stream of the last call and report device counters. */
 mfm_status mfm_get_counters(mfm_ctx *ctx, mfm_counters *out);
 

@@ -1,0 +1,112 @@
+"""Differentiable multi-step MFM evolution: torch.autograd.Function over the
+library's fixed-dt kick-drift-kick steps, with the hand-written adjoint.
+
+Forward runs the initial pass and k steps on the GPU and keeps one checkpoint
+of the state per step (positions, velocities, energies, kernel lengths and the
+pass outputs dp, dE).  Backward walks the steps from last to first: each
+mfm_step_adjoint recomputes its step from the checkpoint and applies the
+reverse step; the initial pass is reversed last with mfm_hydro_pass_adjoint.
+Only v and u of the initial state are differentiable inputs; positions and
+masses are fixed data.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import mfm
+
+_CK = ("x", "y", "z", "m", "vx", "vy", "vz", "u", "H", "dp", "dE", "id")
+
+
+def _copy_state(dst: mfm.State, src: mfm.State):
+    for k in _CK:
+        getattr(dst, k).copy_(getattr(src, k))
+
+
+class Evolution:
+    """Fixed data of one differentiable run: positions, masses, parameters."""
+
+    def __init__(self, w, steps: int, dt: float, cfg: mfm.Config | None = None):
+        self.w = w
+        self.steps = int(steps)
+        self.dt = float(dt)
+        self.cfg = cfg or mfm.config_of(w)
+        self.ctx = mfm.Context(self.cfg, w.n)
+        self.n = w.n
+
+    def _state(self):
+        return mfm.State(self.n)
+
+    def run(self, v0: torch.Tensor, u0: torch.Tensor, keep: bool):
+        """Forward; v0 (3, n) and u0 (n) in the input order.  Returns the final
+        state (library order) and the checkpoints if keep."""
+        st = mfm.State.from_arrays(self.w.arrays())
+        st.vx.copy_(v0[0])
+        st.vy.copy_(v0[1])
+        st.vz.copy_(v0[2])
+        st.u.copy_(u0)
+        self.ctx.build_neighbours(st)
+        self.ctx.hydro_pass(st)
+        cks = []
+        for _ in range(self.steps):
+            if keep:
+                ck = self._state()
+                _copy_state(ck, st)
+                cks.append(ck)
+            self.ctx.step(st, self.dt)
+        return st, cks
+
+
+class MFMSteps(torch.autograd.Function):
+    """(v0 (3, n), u0 (n)) -> (v_k (3, n), u_k (n)) after k fixed-dt steps, both
+    in the input order, differentiable through the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, v0, u0, evo: Evolution):
+        st, cks = evo.run(v0.detach(), u0.detach(), keep=True)
+        ids = st.id
+        vk = torch.empty_like(v0)
+        uk = torch.empty_like(u0)
+        vk[:, ids] = torch.stack([st.vx, st.vy, st.vz])
+        uk[ids] = st.u
+        ctx.evo = evo
+        ctx.cks = cks
+        ctx.final_ids = ids.clone()
+        return vk, uk
+
+    @staticmethod
+    def backward(ctx, gv, gu):
+        evo = ctx.evo
+        n = evo.n
+        f = dict(dtype=torch.float64, device="cuda")
+        ids = ctx.final_ids
+        gv = torch.zeros(3, n, **f) if gv is None else gv.contiguous()
+        gu = torch.zeros(n, **f) if gu is None else gu.contiguous()
+        # adjoints in the library order of the final state
+        ax = torch.zeros(3, n, **f)
+        av = gv[:, ids].contiguous()
+        au = gu[ids].contiguous()
+        ap = torch.zeros(3, n, **f)
+        ae = torch.zeros(n, **f)
+        work = mfm.State(n)
+        for ck in reversed(ctx.cks):
+            evo.ctx.step_adjoint(ck, work, evo.dt, ax, av, au, ap, ae)
+        # the initial pass produced (dp, dE) of the first state: reverse it
+        st0 = mfm.State(n)
+        first = ctx.cks[0] if ctx.cks else None
+        if first is None:
+            raise RuntimeError("MFMSteps needs at least one step")
+        _copy_state(st0, first)
+        evo.ctx.build_neighbours(st0)
+        evo.ctx.hydro_pass(st0)
+        fx, fv, fu = evo.ctx.pass_adjoint(st0, ap, ae)
+        # st0 keeps the checkpoint order (it is already sorted), so the adjoints line up
+        av = av + fv
+        au = au + fu
+        ids0 = st0.id
+        g_v0 = torch.empty(3, n, **f)
+        g_u0 = torch.empty(n, **f)
+        g_v0[:, ids0] = av
+        g_u0[ids0] = au
+        ctx.cks = None
+        return g_v0, g_u0, None

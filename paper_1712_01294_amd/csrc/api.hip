@@ -31,6 +31,7 @@ struct mfm_ctx {
     double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
     double *dt_part = nullptr, *dt_out = nullptr;
     Counters* cnt = nullptr;
+    double* adj = nullptr;                // adjoint scratch, kAdjSlots x cap, allocated on first use
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
@@ -137,7 +138,7 @@ void mfm_destroy(mfm_ctx* c) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -484,3 +485,119 @@ mfm_status mfm_copy_flux_lists(mfm_ctx* c, int32_t* counts, int32_t* list, void*
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ adjoints
+static const int kAdjSlots = 56;   // doubles per particle of adjoint scratch
+
+static mfm_status ensure_adj(mfm_ctx* c) {
+    if (c->adj) return MFM_OK;
+    return hip_check(c, hipMalloc((void**)&c->adj, sizeof(double) * kAdjSlots * c->cap), "adjoint scratch");
+}
+
+extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p, const double* adj_dp,
+                                             const double* adj_dE, double* adj_x, double* adj_v, double* adj_u,
+                                             void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (!adj_dp || !adj_dE || !adj_x || !adj_v || !adj_u) return fail(c, MFM_E_INVALID, "null adjoint array");
+    if (!p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
+        return fail(c, MFM_E_INVALID, "the pass adjoint needs the forward outputs nk, V, B, rho, P, grad");
+    if (!c->have_flux || c->n_tree != p->n)
+        return fail(c, MFM_E_STATE, "the pass adjoint needs the pass of this state on this context");
+    hipSetDevice(c->device);
+    if ((st = ensure_adj(c))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    PassArrays a = arrays_of(p);
+    launch_pass_adjoint(a, c->ph, c->counts, c->gcount, c->list, adj_dp, adj_dE, c->adj, adj_x, adj_v, adj_u, s);
+    c->last = s;
+    return launched(c, "hydro_pass_adjoint");
+}
+
+extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_particles* w, double dt,
+                                       double* adj_x, double* adj_v, double* adj_u, double* adj_dp, double* adj_dE,
+                                       void* stream) {
+    mfm_status st = check_particles(c, ck);
+    if (st) return st;
+    if ((st = check_particles(c, w))) return st;
+    if (w->n != ck->n) return fail(c, MFM_E_INVALID, "checkpoint and work sets differ in size");
+    if (!(dt > 0.0)) return fail(c, MFM_E_INVALID, "the step adjoint needs a fixed dt > 0");
+    if (!ck->dp || !ck->dE) return fail(c, MFM_E_INVALID, "the checkpoint needs dp and dE of its state");
+    if (!w->dp || !w->dE || !w->vsig || !w->nk || !w->V || !w->B || !w->rho || !w->P || !w->grad)
+        return fail(c, MFM_E_INVALID, "the work set needs every pass output array");
+    if (!adj_x || !adj_v || !adj_u || !adj_dp || !adj_dE) return fail(c, MFM_E_INVALID, "null adjoint array");
+    hipSetDevice(c->device);
+    if ((st = ensure_adj(c))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = ck->n;
+    // 1. forward recompute of the step from the checkpoint, on the work set
+    auto cp = [&](double* dst, const double* src, long long len) {
+        hipMemcpyAsync(dst, src, sizeof(double) * len, hipMemcpyDeviceToDevice, s);
+    };
+    cp(w->x, ck->x, n);
+    cp(w->y, ck->y, n);
+    cp(w->z, ck->z, n);
+    cp(w->m, ck->m, n);
+    cp(w->vx, ck->vx, n);
+    cp(w->vy, ck->vy, n);
+    cp(w->vz, ck->vz, n);
+    cp(w->u, ck->u, n);
+    cp(w->H, ck->H, n);
+    cp(w->dp, ck->dp, 3 * n);
+    cp(w->dE, ck->dE, n);
+    if (w->id && ck->id) hipMemcpyAsync(w->id, ck->id, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s);
+    reset_counters(c, s);
+    PassArrays a = arrays_of(w);
+    launch_kick_drift(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, s);
+    double* extra[5] = {c->vp, c->vp + n, c->vp + 2 * n, c->up, c->Ehalf};
+    if ((st = build(c, w, s, extra, 5))) return st;
+    mfm_particles q = *w;
+    q.vx = c->vp;
+    q.vy = c->vp + n;
+    q.vz = c->vp + 2 * n;
+    q.u = c->up;
+    if ((st = do_solve_h(c, &q, s))) return st;
+    if ((st = do_gradients(c, &q, s))) return st;
+    if ((st = do_fluxes(c, &q, s))) return st;
+    // 2. reverse, in the recomputed order
+    double* A = c->adj;
+    double* lxF = A + 28 * n;
+    double* lvp = A + 31 * n;
+    double* lup = A + 34 * n;
+    double* lp2 = A + 35 * n;
+    double* le2 = A + 38 * n;
+    double* lv1 = A + 39 * n;
+    double* lE1 = A + 42 * n;
+    double* olx = A + 43 * n;
+    double* olv = A + 46 * n;
+    double* olu = A + 49 * n;
+    double* olp = A + 50 * n;
+    double* ole = A + 53 * n;
+    double* olE0 = A + 54 * n;
+    double* lE0 = A + 55 * n;
+    launch_step_rev1((int)n, w->m, w->vx, w->vy, w->vz, c->Ehalf, w->dp, w->dE, dt, c->p.u_floor, adj_x, adj_v,
+                     adj_u, adj_dp, adj_dE, lp2, le2, lv1, lE1, s);
+    PassArrays qa = arrays_of(&q);
+    launch_pass_adjoint(qa, c->ph, c->counts, c->gcount, c->list, lp2, le2, A, lxF, lvp, lup, s);
+    launch_step_rev2((int)n, w->m, c->vp, c->up, dt, c->p.u_floor, adj_x, lxF, lvp, lup, lv1, lE1, olx, olv, olu, olp,
+                     ole, olE0, s);
+    // 3. back to the checkpoint's order, then the v-dependent energy term
+    GatherBatch gb;
+    gb.count = 0;
+    auto add = [&](const double* src, double* dst) {
+        gb.src[gb.count] = (const unsigned long long*)src;
+        gb.dst[gb.count] = (unsigned long long*)dst;
+        gb.count++;
+    };
+    for (int k = 0; k < 3; k++) {
+        add(olx + k * n, adj_x + k * n);
+        add(olv + k * n, adj_v + k * n);
+        add(olp + k * n, adj_dp + k * n);
+    }
+    add(olu, adj_u);
+    add(ole, adj_dE);
+    add(olE0, lE0);
+    launch_unpermute((int)n, gb, c->idx, s);
+    launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
+    c->last = s;
+    return launched(c, "step_adjoint");
+}

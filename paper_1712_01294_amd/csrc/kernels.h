@@ -56,4 +56,20 @@ void launch_dt_min(int n, const double* H, const double* vsig, double* partial, 
                    double* out, hipStream_t s);
 int dt_min_parts(int n);
 
+// adjoint.hip
+void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts, const int* gcount,
+                         const int* list, const double* lam_dp, const double* lam_dE, double* scratch,
+                         double* out_x, double* out_v, double* out_u, hipStream_t s);
+void launch_step_rev1(int n, const double* m, const double* v1x, const double* v1y, const double* v1z,
+                      const double* Ehalf, const double* dp2, const double* dE2, double dt, double u_floor,
+                      const double* lx, const double* lv, const double* lu, const double* lp, const double* le,
+                      double* lam_p2, double* lam_e2, double* lv1, double* lE1, hipStream_t s);
+void launch_step_rev2(int n, const double* m, const double* vp, const double* up, double dt, double u_floor,
+                      const double* lx2, const double* lxF, const double* lvp, const double* lup, const double* lv1,
+                      const double* lE1, double* out_lx, double* out_lv, double* out_lu, double* out_lp,
+                      double* out_le, double* out_lE0, hipStream_t s);
+void launch_step_rev3(int n, const double* m, const double* vx, const double* vy, const double* vz,
+                      const double* lE0, double* lv, hipStream_t s);
+void launch_unpermute(int n, const GatherBatch& gb, const int* idx, hipStream_t s);
+
 }  // namespace mfm

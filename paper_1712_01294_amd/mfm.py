@@ -23,7 +23,7 @@ STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV",
 EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "mfm_gradients",
            "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
-           "mfm_hydro_fluxes_adjoint", "mfm_step_adjoint")
+           "mfm_hydro_pass_adjoint", "mfm_step_adjoint")
 
 
 class Params(C.Structure):
@@ -87,9 +87,9 @@ def lib() -> C.CDLL:
         L.mfm_status_str.restype = C.c_char_p
         L.mfm_last_error.argtypes = [vp]
         L.mfm_last_error.restype = C.c_char_p
-        if hasattr(L, "mfm_hydro_fluxes_adjoint"):
-            L.mfm_hydro_fluxes_adjoint.argtypes = [vp, C.POINTER(Particles), vp, vp, vp, vp, vp, vp]
-            L.mfm_step_adjoint.argtypes = [vp, C.POINTER(Particles), C.c_double, vp, vp, vp, vp]
+        L.mfm_hydro_pass_adjoint.argtypes = [vp, C.POINTER(Particles), vp, vp, vp, vp, vp, vp]
+        L.mfm_step_adjoint.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.c_double, vp, vp, vp,
+                                       vp, vp, vp]
         _lib = L
     return _lib
 
@@ -228,6 +228,26 @@ class Context:
         used = C.c_double(0.0)
         self._rc(self._L.mfm_step(self.h, C.byref(p), C.c_double(dt), C.byref(used), _stream(stream)))
         return used.value
+
+    def pass_adjoint(self, st: State, adj_dp, adj_dE, stream=None):
+        """(dF/d(x, v, u))^T (adj_dp, adj_dE) for the pass last run on st;
+        returns adj_x (3, n), adj_v (3, n), adj_u (n) in st's order."""
+        n = st.n
+        f = dict(dtype=torch.float64, device="cuda")
+        ax, av, au = torch.empty(3, n, **f), torch.empty(3, n, **f), torch.empty(n, **f)
+        p = st.struct()
+        v = lambda t: C.c_void_p(t.data_ptr())
+        self._rc(self._L.mfm_hydro_pass_adjoint(self.h, C.byref(p), v(adj_dp.contiguous()),
+                                                v(adj_dE.contiguous()), v(ax), v(av), v(au), _stream(stream)))
+        return ax, av, au
+
+    def step_adjoint(self, ckpt: State, work: State, dt: float, ax, av, au, ap, ae, stream=None):
+        """In place: adjoints of the state after one fixed-dt step (in the order the
+        step produced) -> adjoints of the checkpointed state (in its order)."""
+        pc, pw = ckpt.struct(), work.struct()
+        v = lambda t: C.c_void_p(t.data_ptr())
+        self._rc(self._L.mfm_step_adjoint(self.h, C.byref(pc), C.byref(pw), C.c_double(dt), v(ax), v(av), v(au),
+                                          v(ap), v(ae), _stream(stream)))
 
     def counters(self) -> dict:
         c = Counters()
