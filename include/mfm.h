@@ -112,6 +112,7 @@ typedef struct {
     double cond_max_seen;    /* largest ||E||_F ||B||_F                             */
     int64_t h_rounds_max;    /* most neighbour scans one kernel-length solve needed */
     int64_t h_fallback;      /* particles solved one by one (very long gather sets) */
+    int64_t h_rounds3;       /* particles whose solve needed three or more scans    */
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:

@@ -304,7 +304,7 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->nk || !p->V) return fail(c, MFM_E_INVALID, "nk and V are required");
     if (c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_build_neighbours must run on these particles first");
     PassArrays a = arrays_of(p);
-    launch_solve_h(a, c->td, c->tab, c->keys, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
+    launch_solve_h(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
                    c->fb_list, c->fb_count, s);
     c->have_h = 1;
     c->have_grad = 0;
@@ -434,6 +434,7 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     out->cond_max_seen = cm;
     out->h_rounds_max = (int64_t)h.h_rounds_max;
     out->h_fallback = (int64_t)h.h_fallback;
+    out->h_rounds3 = (int64_t)h.h_rounds3;
     return MFM_OK;
 }
 

@@ -58,30 +58,29 @@ struct Counters {
     unsigned long long cond_bits;    // max of the positive double cond, as bits
     unsigned long long h_rounds_max; // most group scans a kernel-length solve needed
     unsigned long long h_fallback;   // particles solved by the per-particle kernel
+    unsigned long long h_rounds3;    // particles that needed three or more scans
 };
 
 // ---------------------------------------------------------------- kernel
 // Cubic spline with support radius H: W = 8/(pi H^3) w(q), q = r/H,
 // w = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1), 0 beyond.
+// Both branches are evaluated and one is selected, so lanes of a wave with q
+// on different pieces do not diverge; the arithmetic of each piece is as written.
 template <typename T>
 __device__ __forceinline__ T spline_w(T q) {
-    if (q <= T(0.5)) return T(1) + q * q * (T(6) * q - T(6));
-    if (q <= T(1)) {
-        T t = T(1) - q;
-        return T(2) * t * t * t;
-    }
-    return T(0);
+    const T t = T(1) - q;
+    const T inner = T(1) + q * q * (T(6) * q - T(6));
+    const T outer = T(2) * t * t * t;
+    return q <= T(0.5) ? inner : (q <= T(1) ? outer : T(0));
 }
 
 // q * dw/dq
 template <typename T>
 __device__ __forceinline__ T spline_qdw(T q) {
-    if (q <= T(0.5)) return q * q * (T(18) * q - T(12));
-    if (q <= T(1)) {
-        T t = T(1) - q;
-        return T(-6) * q * t * t;
-    }
-    return T(0);
+    const T t = T(1) - q;
+    const T inner = q * q * (T(18) * q - T(12));
+    const T outer = T(-6) * q * t * t;
+    return q <= T(0.5) ? inner : (q <= T(1) ? outer : T(0));
 }
 
 template <typename T>
@@ -210,16 +209,22 @@ __device__ __forceinline__ double box_dist2(const TreeDesc& td, const double glo
     return s;
 }
 
-// ------------------------------------------------------- cell stencil scan
-// Each particle scans, on its own, the cells of one table level that overlap
-// the cube [x - R, x + R]: the finest level whose cells are at least
-// kStencilScale R wide, so a scan touches about (2 / kStencilScale + 1)^3
-// cells.  Lanes of a wave (Morton neighbours) run the same loop shape on
-// nearby cells, so there is no tree-shaped divergence.  Cell keys are stepped
-// with dilated-integer increments on the per-axis bit masks of the key; on a
-// periodic axis the increment past the last cell wraps to cell 0 by itself
-// (cells per axis are a power of two).
-constexpr double kStencilScale = 0.5;
+// ------------------------------------------------- wave-cooperative cell scan
+// A group of lanes (Morton neighbours with similar trial radii) scans the union
+// of their neighbourhoods together: the cells of one table level whose boxes
+// come within Rq of the group's bounding box, on the finest level whose cells
+// are at least kScanScale Rq wide.  Cells are taken 64 at a time, one per lane
+// (key, table entry, periodic image); their particles are then staged 64 at a
+// time in LDS with coalesced loads, already moved to the periodic image next to
+// the group, and every lane tests each staged particle against its own sphere.
+// The loop structure is the same for all lanes, so the wave never diverges on
+// cell or particle counts and no lane waits on a dependent gather of its own.
+// Cell keys come from per-axis cell coordinates deposited into the key bits of
+// that axis (cells per axis are a power of two).
+#ifndef MFM_SCAN_SCALE
+#define MFM_SCAN_SCALE 0.35
+#endif
+constexpr double kScanScale = MFM_SCAN_SCALE;
 
 // scatter the low bits of v into the set bits of mask (lowest first)
 __device__ __forceinline__ unsigned long long deposit_bits(unsigned v, unsigned long long mask) {
@@ -233,56 +238,181 @@ __device__ __forceinline__ unsigned long long deposit_bits(unsigned v, unsigned 
     return r;
 }
 
-// key with the axis coordinate held in `mask` incremented by one
-__device__ __forceinline__ unsigned long long dilated_inc(unsigned long long k, unsigned long long mask) {
-    return (((k | ~mask) + 1) & mask) | (k & ~mask);
+// per-wave LDS of the cooperative scan
+struct ScanLds {
+    double4 cand[kWave];    // staged particles: image position, index bits in w
+    int excl[kWave];        // exclusive prefix of the batch cells' particle counts
+    int start[kWave];       // first particle of each batch cell
+    double sh[3][kWave];    // periodic image shift of each batch cell
+};
+
+// order the LDS traffic of one wave (lanes read what other lanes wrote)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename Visit>
-__device__ __forceinline__ void stencil_scan(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3],
-                                             double R, Visit&& visit) {
+// Tests every particle of every cell within Rq of the box [bmin, bmax] against
+// the calling lane's sphere |x - xi|^2 < R2 (lanes with sel false take no
+// hits) and calls hit(j, r2) for each particle inside, in the order the cells
+// are scanned.  Staged positions are moved to the periodic image next to the
+// box; an axis that the scan spans whole (bit d of `wrap`) takes the minimum
+// image per displacement instead.  bmin, bmax and Rq must be uniform over the
+// wave, with Rq below half of every periodic side.  Each batch of 64 staged
+// particles is first tested without branches into a 64-bit mask per lane, so
+// the tests of neighbouring particles overlap, and the lane then walks its
+// set bits.
+__device__ __forceinline__ double sq_disp(const double4& q, const double xi[3], int wrap, const double box[3]) {
+    double d0 = q.x - xi[0], d1 = q.y - xi[1], d2 = q.z - xi[2];
+    if (wrap) {
+        d0 = min_image(d0, box[0], wrap & 1);
+        d1 = min_image(d1, box[1], wrap & 2);
+        d2 = min_image(d2, box[2], wrap & 4);
+    }
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+template <bool kWrap>
+__device__ __forceinline__ unsigned long long batch_mask(const ScanLds& S, int nb, const double xi[3], double R2,
+                                                         int wrap, const double box[3]) {
+    unsigned long long mk = 0;
+    for (int k0 = 0; k0 < nb; k0 += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const double r2 = sq_disp(S.cand[k0 + k], xi, kWrap ? wrap : 0, box);
+            mk |= (r2 < R2 ? 1ull : 0ull) << (k0 + k);
+        }
+    }
+    return mk;
+}
+
+template <typename Hit>
+__device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __restrict__ tab,
+                                           const double4* __restrict__ pos, ScanLds& S, int lane,
+                                           const double bmin[3], const double bmax[3], double Rq,
+                                           const double xi[3], double R2, bool sel, Hit&& hit) {
     int L = td.bmax;
-    while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < kStencilScale * R) L--;
-    int lo[3], cnt[3];
+    while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < kScanScale * Rq) L--;
+    L = __builtin_amdgcn_readfirstlane(L);
+    int a[3], cnt[3], nc[3];
+    int wrap = 0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const double s = td.cs[L][d];
-        const int nc = td.ncell[L][d];
-        int a = (int)floor((xi[d] - R) / s);
-        int b = (int)floor((xi[d] + R) / s);
+        nc[d] = td.ncell[L][d];
+        int lo = (int)floor((bmin[d] - Rq) / s);
+        int hi = (int)floor((bmax[d] + Rq) / s);
         if (td.periodic[d]) {
-            if (b - a + 1 >= nc) {
-                a = 0;
-                b = nc - 1;
+            if (hi - lo + 1 >= nc[d]) {
+                lo = 0;
+                hi = nc[d] - 1;
+                wrap |= 1 << d;
             }
-            cnt[d] = b - a + 1;
-            a %= nc;
-            if (a < 0) a += nc;
         } else {
-            if (a < 0) a = 0;
-            if (b > nc - 1) b = nc - 1;
-            cnt[d] = b - a + 1;
+            lo = max(lo, 0);
+            hi = min(hi, nc[d] - 1);
         }
-        lo[d] = a;
+        a[d] = __builtin_amdgcn_readfirstlane(lo);
+        cnt[d] = __builtin_amdgcn_readfirstlane(hi - lo + 1);
     }
+    wrap = __builtin_amdgcn_readfirstlane(wrap);
     if (cnt[0] <= 0 || cnt[1] <= 0 || cnt[2] <= 0) return;
-    const unsigned long long m0 = td.mask[L][0], m1 = td.mask[L][1], m2 = td.mask[L][2];
+    const int ncells = cnt[0] * cnt[1] * cnt[2];
+    // slack for the rounding of cell edges and of the keys' quantisation
+    const double Rg = Rq * (1.0 + 1e-9) + 1e-12 * fmax(td.box[0], fmax(td.box[1], td.box[2]));
+    const double Rg2 = Rg * Rg;
     const long long off = td.tab_off[L];
-    unsigned long long kx = deposit_bits((unsigned)lo[0], m0) | deposit_bits((unsigned)lo[1], m1) |
-                            deposit_bits((unsigned)lo[2], m2);
-    for (int ix = 0; ix < cnt[0]; ix++) {
-        unsigned long long ky = kx;
-        for (int iy = 0; iy < cnt[1]; iy++) {
-            unsigned long long kz = ky;
-            for (int iz = 0; iz < cnt[2]; iz++) {
-                const int2 se = tab[off + (long long)kz];
-                for (int j = se.x; j < se.y; j++) visit(j);
-                kz = dilated_inc(kz, m2);
+    // cell coordinates from the flat index through FP32 reciprocals (exact for
+    // the few thousand cells a scan covers)
+    const float inv2 = 1.0f / (float)cnt[2], inv1 = 1.0f / (float)cnt[1];
+    for (int c0 = 0; c0 < ncells; c0 += kWave) {
+        const int c = c0 + lane;
+        int num = 0, st = 0;
+        double sh[3] = {0.0, 0.0, 0.0};
+        if (c < ncells) {
+            const int t = (int)(((float)c + 0.5f) * inv2);
+            const int tz = c - t * cnt[2];
+            const int tx = (int)(((float)t + 0.5f) * inv1);
+            const int ty = t - tx * cnt[1];
+            const int u[3] = {a[0] + tx, a[1] + ty, a[2] + tz};
+            double g2 = 0.0;
+            unsigned long long key = 0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const double s = td.cs[L][d];
+                const double clo = u[d] * s;
+                const double g = (wrap >> d) & 1 ? 0.0 : fmax(0.0, fmax(clo - bmax[d], bmin[d] - (clo + s)));
+                g2 += g * g;
+                // unwrapped cell coordinates stay within one box side of [0, nc)
+                int w = u[d];
+                if (w < 0) {
+                    w += nc[d];
+                    sh[d] = -td.box[d];
+                } else if (w >= nc[d]) {
+                    w -= nc[d];
+                    sh[d] = td.box[d];
+                }
+                key |= deposit_bits((unsigned)w, td.mask[L][d]);
             }
-            ky = dilated_inc(ky, m1);
+            if (g2 < Rg2) {
+                const int2 se = tab[off + (long long)key];
+                st = se.x;
+                num = se.y - se.x;
+            }
         }
-        kx = dilated_inc(kx, m0);
+        int incl = num;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int v = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += v;
+        }
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+        if (total == 0) continue;
+        S.excl[lane] = incl - num;
+        S.start[lane] = st;
+        S.sh[0][lane] = sh[0];
+        S.sh[1][lane] = sh[1];
+        S.sh[2][lane] = sh[2];
+        wave_lds_sync();
+        for (int t0 = 0; t0 < total; t0 += kWave) {
+            const int t = t0 + lane;
+            // slots past the end hold a far-away point that no sphere reaches
+            double4 q = make_double4(1e30, 1e30, 1e30, __longlong_as_double(-1ll));
+            if (t < total) {
+                // the last batch cell whose prefix is <= t holds particle t
+                int k = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    if (S.excl[k + step] <= t) k += step;
+                const int j = S.start[k] + (t - S.excl[k]);
+                const double4 p = pos[j];
+                q = make_double4(p.x + S.sh[0][k], p.y + S.sh[1][k], p.z + S.sh[2][k],
+                                 __longlong_as_double((long long)j));
+            }
+            S.cand[lane] = q;
+            wave_lds_sync();
+            const int nb = min(kWave, total - t0);
+            unsigned long long mk = wrap ? batch_mask<true>(S, nb, xi, R2, wrap, td.box)
+                                         : batch_mask<false>(S, nb, xi, R2, 0, td.box);
+            if (!sel) mk = 0;
+            while (mk) {
+                const int k = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                const double4 qk = S.cand[k];
+                hit((int)__double_as_longlong(qk.w), sq_disp(qk, xi, wrap, td.box));
+            }
+            wave_lds_sync();
+        }
     }
+}
+
+// a value known to be equal on all lanes, moved to scalar registers
+__device__ __forceinline__ double uniform_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // wave-wide min / max of doubles (all 64 lanes participate)

@@ -8,7 +8,10 @@
 namespace mfm {
 
 constexpr int kGatherMax = 20;
-constexpr int kRCap = 96;        // radii slots per particle in the kernel-length solve
+#ifndef MFM_RCAP
+#define MFM_RCAP 160
+#endif
+constexpr int kRCap = MFM_RCAP;  // radii slots per particle in the kernel-length solve
 
 // up to kGatherMax arrays of 8-byte elements reordered by one launch: dst[i] = src[idx[i]]
 struct GatherBatch {
@@ -39,7 +42,7 @@ void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, in
 void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s);
 
 // pass.hip
-void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
+void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
                     int* counts, int* fb_list, unsigned long long* fb_count, hipStream_t s);
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list,

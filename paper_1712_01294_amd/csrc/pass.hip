@@ -60,23 +60,59 @@ __device__ __forceinline__ void displacement(const Phys& ph, const double xi[3],
 // ------------------------------------------------------------ kernel length
 // The root of (32/3) sum_j w(r_ij / H) = n_ngb is found per particle by
 // safeguarded Newton iterations on the radii r_ij < hi of a bracket (lo, hi].
-// One stencil scan at a trial radius R collects the radii (rl) and indices
-// (jl) into interleaved global lists (rl[k * n + i], coalesced across a wave);
-// a lane whose R holds too few neighbours, or more than the list holds,
-// adjusts R and scans again.  Particles still without a bracket go to the
-// per-particle fallback.  After the root, the indices with r < H (self
-// excluded) are compacted in place: that is the gather part of the flux list.
+// A scan at a trial radius R collects the radii (rl) and indices (jl) within R
+// into interleaved global lists (rl[k * n + i], coalesced across a wave); a
+// lane whose R holds too few neighbours, or more than the list holds, adjusts R
+// and scans again.  Scans are wave-cooperative: each pass takes the lanes whose
+// trial radius is within a factor two of the largest one and lie close to the
+// first of them, and scans their union once.  Particles still without a
+// bracket go to the per-particle fallback.  After the root, the indices with
+// r < H (self excluded) are compacted in place: the gather part of the flux list.
 
-__device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, unsigned long long key,
+// Local density from the 3x3x3 block of cells around the particle's own cell,
+// on the finest level where the block holds at least kColdCount particles (so
+// the block is about as wide as the kernel support); the radius holding n_ngb
+// particles at that density.  Open sides shrink the block to the cells inside.
+#ifndef MFM_COLD_COUNT
+#define MFM_COLD_COUNT 32
+#endif
+__device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3],
                              double n_ngb) {
-    if (key >> td.ktot) key = 0;
     for (int l = td.bmax; l >= 0; l--) {
-        unsigned long long c = key >> (td.ktot - td.kbits[l]);
-        int2 se = tab[td.tab_off[l] + (long long)c];
-        double cntp = (double)(se.y - se.x);
-        if (cntp >= n_ngb || l == 0) {
-            double vol = td.cs[l][0] * td.cs[l][1] * td.cs[l][2];
-            return cbrt(3.0 * n_ngb * vol / (4.0 * M_PI * cntp));
+        int c[3];
+        unsigned long long dil[3][3];   // deposited keys of coordinates c-1, c, c+1 per axis
+        bool ok[3][3];
+        int ncl[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const int nc = td.ncell[l][d];
+            c[d] = min(nc - 1, max(0, (int)floor(xi[d] / td.cs[l][d])));
+            ncl[d] = 0;
+#pragma unroll
+            for (int o = 0; o < 3; o++) {
+                int w = c[d] + o - 1;
+                bool in = true;
+                if (w < 0 || w >= nc) {
+                    if (td.periodic[d] && nc >= 3) w = (w + nc) % nc;
+                    else in = false;
+                }
+                if (nc < 3 && o != 1) in = false;   // fewer than 3 cells: count each once
+                ok[d][o] = in;
+                ncl[d] += in;
+                dil[d][o] = in ? deposit_bits((unsigned)w, td.mask[l][d]) : 0ull;
+            }
+        }
+        double cntp = 0.0;
+        for (int ox = 0; ox < 3; ox++)
+            for (int oy = 0; oy < 3; oy++)
+                for (int oz = 0; oz < 3; oz++) {
+                    if (!(ok[0][ox] && ok[1][oy] && ok[2][oz])) continue;
+                    const int2 se = tab[td.tab_off[l] + (long long)(dil[0][ox] | dil[1][oy] | dil[2][oz])];
+                    cntp += (double)(se.y - se.x);
+                }
+        if (cntp >= (double)MFM_COLD_COUNT || l == 0) {
+            const double vol = ncl[0] * td.cs[l][0] * ncl[1] * td.cs[l][1] * ncl[2] * td.cs[l][2];
+            return cbrt(3.0 * n_ngb * vol / (4.0 * M_PI * fmax(cntp, 1.0)));
         }
     }
     return 0.0;
@@ -90,6 +126,7 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
         iters++;
         const double iH = 1.0 / Hc;
         double s = 0.0, sq = 0.0;
+#pragma unroll 4
         for (int k = 0; k < m; k++) {
             const double q = rl[(long long)k * n + i] * iH;
             s += spline_w(q);
@@ -115,119 +152,151 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
     return false;
 }
 
-__global__ __launch_bounds__(256) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
-                                                  const unsigned long long* __restrict__ keys,
+constexpr int kScanRounds = 12;   // scans per particle before the fallback takes it
+
+// Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
+// outweighs the few loop-invariant values this budget spills to scratch.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                   const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
                                                   int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count) {
+    __shared__ ScanLds lds[256 / kWave];
+    ScanLds& S = lds[threadIdx.x / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
-    unsigned long long iters = 0, rounds = 0;
+    const long long n = a.n;
+    const int cap = min(kRCap, ph.max_ngb);
+    const double c32 = 32.0 / 3.0;
+    double half = INFINITY;
+    for (int d = 0; d < 3; d++)
+        if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+    double xi[3] = {0.0, 0.0, 0.0};
+    double guess = 0.0;
+    bool warm = false;
     if (act) {
-        const long long n = a.n;
-        const int cap = min(kRCap, ph.max_ngb);
-        const double c32 = 32.0 / 3.0;
         const double4 pi = pos[i];
-        const double xi[3] = {pi.x, pi.y, pi.z};
-        double half = INFINITY;
-        for (int d = 0; d < 3; d++)
-            if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
-        double guess = a.H[i];
-        const bool warm = guess > 0.0;
-        if (!warm) guess = cold_guess(td, tab, keys[i], ph.n_ngb);
-        double lo = 0.0, hi = INFINITY;
-        double R = (warm ? 1.1 : 1.4) * guess;
-        int m = 0;
-        double neff_hi = 0.0;
-        bool ok = false;
-        for (int round = 0; round < 12; round++) {
-            if (!(R < half)) {
-                R = half * (1.0 - 1e-12);
-                if (!(R > lo)) break;   // the root lies beyond half a periodic side
-            }
+        xi[0] = pi.x;
+        xi[1] = pi.y;
+        xi[2] = pi.z;
+        guess = a.H[i];
+        warm = guess > 0.0;
+        if (!warm) guess = cold_guess(td, tab, xi, ph.n_ngb);
+    }
+    // state 0: scanning, 1: bracketed with every radius below hi listed, 2: given up
+    int state = act ? 0 : 2;
+    double lo = 0.0, hi = INFINITY, top = INFINITY;   // top: smallest R whose list overflowed
+    double R = (warm ? 1.1 : 1.4) * guess;
+    double neff_hi = 0.0;
+    int m = 0, rounds = 0;
+    unsigned long long iters = 0;
+    for (int pass = 0; pass < kScanRounds * kWave; pass++) {
+        if (state == 0 && (rounds >= kScanRounds || !(R > lo))) state = 2;
+        if (state == 0 && !(R < half)) {
+            R = half * (1.0 - 1e-12);
+            if (!(R > lo)) state = 2;   // the root lies beyond half a periodic side
+        }
+        const bool need = state == 0;
+        if (__ballot(need) == 0) break;
+        // this pass: lanes within 2x of the largest radius and within 2 Rref of the first such lane
+        const double Rref = uniform_d(wave_max_d(need ? R : 0.0));
+        const bool big = need && R >= 0.5 * Rref;
+        const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)__ballot(big)) - 1);
+        const double xl0 = uniform_d(__shfl(xi[0], leader, kWave)), xl1 = uniform_d(__shfl(xi[1], leader, kWave)),
+                     xl2 = uniform_d(__shfl(xi[2], leader, kWave));
+        const bool cls = big && fabs(xi[0] - xl0) <= 2.0 * Rref && fabs(xi[1] - xl1) <= 2.0 * Rref &&
+                         fabs(xi[2] - xl2) <= 2.0 * Rref;
+        const double Rq = uniform_d(wave_max_d(cls ? R : 0.0));
+        double bmin[3], bmax[3];
+        for (int d = 0; d < 3; d++) {
+            bmin[d] = uniform_d(wave_min_d(cls ? xi[d] : INFINITY));
+            bmax[d] = uniform_d(wave_max_d(cls ? xi[d] : -INFINITY));
+        }
+        const double R2 = R * R;
+        if (cls) {
             rounds++;
-            const double R2 = R * R, iR = 1.0 / R;
-            double sw = 0.0;
             m = 0;
-            stencil_scan(td, tab, xi, R, [&](int j) {
-                const double4 pj = pos[j];
-                double d[3];
-                displacement(ph, xi, pj.x, pj.y, pj.z, d);
-                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (r2 < R2) {
-                    const double r = sqrt(r2);
-                    if (r < R) {
-                        if (m < cap) {
-                            rl[(long long)m * n + i] = r;
-                            jl[(long long)m * n + i] = j;
-                        }
-                        m++;
-                        sw += spline_w(r * iR);
-                    }
-                }
-            });
-            const double neff = c32 * sw;
-            if (neff < ph.n_ngb) {
-                lo = R;
-                if (hi < INFINITY) {
-                    R = 0.5 * (lo + hi);
-                } else {
-                    // grow by the density estimate, at least 1.15x, at most 2x
-                    const double g = 1.1 * cbrt(ph.n_ngb / neff);
-                    R *= fmin(2.0, fmax(1.15, g));
-                }
+        }
+        group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, R2, cls, [&](int j, double r2) {
+            if (m < cap) {
+                rl[(long long)m * n + i] = r2;
+                jl[(long long)m * n + i] = j;
+            }
+            m++;
+        });
+        if (cls) {
+            if (m > cap) {
+                // too many radii to keep: shrink by the count, without bracketing
+                top = fmin(top, R);
+                R = fmax(lo + 0.25 * (R - lo), R * cbrt(0.6 * cap / (double)m));
             } else {
-                hi = R;
-                if (m > cap) {
-                    // too many radii to keep: shrink towards the estimated root
-                    const double est = R * cbrt(ph.n_ngb / neff);
-                    const double fit = R * cbrt(0.8 * cap / (double)m);
-                    R = fmax(lo + 0.25 * (hi - lo), fmax(1.02 * est, fit));
-                    if (!(R < hi)) R = 0.5 * (lo + hi);
+                // radii from the squared distances, and the weighted count at R
+                const double iR = 1.0 / R;
+                double sw = 0.0;
+#pragma unroll 4
+                for (int k = 0; k < m; k++) {
+                    const double r = sqrt(rl[(long long)k * n + i]);
+                    rl[(long long)k * n + i] = r;
+                    sw += spline_w(r * iR);
+                }
+                const double neff = c32 * sw;
+                if (neff < ph.n_ngb) {
+                    lo = R;
+                    if (hi < INFINITY) {
+                        R = 0.5 * (lo + hi);
+                    } else {
+                        // grow by the density estimate, at least 1.15x, at most 4x,
+                        // and not past a radius known to overflow
+                        const double g = 1.1 * cbrt(ph.n_ngb / fmax(neff, 1e-300));
+                        R *= fmin(4.0, fmax(1.15, g));
+                        if (top < INFINITY) R = fmin(R, 0.5 * (lo + top));
+                    }
                 } else {
+                    hi = R;
                     neff_hi = neff;
-                    ok = true;
-                    break;
+                    state = 1;
                 }
             }
-        }
-        bool conv = false;
-        double Hc = 0.0;
-        if (ok) {
-            Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
-            if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
-            conv = newton_h(rl, n, i, m, ph.n_ngb, ph.h_maxit, lo, hi, Hc, iters);
-        }
-        if (ok && conv) {
-            double s = 0.0;
-            const double iH = 1.0 / Hc;
-            int c = 0;
-            for (int k = 0; k < m; k++) {
-                const double r = rl[(long long)k * n + i];
-                s += spline_w(r * iH);
-                const int j = jl[(long long)k * n + i];
-                if (r < Hc && j != i) {
-                    jl[(long long)c * n + i] = j;
-                    c++;
-                }
-            }
-            const double nk = kernel_norm(Hc) * s;
-            a.H[i] = Hc;
-            a.nk[i] = nk;
-            a.V[i] = 1.0 / nk;
-            gcount[i] = c;
-            counts[i] = c;
-        } else {
-            // hand over to the per-particle solver, which starts from this bracket
-            const unsigned long long slot = atomicAdd(fb_count, 1ull);
-            if (slot < (unsigned long long)a.n) fb_list[slot] = i;
-            a.H[i] = (hi < INFINITY) ? hi : (lo > 0.0 ? lo : guess);
         }
     }
-    count_add(&cnt->h_iters, iters + rounds);
-    count_max(&cnt->h_iters_max, iters + rounds);
-    count_max(&cnt->h_rounds_max, rounds);
+    bool conv = false;
+    double Hc = 0.0;
+    if (state == 1) {
+        Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
+        if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
+        conv = newton_h(rl, n, i, m, ph.n_ngb, ph.h_maxit, lo, hi, Hc, iters);
+    }
+    if (state == 1 && conv) {
+        double sum = 0.0;
+        const double iH = 1.0 / Hc;
+        int c = 0;
+        for (int k = 0; k < m; k++) {
+            const double r = rl[(long long)k * n + i];
+            sum += spline_w(r * iH);
+            const int j = jl[(long long)k * n + i];
+            if (r < Hc && j != i) {
+                jl[(long long)c * n + i] = j;
+                c++;
+            }
+        }
+        const double nk = kernel_norm(Hc) * sum;
+        a.H[i] = Hc;
+        a.nk[i] = nk;
+        a.V[i] = 1.0 / nk;
+        gcount[i] = c;
+        counts[i] = c;
+    } else if (act) {
+        // hand over to the per-particle solver, which starts from this bracket
+        const unsigned long long slot = atomicAdd(fb_count, 1ull);
+        if (slot < (unsigned long long)a.n) fb_list[slot] = i;
+        a.H[i] = (hi < INFINITY) ? hi : (lo > 0.0 ? lo : guess);
+    }
+    const unsigned long long rr = (unsigned long long)rounds;
+    count_add(&cnt->h_iters, iters + rr);
+    count_max(&cnt->h_iters_max, iters + rr);
+    count_max(&cnt->h_rounds_max, rr);
+    count_add(&cnt->h_rounds3, rounds >= 3 ? 1ull : 0ull);
 }
 
 // Per-particle solve for the few particles the stencil solve handed over:
@@ -802,11 +871,11 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
 // ------------------------------------------------------------------ launchers
 static int blocks_of(int n, int b) { return (n + b - 1) / b; }
 
-void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab, const unsigned long long* keys,
+void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
                     int* counts, int* fb_list, unsigned long long* fb_count, hipStream_t s) {
     launch_fill_u64(1, fb_count, 0ull, s);
-    k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, keys, pos, ph, cnt, rl, list, gcount, counts,
+    k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
                                                   fb_list, fb_count);
     // the fallback grid covers every particle; blocks past the handed-over count exit at once
     k_solve_h_fallback<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, ph, cnt, fb_list, fb_count, list, gcount,

@@ -48,7 +48,8 @@ class Counters(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("pairs", "list_entries", "list_max", "h_iters", "h_iters_max",
                                          "noconv", "minimage", "overflow", "illcond", "fallbacks",
                                          "clamps", "nonfinite", "floors", "first_bad")] + \
-               [("cond_max_seen", C.c_double), ("h_rounds_max", C.c_int64), ("h_fallback", C.c_int64)]
+               [("cond_max_seen", C.c_double), ("h_rounds_max", C.c_int64), ("h_fallback", C.c_int64),
+                ("h_rounds3", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
