@@ -76,7 +76,6 @@ static void setup_tree(mfm_ctx* c) {
         td.periodic[d] = c->p.periodic[d];
     }
     td.bmax = bmax;
-    td.leaf = 8;
     long long off = 0;
     int k = 0;
     for (int l = 0; l <= bmax; l++) {
@@ -88,7 +87,6 @@ static void setup_tree(mfm_ctx* c) {
             }
         k += nb;
         td.actmask[l] = m;
-        td.nact[l] = nb;
         td.kbits[l] = k;
         td.tab_off[l] = off;
         off += 1ll << k;

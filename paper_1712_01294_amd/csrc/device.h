@@ -1,6 +1,7 @@
 // Device-side building blocks of the gfx950 MFM pass: cubic-spline kernel,
-// minimum-image displacement, and the stackless walk over the implicit octree
-// that the Morton-sorted particle order and the per-level cell tables define.
+// minimum-image displacement, and the wave-cooperative scans over the cell
+// tables that the Morton-sorted particle order defines (one (start, end)
+// range per cell of every level of an implicit octree).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,8 +16,6 @@ constexpr int kWave = 64;
 struct TreeDesc {
     int bmax;                        // deepest level
     int ktot;                        // key bits at bmax
-    int leaf;                        // stop descending at <= leaf particles
-    int nact[kMaxLevels];            // axes refined at level l (0 at l = 0)
     int actmask[kMaxLevels];         // bit d set when axis d refines at level l
     int kbits[kMaxLevels];           // key-prefix bits of a level-l cell
     long long tab_off[kMaxLevels];   // offset of level l in the (start, end) table
@@ -97,118 +96,6 @@ __device__ __forceinline__ double min_image(double d, double L, int periodic) {
     return d;
 }
 
-// distance along one axis from coordinate x to the interval [lo, hi)
-__device__ __forceinline__ double axis_gap(double x, double lo, double hi, double L, int periodic) {
-    if (x >= lo && x < hi) return 0.0;
-    if (!periodic) return fmax(lo - x, x - hi);
-    double g1 = lo - x;
-    if (g1 < 0.0) g1 += L;
-    double g2 = x - hi;
-    if (g2 < 0.0) g2 += L;
-    return fmin(g1, g2);
-}
-
-// ------------------------------------------------------ implicit octree walk
-// Node = (level l, key prefix c, integer cell coordinates cx, cy, cz).
-// A level-l cell holds the particles whose key starts with c: the sorted
-// range tab[l][c] = [start, end).  `accept(l, c, cell_lo[3], cell_hi[3])`
-// decides whether a non-empty node can hold a neighbour; `leaf(start, end)`
-// scans a node's particles.  The walk visits nodes in Morton order without a
-// stack: after a node it moves to the next sibling, climbing while the node
-// is the last child of its parent.
-template <typename Accept, typename Leaf>
-__device__ __forceinline__ void tree_walk(const TreeDesc& td, const int2* __restrict__ tab,
-                                          Accept&& accept, Leaf&& leaf) {
-    int l = 0;
-    unsigned long long c = 0;
-    int cc[3] = {0, 0, 0};
-    for (;;) {
-        int2 se = tab[td.tab_off[l] + (long long)c];
-        if (se.y > se.x) {
-            double lo[3], hi[3];
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                lo[d] = cc[d] * td.cs[l][d];
-                hi[d] = lo[d] + td.cs[l][d];
-            }
-            if (accept(l, c, lo, hi)) {
-                if (l == td.bmax || se.y - se.x <= td.leaf) {
-                    leaf(se.x, se.y);
-                } else {
-                    // first child
-                    l++;
-                    int nb = td.nact[l];
-                    c <<= nb;
-                    int m = td.actmask[l];
-#pragma unroll
-                    for (int d = 0; d < 3; d++)
-                        if (m & (1 << d)) cc[d] <<= 1;
-                    continue;
-                }
-            }
-        }
-        // advance to the next sibling, climbing past last children
-        for (;;) {
-            if (l == 0) return;
-            int nb = td.nact[l];
-            unsigned k = (unsigned)(c & ((1ull << nb) - 1));
-            if (k + 1 < (1u << nb)) {
-                c++;
-                k++;
-                int m = td.actmask[l];
-                int pos = nb;
-#pragma unroll
-                for (int d = 0; d < 3; d++)
-                    if (m & (1 << d)) {
-                        pos--;
-                        cc[d] = (cc[d] & ~1) | ((k >> pos) & 1);
-                    }
-                break;
-            }
-            c >>= nb;
-            int m = td.actmask[l];
-#pragma unroll
-            for (int d = 0; d < 3; d++)
-                if (m & (1 << d)) cc[d] >>= 1;
-            l--;
-        }
-    }
-}
-
-// squared distance from a point to a node box, with a relative pad so that a
-// particle binned into a cell by rounding is never rejected by its bounds
-__device__ __forceinline__ double node_dist2(const TreeDesc& td, const double xi[3],
-                                             const double lo[3], const double hi[3]) {
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        double pad = 1e-12 * td.box[d];
-        double g = axis_gap(xi[d], lo[d] - pad, hi[d] + pad, td.box[d], td.periodic[d]);
-        s += g * g;
-    }
-    return s;
-}
-
-// squared distance between a node box and a group box (both inside [0, box)),
-// nearest periodic image per axis, padded like node_dist2
-__device__ __forceinline__ double box_dist2(const TreeDesc& td, const double glo[3], const double ghi[3],
-                                            const double lo[3], const double hi[3]) {
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const double pad = 1e-12 * td.box[d];
-        const double a = lo[d] - pad, b = hi[d] + pad;
-        double g = fmax(0.0, fmax(a - ghi[d], glo[d] - b));
-        if (td.periodic[d]) {
-            const double L = td.box[d];
-            g = fmin(g, fmax(0.0, fmax(a + L - ghi[d], glo[d] - b - L)));
-            g = fmin(g, fmax(0.0, fmax(a - L - ghi[d], glo[d] - b + L)));
-        }
-        s += g * g;
-    }
-    return s;
-}
-
 // ------------------------------------------------- wave-cooperative cell scan
 // A group of lanes (Morton neighbours with similar trial radii) scans the union
 // of their neighbourhoods together: the cells of one table level whose boxes
@@ -253,16 +140,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Tests every particle of every cell within Rq of the box [bmin, bmax] against
-// the calling lane's sphere |x - xi|^2 < R2 (lanes with sel false take no
-// hits) and calls hit(j, r2) for each particle inside, in the order the cells
-// are scanned.  Staged positions are moved to the periodic image next to the
-// box; an axis that the scan spans whole (bit d of `wrap`) takes the minimum
-// image per displacement instead.  bmin, bmax and Rq must be uniform over the
-// wave, with Rq below half of every periodic side.  Each batch of 64 staged
-// particles is first tested without branches into a 64-bit mask per lane, so
-// the tests of neighbouring particles overlap, and the lane then walks its
-// set bits.
 __device__ __forceinline__ double sq_disp(const double4& q, const double xi[3], int wrap, const double box[3]) {
     double d0 = q.x - xi[0], d1 = q.y - xi[1], d2 = q.z - xi[2];
     if (wrap) {
@@ -287,11 +164,21 @@ __device__ __forceinline__ unsigned long long batch_mask(const ScanLds& S, int n
     return mk;
 }
 
-template <typename Hit>
-__device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __restrict__ tab,
+// Cell enumeration and staging shared by the cooperative scans: the cells of
+// one table level within Rq of the box [bmin, bmax] (the finest level whose
+// cells are at least kScanScale Rq wide) are taken 64 at a time, one per lane
+// (key, table entry, periodic image), and their particles are handed out 64 at
+// a time, one per lane, with coalesced loads: chunk(q, valid, nb, wrap) runs on
+// every lane for each such chunk, q being the lane's particle moved to the
+// periodic image next to the box (index bits in q.w), valid whether the lane
+// holds one, nb how many lanes do.  `wrap` has bit d set when the scan spans
+// periodic axis d whole; displacements along such an axis must then take the
+// minimum image themselves.  bmin, bmax and Rq must be uniform over the wave,
+// with Rq below half of every periodic side.
+template <typename Chunk>
+__device__ __forceinline__ void scan_cells(const TreeDesc& td, const int2* __restrict__ tab,
                                            const double4* __restrict__ pos, ScanLds& S, int lane,
-                                           const double bmin[3], const double bmax[3], double Rq,
-                                           const double xi[3], double R2, bool sel, Hit&& hit) {
+                                           const double bmin[3], const double bmax[3], double Rq, Chunk&& chunk) {
     int L = td.bmax;
     while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < kScanScale * Rq) L--;
     L = __builtin_amdgcn_readfirstlane(L);
@@ -377,7 +264,7 @@ __device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __res
         wave_lds_sync();
         for (int t0 = 0; t0 < total; t0 += kWave) {
             const int t = t0 + lane;
-            // slots past the end hold a far-away point that no sphere reaches
+            // lanes past the end hold a far-away point that no sphere reaches
             double4 q = make_double4(1e30, 1e30, 1e30, __longlong_as_double(-1ll));
             if (t < total) {
                 // the last batch cell whose prefix is <= t holds particle t
@@ -390,21 +277,44 @@ __device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __res
                 q = make_double4(p.x + S.sh[0][k], p.y + S.sh[1][k], p.z + S.sh[2][k],
                                  __longlong_as_double((long long)j));
             }
-            S.cand[lane] = q;
-            wave_lds_sync();
-            const int nb = min(kWave, total - t0);
-            unsigned long long mk = wrap ? batch_mask<true>(S, nb, xi, R2, wrap, td.box)
-                                         : batch_mask<false>(S, nb, xi, R2, 0, td.box);
-            if (!sel) mk = 0;
-            while (mk) {
-                const int k = __builtin_ctzll(mk);
-                mk &= mk - 1;
-                const double4 qk = S.cand[k];
-                hit((int)__double_as_longlong(qk.w), sq_disp(qk, xi, wrap, td.box));
-            }
-            wave_lds_sync();
+            chunk(q, t < total, min(kWave, total - t0), wrap);
         }
+        wave_lds_sync();   // the next batch overwrites the cell data
     }
+}
+
+// Tests every particle of every cell within Rq of the box [bmin, bmax] against
+// the calling lane's sphere |x - xi|^2 < R2 (lanes with sel false take no
+// hits) and calls hit(j, r2) for each particle inside, in the order the cells
+// are scanned.  Each chunk of 64 staged particles is put in LDS and first
+// tested without branches into a 64-bit mask per lane, so the tests of
+// neighbouring particles overlap; the lane then walks its set bits.
+template <typename Hit>
+__device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __restrict__ tab,
+                                           const double4* __restrict__ pos, ScanLds& S, int lane,
+                                           const double bmin[3], const double bmax[3], double Rq,
+                                           const double xi[3], double R2, bool sel, Hit&& hit) {
+    scan_cells(td, tab, pos, S, lane, bmin, bmax, Rq, [&](const double4& q, bool, int nb, int wrap) {
+        S.cand[lane] = q;
+        wave_lds_sync();
+        unsigned long long mk = wrap ? batch_mask<true>(S, nb, xi, R2, wrap, td.box)
+                                     : batch_mask<false>(S, nb, xi, R2, 0, td.box);
+        if (!sel) mk = 0;
+        while (mk) {
+            const int k = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const double4 qk = S.cand[k];
+            hit((int)__double_as_longlong(qk.w), sq_disp(qk, xi, wrap, td.box));
+        }
+        wave_lds_sync();
+    });
+}
+
+// wave-wide sum of doubles in a fixed order (all 64 lanes participate)
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // a value known to be equal on all lanes, moved to scalar registers

@@ -299,53 +299,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     count_add(&cnt->h_rounds3, rounds >= 3 ? 1ull : 0ull);
 }
 
-// Per-particle solve for the few particles the stencil solve handed over:
-// every residual evaluation walks the tree again, so there is no limit on the
-// number of neighbours.  The bracket grows from H until it holds the root,
-// then Newton with bisection safeguard; a last walk writes the gather list.
+// Solve for the few particles the group scan handed over (no bracket within
+// the scan rounds, or more radii than the list holds): one wave per particle,
+// every residual evaluation scans the cells within H again with the lanes
+// splitting the particles, so there is no limit on the number of neighbours.
+// The bracket grows from the handed-over H until it holds the root, then
+// Newton with bisection safeguard; a last scan writes the gather list.
 __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
-                                                          Phys ph, Counters* cnt, const int* __restrict__ fb_list,
+                                                          const double4* __restrict__ pos, Phys ph, Counters* cnt,
+                                                          const int* __restrict__ fb_list,
                                                           const unsigned long long* __restrict__ fb_count,
                                                           int* __restrict__ jl, int* __restrict__ gcount,
                                                           int* __restrict__ counts) {
-    const unsigned long long nfb = *fb_count;
-    const unsigned long long t = (unsigned long long)blockIdx.x * 64 + threadIdx.x;
-    if (t == 0) cnt->h_fallback = nfb;
-    unsigned long long iters = 0, noconv = 0, noimg = 0, over = 0;
-    if (t < nfb && t < (unsigned long long)a.n) {
-        const long long n = a.n;
-        const int i = fb_list[t];
-        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
-        double half = INFINITY;
-        for (int d = 0; d < 3; d++)
-            if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
-        const double c32 = 32.0 / 3.0;
+    __shared__ ScanLds S;
+    const int lane = threadIdx.x;
+    const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
+    if (blockIdx.x == 0 && lane == 0) cnt->h_fallback = *fb_count;
+    const long long n = a.n;
+    const double c32 = 32.0 / 3.0;
+    double half = INFINITY;
+    for (int d = 0; d < 3; d++)
+        if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+    unsigned long long iters = 0, iters_max = 0, noconv = 0, noimg = 0, over = 0;
+    for (unsigned long long t = blockIdx.x; t < nfb; t += gridDim.x) {
+        const unsigned long long iters0 = iters;
+        const int i = __builtin_amdgcn_readfirstlane(fb_list[t]);
+        const double4 pi = pos[i];
+        const double xi[3] = {uniform_d(pi.x), uniform_d(pi.y), uniform_d(pi.z)};
         // residual and slope at H, summing over r < H
         auto eval = [&](double H, double& f, double& fp, double& nk) {
             const double H2 = H * H, iH = 1.0 / H;
             double s = 0.0, sq = 0.0;
-            tree_walk(
-                td, tab,
-                [&](int, unsigned long long, const double* nlo, const double* nhi) {
-                    return node_dist2(td, xi, nlo, nhi) < H2;
-                },
-                [&](int s0, int e0) {
-                    for (int j = s0; j < e0; j++) {
-                        double d[3];
-                        displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
-                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        if (r2 < H2) {
-                            const double q = sqrt(r2) * iH;
-                            s += spline_w(q);
-                            sq += spline_qdw(q);
-                        }
-                    }
-                });
+            scan_cells(td, tab, pos, S, lane, xi, xi, H, [&](const double4& q, bool valid, int, int wrap) {
+                const double r2 = sq_disp(q, xi, wrap, td.box);
+                if (valid && r2 < H2) {
+                    const double qq = sqrt(r2) * iH;
+                    s += spline_w(qq);
+                    sq += spline_qdw(qq);
+                }
+            });
+            s = uniform_d(wave_sum_d(s));
+            sq = uniform_d(wave_sum_d(sq));
             f = c32 * s - ph.n_ngb;
             fp = -c32 * sq * iH;
             nk = kernel_norm(H) * s;
         };
         double lo = 0.0, hi = a.H[i];
+        hi = uniform_d(hi);
         double f, fp, nk;
         bool ok = false;
         for (int k = 0; k < 64; k++) {
@@ -393,45 +393,43 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
             eval(Hc, f, fp, nk);
             const double H2 = Hc * Hc;
             const int cap = ph.max_ngb;
-            tree_walk(
-                td, tab,
-                [&](int, unsigned long long, const double* nlo, const double* nhi) {
-                    return node_dist2(td, xi, nlo, nhi) < H2;
-                },
-                [&](int s0, int e0) {
-                    for (int j = s0; j < e0; j++) {
-                        if (j == i) continue;
-                        double d[3];
-                        displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
-                        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                        if (r < Hc) {
-                            if (c < cap) jl[(long long)c * n + i] = j;
-                            c++;
-                        }
-                    }
-                });
+            // every gather neighbour but the particle itself, in scan order
+            scan_cells(td, tab, pos, S, lane, xi, xi, Hc, [&](const double4& q, bool valid, int, int wrap) {
+                const double r2 = sq_disp(q, xi, wrap, td.box);
+                const int j = (int)__double_as_longlong(q.w);
+                const bool in = valid && r2 < H2 && j != i && sqrt(r2) < Hc;
+                const unsigned long long b = __ballot(in);
+                const int slot = c + __popcll(b & ((1ull << lane) - 1ull));
+                if (in && slot < cap) jl[(long long)slot * n + i] = j;
+                c += __popcll(b);
+            });
             if (c > cap) {
                 c = cap;
                 over = 1;
-                flag_index(cnt, i);
+                if (lane == 0) flag_index(cnt, i);
             }
         } else {
             nk = 0.0;
             if (!ok) noimg = 1;
             else noconv = 1;
-            flag_index(cnt, i);
+            if (lane == 0) flag_index(cnt, i);
         }
-        a.H[i] = Hc;
-        a.nk[i] = nk;
-        a.V[i] = 1.0 / nk;
-        gcount[i] = c;
-        counts[i] = c;
+        if (lane == 0) {
+            a.H[i] = Hc;
+            a.nk[i] = nk;
+            a.V[i] = 1.0 / nk;
+            gcount[i] = c;
+            counts[i] = c;
+        }
+        iters_max = max(iters_max, iters - iters0);
     }
-    count_add(&cnt->h_iters, iters);
-    count_max(&cnt->h_iters_max, iters);
-    count_add(&cnt->noconv, noconv);
-    count_add(&cnt->minimage, noimg);
-    count_add(&cnt->overflow, over);
+    if (lane == 0) {
+        if (iters) atomicAdd(&cnt->h_iters, iters);
+        if (iters_max) atomicMax(&cnt->h_iters_max, iters_max);
+        if (noconv) atomicAdd(&cnt->noconv, noconv);
+        if (noimg) atomicAdd(&cnt->minimage, noimg);
+        if (over) atomicAdd(&cnt->overflow, over);
+    }
 }
 
 // --------------------------------------------------------------- flux lists
@@ -870,6 +868,7 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
 
 // ------------------------------------------------------------------ launchers
 static int blocks_of(int n, int b) { return (n + b - 1) / b; }
+constexpr int kFallbackWaves = 1024;
 
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
@@ -877,9 +876,9 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
     launch_fill_u64(1, fb_count, 0ull, s);
     k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
                                                   fb_list, fb_count);
-    // the fallback grid covers every particle; blocks past the handed-over count exit at once
-    k_solve_h_fallback<<<blocks_of(a.n, 64), 64, 0, s>>>(a, td, tab, ph, cnt, fb_list, fb_count, list, gcount,
-                                                          counts);
+    // one wave per handed-over particle, striding over the count the solve left on the device
+    k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, list, gcount,
+                                                     counts);
     k_scatter_lists<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, pos, gcount, counts, list);
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
 }
