@@ -73,49 +73,73 @@ __device__ __forceinline__ void displacement(const Phys& ph, const double xi[3],
 // on the finest level where the block holds at least kColdCount particles (so
 // the block is about as wide as the kernel support); the radius holding n_ngb
 // particles at that density.  Open sides shrink the block to the cells inside.
+// The search starts at the level where a block at the mean density would hold
+// kColdCount particles and moves finer or coarser from there.
 #ifndef MFM_COLD_COUNT
 #define MFM_COLD_COUNT 32
 #endif
-__device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3],
-                             double n_ngb) {
-    for (int l = td.bmax; l >= 0; l--) {
-        int c[3];
-        unsigned long long dil[3][3];   // deposited keys of coordinates c-1, c, c+1 per axis
-        bool ok[3][3];
-        int ncl[3];
+struct BlockCount {
+    double count;
+    double vol;
+};
+
+__device__ BlockCount block_count(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3], int l) {
+    unsigned long long dil[3][3];   // deposited keys of coordinates c-1, c, c+1 per axis
+    bool ok[3][3];
+    int ncl[3];
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const int nc = td.ncell[l][d];
-            c[d] = min(nc - 1, max(0, (int)floor(xi[d] / td.cs[l][d])));
-            ncl[d] = 0;
+    for (int d = 0; d < 3; d++) {
+        const int nc = td.ncell[l][d];
+        const int c = min(nc - 1, max(0, (int)floor(xi[d] / td.cs[l][d])));
+        ncl[d] = 0;
 #pragma unroll
-            for (int o = 0; o < 3; o++) {
-                int w = c[d] + o - 1;
-                bool in = true;
-                if (w < 0 || w >= nc) {
-                    if (td.periodic[d] && nc >= 3) w = (w + nc) % nc;
-                    else in = false;
-                }
-                if (nc < 3 && o != 1) in = false;   // fewer than 3 cells: count each once
-                ok[d][o] = in;
-                ncl[d] += in;
-                dil[d][o] = in ? deposit_bits((unsigned)w, td.mask[l][d]) : 0ull;
+        for (int o = 0; o < 3; o++) {
+            int w = c + o - 1;
+            bool in = true;
+            if (w < 0 || w >= nc) {
+                if (td.periodic[d] && nc >= 3) w = (w + nc) % nc;
+                else in = false;
             }
-        }
-        double cntp = 0.0;
-        for (int ox = 0; ox < 3; ox++)
-            for (int oy = 0; oy < 3; oy++)
-                for (int oz = 0; oz < 3; oz++) {
-                    if (!(ok[0][ox] && ok[1][oy] && ok[2][oz])) continue;
-                    const int2 se = tab[td.tab_off[l] + (long long)(dil[0][ox] | dil[1][oy] | dil[2][oz])];
-                    cntp += (double)(se.y - se.x);
-                }
-        if (cntp >= (double)MFM_COLD_COUNT || l == 0) {
-            const double vol = ncl[0] * td.cs[l][0] * ncl[1] * td.cs[l][1] * ncl[2] * td.cs[l][2];
-            return cbrt(3.0 * n_ngb * vol / (4.0 * M_PI * fmax(cntp, 1.0)));
+            if (nc < 3 && o != 1) in = false;   // fewer than 3 cells: count each once
+            ok[d][o] = in;
+            ncl[d] += in;
+            dil[d][o] = in ? deposit_bits((unsigned)w, td.mask[l][d]) : 0ull;
         }
     }
-    return 0.0;
+    int cnt = 0;
+    const long long off = td.tab_off[l];
+#pragma unroll
+    for (int ox = 0; ox < 3; ox++)
+#pragma unroll
+        for (int oy = 0; oy < 3; oy++)
+#pragma unroll
+            for (int oz = 0; oz < 3; oz++) {
+                // cells outside an open side read cell 0 and count nothing
+                const bool in = ok[0][ox] && ok[1][oy] && ok[2][oz];
+                const int2 se = tab[off + (long long)(in ? (dil[0][ox] | dil[1][oy] | dil[2][oz]) : 0ull)];
+                cnt += in ? se.y - se.x : 0;
+            }
+    return {(double)cnt, ncl[0] * td.cs[l][0] * ncl[1] * td.cs[l][1] * ncl[2] * td.cs[l][2]};
+}
+
+__device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, const double xi[3],
+                             double n_ngb, long long n) {
+    const double need = (double)MFM_COLD_COUNT;
+    const double nbox = (double)n / (td.box[0] * td.box[1] * td.box[2]);
+    int l = td.bmax;
+    while (l > 0 && 27.0 * nbox * td.cs[l][0] * td.cs[l][1] * td.cs[l][2] < need) l--;
+    BlockCount b = block_count(td, tab, xi, l);
+    if (b.count >= need) {
+        while (l < td.bmax) {
+            const BlockCount f = block_count(td, tab, xi, l + 1);
+            if (f.count < need) break;
+            b = f;
+            l++;
+        }
+    } else {
+        while (l > 0 && b.count < need) b = block_count(td, tab, xi, --l);
+    }
+    return cbrt(3.0 * n_ngb * b.vol / (4.0 * M_PI * fmax(b.count, 1.0)));
 }
 
 // safeguarded Newton on the m radii rl[k * n + i]; returns converged
@@ -126,7 +150,7 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
         iters++;
         const double iH = 1.0 / Hc;
         double s = 0.0, sq = 0.0;
-#pragma unroll 4
+#pragma unroll 8
         for (int k = 0; k < m; k++) {
             const double q = rl[(long long)k * n + i] * iH;
             s += spline_w(q);
@@ -153,6 +177,10 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
 }
 
 constexpr int kScanRounds = 12;   // scans per particle before the fallback takes it
+#ifndef MFM_COLD_PAD
+#define MFM_COLD_PAD 1.25
+#endif
+constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
@@ -182,13 +210,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         xi[2] = pi.z;
         guess = a.H[i];
         warm = guess > 0.0;
-        if (!warm) guess = cold_guess(td, tab, xi, ph.n_ngb);
+        if (!warm) guess = cold_guess(td, tab, xi, ph.n_ngb, a.n);
     }
     // state 0: scanning, 1: bracketed with every radius below hi listed, 2: given up
     int state = act ? 0 : 2;
     double lo = 0.0, hi = INFINITY, top = INFINITY;   // top: smallest R whose list overflowed
-    double R = (warm ? 1.1 : 1.4) * guess;
-    double neff_hi = 0.0;
+    double R = (warm ? 1.1 : kColdPad) * guess;
+    double neff_hi = 0.0, fa = NAN;                   // residuals at the bracket ends
     int m = 0, rounds = 0;
     unsigned long long iters = 0;
     for (int pass = 0; pass < kScanRounds * kWave; pass++) {
@@ -214,56 +242,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             bmax[d] = uniform_d(wave_max_d(cls ? xi[d] : -INFINITY));
         }
         const double R2 = R * R;
+        // weighted counts at R and at two trial lengths around the expected root
+        const double Hg = R * (warm ? 1.0 / 1.1 : 1.0 / kColdPad);
+        const double Ht[2] = {0.97 * Hg, 1.03 * Hg};
+        const double iR = 1.0 / R, iT0 = 1.0 / Ht[0], iT1 = 1.0 / Ht[1];
+        double sw = 0.0, st0 = 0.0, st1 = 0.0;
         if (cls) {
             rounds++;
             m = 0;
         }
         group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, R2, cls, [&](int j, double r2) {
+            const double r = sqrt(r2);
             if (m < cap) {
-                rl[(long long)m * n + i] = r2;
+                rl[(long long)m * n + i] = r;
                 jl[(long long)m * n + i] = j;
             }
             m++;
+            sw += spline_w(r * iR);
+            st0 += spline_w(r * iT0);
+            st1 += spline_w(r * iT1);
         });
         if (cls) {
-            if (m > cap) {
-                // too many radii to keep: shrink by the count, without bracketing
-                top = fmin(top, R);
-                R = fmax(lo + 0.25 * (R - lo), R * cbrt(0.6 * cap / (double)m));
-            } else {
-                // radii from the squared distances, and the weighted count at R
-                const double iR = 1.0 / R;
-                double sw = 0.0;
-#pragma unroll 4
-                for (int k = 0; k < m; k++) {
-                    const double r = sqrt(rl[(long long)k * n + i]);
-                    rl[(long long)k * n + i] = r;
-                    sw += spline_w(r * iR);
-                }
-                const double neff = c32 * sw;
-                if (neff < ph.n_ngb) {
-                    lo = R;
-                    if (hi < INFINITY) {
-                        R = 0.5 * (lo + hi);
-                    } else {
-                        // grow by the density estimate, at least 1.15x, at most 4x,
-                        // and not past a radius known to overflow
-                        const double g = 1.1 * cbrt(ph.n_ngb / fmax(neff, 1e-300));
-                        R *= fmin(4.0, fmax(1.15, g));
-                        if (top < INFINITY) R = fmin(R, 0.5 * (lo + top));
-                    }
+            const double neff = c32 * sw;
+            if (neff < ph.n_ngb) {
+                lo = R;
+                if (hi < INFINITY) {
+                    R = 0.5 * (lo + hi);
                 } else {
-                    hi = R;
-                    neff_hi = neff;
-                    state = 1;
+                    // grow by the density estimate, at least 1.15x, at most 4x,
+                    // and not past a radius known to overflow
+                    const double g = 1.1 * cbrt(ph.n_ngb / fmax(neff, 1e-300));
+                    R *= fmin(4.0, fmax(1.15, g));
+                    if (top < INFINITY) R = fmin(R, 0.5 * (lo + top));
                 }
+            } else if (m > cap) {
+                // bracketed, but too many radii to keep: rescan just above the estimated root
+                hi = R;
+                top = fmin(top, R);
+                R = fmax(lo + 0.25 * (hi - lo), fmin(1.05 * R * cbrt(ph.n_ngb / neff), R * cbrt(0.8 * cap / m)));
+                if (!(R < hi)) R = 0.5 * (lo + hi);
+            } else {
+                // every radius below R is listed: narrow the bracket with the trial counts
+                // (summed in the same order as the Newton sums, so the signs agree)
+                hi = R;
+                neff_hi = neff;
+                const double f0 = c32 * st0 - ph.n_ngb, f1 = c32 * st1 - ph.n_ngb;
+                fa = NAN;
+                if (Ht[1] < hi && Ht[1] > lo) {
+                    if (f1 >= 0.0) hi = Ht[1], neff_hi = f1 + ph.n_ngb;
+                    else lo = Ht[1], fa = f1;
+                }
+                if (Ht[0] < hi && Ht[0] > lo) {
+                    if (f0 >= 0.0) hi = Ht[0], neff_hi = f0 + ph.n_ngb;
+                    else lo = Ht[0], fa = f0;
+                }
+                state = 1;
             }
         }
     }
     bool conv = false;
     double Hc = 0.0;
     if (state == 1) {
-        Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
+        // start from the secant of the bracket when both ends carry a residual,
+        // else from the density scaling of the upper end
+        const double fb = neff_hi - ph.n_ngb;
+        if (fa < 0.0 && fb >= 0.0) Hc = lo + (hi - lo) * (-fa / (fb - fa));
+        else Hc = (warm && guess > lo && guess < hi) ? guess : hi * cbrt(ph.n_ngb / neff_hi);
         if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
         conv = newton_h(rl, n, i, m, ph.n_ngb, ph.h_maxit, lo, hi, Hc, iters);
     }
@@ -271,6 +315,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         double sum = 0.0;
         const double iH = 1.0 / Hc;
         int c = 0;
+#pragma unroll 4
         for (int k = 0; k < m; k++) {
             const double r = rl[(long long)k * n + i];
             sum += spline_w(r * iH);
