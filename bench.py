@@ -1,16 +1,24 @@
-"""Benchmark of the gfx950 MFM hydro pass: unordered particle-pair interactions per
-second per hydro pass (kernel length + gradients + fluxes on particles already
-in the library's spatial order), FP64 and mixed precision.
+"""Benchmark of the gfx950 MFM hydro pass.
 
-    python bench.py [--steps K] [--warmup W] [--workload clustered|turbulence|...]
+    python bench.py [--steps K] [--warmup W] [--workload clustered|turbulence|shock_tube|...]
+    python bench.py --copy-probe        # plain device copy of known size (counter calibration)
 
-Prints one JSON line.  Inputs are seeded synthetic particle sets resident in
-HBM before timing starts; each timed step starts the kernel-length solve cold
-(H = 0), so every step redoes the whole pass.
+Metric: unordered particle-pair interactions per second per hydro pass (kernel
+length + gradients + fluxes on particles already in the library's spatial
+order), FP64, with the mixed form and its per-field error beside it, and the
+forward + adjoint time of 10 fixed-dt steps on the 64^3 jittered box.
+
+Inputs are seeded synthetic particle sets resident in HBM before timing starts.
+Every timed pass starts the kernel-length solve cold (H = 0), so each step
+redoes all of the pass's work.  Stage times come from HIP events on the stream
+the library launches on; the dominant kernel's own duration comes from the
+library's per-kernel event pairs (mfm_set_kernel_timing), which bracket that
+kernel alone on the same stream.  Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,12 +29,54 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic work and traffic per unit (derivation in the design document)
-FLOPS_PER_PAIR_FLUX = 236          # one unordered pair through faces, reconstruction, HLLC, flux
-BYTES_PER_PARTICLE_FLUX64 = 288    # FP64 flux kernel: record in, dp/dE/vsig out, list counts
-PEAK_FP64_VALU = 78.6e12
-PEAK_FP32_VALU = 157.3e12
-PEAK_HBM = 8.0e12
+METRIC = "particle-pair interactions/s per hydro pass, FP64 vs mixed at stated error; fwd+adj time"
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_FP64_VALU = 78.6e12   # flop/s, FP64 vector
+PEAK_FP32_VALU = 157.3e12  # flop/s, FP32 vector (packed)
+
+# Algorithmic work per unit (each particle's inputs read once and its outputs
+# written once; neighbour data are re-reads).  n particles, G gather entries
+# (self excluded), F directed flux-list entries (= 2 pairs), P unordered pairs.
+#   solve_h:   x (24 B) + H guess (8 B) in; H, n, V (24 B) + two list lengths (8 B)
+#              out; one 4 B index per gather entry.  Flops: distance and root
+#              (sqrt) 9 + two spline evaluations (f, f') 24 per gather entry.
+#   gradients: x, H, V, n, m, v, u (88 B) and the gather list in; B (48 B),
+#              rho, P (16 B), five gradients (120 B) out.  Flops: about 75 per
+#              gather entry (distance, W, E and the 15 weighted differences,
+#              extrema) and 200 per particle (inverse, products, limiter).
+#   fluxes:    x, H, V, B, rho, P, v, gradients (248 B) and the flux list in;
+#              dp, dE, vsig (40 B) out.  Flops: 236 per unordered pair (kernel
+#              weights 20, faces 52, reconstruction 70, frame 22, HLLC 31, flux
+#              6, distance 9, accumulation and signal speed 26), add/mul/div/sqrt
+#              counted as one and fma as two.
+def algorithmic(kernel, n, G, F, P):
+    if kernel == "solve_h":
+        return 64.0 * n + 4.0 * G, 33.0 * G
+    if kernel == "gradients":
+        return 272.0 * n + 4.0 * G, 75.0 * G + 200.0 * n
+    if kernel == "hydro_fluxes":
+        return 288.0 * n + 4.0 * F, 236.0 * P
+    raise KeyError(kernel)
+
+
+KERNEL_NAMES = {"solve_h": "k_solve_h", "gradients": "k_gradients<double>", "hydro_fluxes": "k_fluxes<double>"}
+KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/csrc/device.h",
+                  "paper_1712_01294_amd/csrc/kernels.h")
+
+# HBM traffic per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
+# this benchmark, scaled by what the same counters read for a plain copy of
+# known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
+# only for the kernel sources whose fingerprint is recorded with it.
+TRAFFIC = {}
+
+
+def source_fingerprint():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -44,15 +94,33 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
 
 
+def copy_probe():
+    """Five copies of a 1 GiB device buffer: 1 GiB fetched and 1 GiB written per launch."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": nbytes, "launches": 5}), flush=True)
+
+
 def timed_pass(ctx, st, steps, warmup, stream):
-    """Run warmup + steps passes; per stage HIP-event durations (ms) of the timed steps."""
+    """Warmup + timed passes, each from a cold kernel-length solve.  Returns the
+    mean per-stage HIP-event durations (ms) of the timed passes and the
+    per-kernel totals of the library's event pairs over the timed passes."""
     import torch
     stages = ("build", "solve_h", "gradients", "fluxes")
     acc = {k: [] for k in stages}
     for it in range(warmup + steps):
+        if it == warmup:
+            ctx.set_kernel_timing(True)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         st.H.zero_()
         ev[0].record(stream)
@@ -69,7 +137,12 @@ def timed_pass(ctx, st, steps, warmup, stream):
             for k, s in enumerate(stages):
                 acc[s].append(ev[k].elapsed_time(ev[k + 1]))
     torch.cuda.synchronize()
-    return {k: float(np.mean(v)) for k, v in acc.items()}
+    kern = {}
+    for k in ("solve_h", "gradients", "hydro_fluxes"):
+        ms, launches = ctx.kernel_time(k)
+        kern[k] = {"ms_total": ms, "launches": launches, "ms_avg": ms / max(launches, 1)}
+    ctx.set_kernel_timing(False)
+    return {k: float(np.mean(v)) for k, v in acc.items()}, kern
 
 
 def cpu_baseline(w, budget_s):
@@ -105,16 +178,66 @@ def cpu_baseline(w, budget_s):
                       f"particle they depend on; {out['pair_entries']} directed flux entries in {t:.1f} s"}
 
 
+def adjoint_timing(reps=3):
+    """Forward (initial pass + 10 fixed-dt steps with checkpoints) and backward
+    (hand-written adjoint with recomputation) on the 64^3 jittered box, FP64."""
+    import torch
+
+    from paper_1712_01294_amd import autodiff, workloads
+    w = workloads.adjoint_box()
+    evo = autodiff.Evolution(w, w.steps, w.dt)
+    m = torch.tensor(w.m, device="cuda")
+    v0 = torch.tensor(np.stack([w.vx, w.vy, w.vz]), device="cuda")
+    u0 = torch.tensor(w.u, device="cuda")
+    fw, bw = [], []
+    for it in range(reps + 1):
+        vr = v0.clone().requires_grad_(True)
+        ur = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vk, uk = autodiff.MFMSteps.apply(vr, ur, evo)
+        L = (m * (vk * vk).sum(0)).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    evo.ctx.check()
+    fwd, adj = float(np.median(fw)) * 1e3, float(np.median(bw)) * 1e3
+    return {"workload": f"jittered box 64^3 = {w.n} particles, {w.steps} fixed steps of dt = {w.dt}, "
+                        "L = sum m |v|^2 at the end, gradient w.r.t. (v0, u0)",
+            "fwd_ms": fwd, "adj_ms": adj, "fwd_adj_ms": fwd + adj, "reps": reps,
+            "note": "wall clock with the stream synchronised at both ends; forward keeps one checkpoint per step"}
+
+
+def run_precision(mfm, w, prec, kw, args, stream):
+    ctx = mfm.Context(mfm.config_of(w, precision=prec, **kw), w.n)
+    st = mfm.State.from_arrays(w.arrays(), ids=True)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    ctx.check(allow_illcond=True)
+    tm, kern = timed_pass(ctx, st, args.steps, args.warmup, stream)
+    ctx.check(allow_illcond=True)
+    cnt = ctx.counters()
+    return ctx, st, tm, kern, cnt
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import torch
+    assert torch.cuda.is_available(), "no GPU"
+    if args.copy_probe:
+        copy_probe()
+        return
 
     from paper_1712_01294_amd import mfm, workloads
-    assert torch.cuda.is_available(), "no GPU"
     t0 = time.time()
     w = workloads.by_name(args.workload)
     log(f"workload {w.name}: n={w.n} generated in {time.time() - t0:.1f}s")
@@ -124,65 +247,86 @@ def main():
     if args.max_ngb:
         kw["max_ngb"] = args.max_ngb
     stream = torch.cuda.current_stream()
-    res = {}
-    states = {}
-    for name, prec in (("fp64", mfm.FP64), ("mixed", mfm.MIXED)):
-        if name == "mixed" and args.no_mixed:
-            continue
-        ctx = mfm.Context(mfm.config_of(w, precision=prec, **kw), w.n)
-        st = mfm.State.from_arrays(w.arrays(), ids=True)
-        ctx.build_neighbours(st)
-        ctx.hydro_pass(st)
-        ctx.check(allow_illcond=True)
-        cnt = ctx.counters()
-        log(f"{name}: pairs={cnt['pairs']} list_max={cnt['list_max']} h_iters_max={cnt['h_iters_max']} "
-            f"h_rounds_max={cnt['h_rounds_max']} h_fallback={cnt['h_fallback']} "
-            f"fallbacks={cnt['fallbacks']} clamps={cnt['clamps']} illcond={cnt['illcond']}")
-        tm = timed_pass(ctx, st, args.steps, args.warmup, stream)
-        ctx.check(allow_illcond=True)
-        cnt = ctx.counters()
-        pass_ms = tm["solve_h"] + tm["gradients"] + tm["fluxes"]
-        res[name] = dict(stage_ms=tm, pass_ms=pass_ms, pairs=cnt["pairs"], counters=cnt)
-        states[name] = st
-        log(f"{name}: " + " ".join(f"{k}={v:.3f}ms" for k, v in tm.items()))
-        del ctx
-    f64 = res["fp64"]
-    pairs = f64["pairs"]
-    value = pairs / (f64["pass_ms"] * 1e-3)
-    flux_ms = f64["stage_ms"]["fluxes"]
-    achieved = FLOPS_PER_PAIR_FLUX * pairs / (flux_ms * 1e-3)
+
+    ctx, st64, tm, kern, cnt = run_precision(mfm, w, mfm.FP64, kw, args, stream)
+    log(f"fp64: pairs={cnt['pairs']} gather={cnt['gather_entries']} list_max={cnt['list_max']} "
+        f"h_rounds_max={cnt['h_rounds_max']} h_fallback={cnt['h_fallback']} illcond={cnt['illcond']} "
+        + " ".join(f"{k}={v:.3f}ms" for k, v in tm.items()))
+    del ctx
+    n, P, F, G = w.n, cnt["pairs"], cnt["list_entries"], cnt["gather_entries"]
+    pass_ms = tm["solve_h"] + tm["gradients"] + tm["fluxes"]
+
+    kernels = {}
+    for k, v in kern.items():
+        b, f = algorithmic(k, n, G, F, P)
+        s = v["ms_avg"] * 1e-3
+        kernels[k] = {"kernel": KERNEL_NAMES[k], "ms_avg": v["ms_avg"], "launches": v["launches"],
+                      "algorithmic_bytes": b, "algorithmic_flops": f,
+                      "GBps": b / s / 1e9, "frac_hbm": b / s / PEAK_HBM,
+                      "GFLOPps": f / s / 1e9, "frac_fp64": f / s / PEAK_FP64_VALU}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_avg"])
+    dk = kernels[dom]
+    fp = source_fingerprint()
+    tr = TRAFFIC.get((w.name, dom))
+    traffic = tr["bytes_per_launch"] if tr and tr["fingerprint"] == fp else None
+    # the pass is memory-side at algorithmic intensity (flop/B below the FP64 ridge)
+    roofline = {"kernel": dk["kernel"], "bound": "hbm", "achieved": dk["GBps"], "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": dk["frac_hbm"], "traffic": traffic,
+                "algorithmic_bytes_per_launch": dk["algorithmic_bytes"], "ms_avg": dk["ms_avg"],
+                "fp64_alu": {"achieved": dk["GFLOPps"] / 1e3, "peak": PEAK_FP64_VALU / 1e12,
+                             "unit": "TFLOP/s", "frac": dk["frac_fp64"]},
+                "source_fingerprint": fp}
+
     out = {
-        "metric": "particle-pair interactions/s per hydro pass (FP64; mixed alongside)",
-        "value": value,
+        "metric": METRIC,
+        "value": P / (pass_ms * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f64["pass_ms"],
+        "ms_per_step": pass_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_particles": w.n, "unordered_pairs": pairs,
-                   "n_ngb": w.n_ngb, "gamma": w.gamma, "box": list(w.box)},
-        "stage_ms": f64["stage_ms"],
-        "build_ms": f64["stage_ms"]["build"],
-        "value_incl_build": pairs / ((f64["pass_ms"] + f64["stage_ms"]["build"]) * 1e-3),
-        "roofline": {"kernel": "hydro_fluxes (FP64)", "bound": "alu", "achieved": achieved / 1e12,
-                     "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-                     "traffic": None, "flops_per_pair": FLOPS_PER_PAIR_FLUX},
+        "config": {"workload": w.name, "n_particles": n, "unordered_pairs": P, "gather_entries": G,
+                   "n_ngb": w.n_ngb, "gamma": w.gamma, "box": list(w.box), "h_start": "cold (H = 0)"},
+        "stage_ms": tm,
+        "value_incl_build": P / ((pass_ms + tm["build"]) * 1e-3),
+        "roofline": roofline,
+        "kernels": kernels,
     }
-    if "mixed" in res:
-        mx = res["mixed"]
-        a = {k: getattr(states["fp64"], k).cpu().numpy() for k in ("dp", "dE", "H", "grad", "B")}
-        b = {k: getattr(states["mixed"], k).cpu().numpy() for k in ("dp", "dE", "H", "grad", "B")}
-        same = np.array_equal(states["fp64"].id.cpu().numpy(), states["mixed"].id.cpu().numpy())
-        errs = {k: float(np.abs(a[k] - b[k]).max() / np.abs(a[k]).max()) for k in a} if same else None
-        out["mixed"] = {"value": mx["pairs"] / (mx["pass_ms"] * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
-                        "ms_per_step": mx["pass_ms"], "stage_ms": mx["stage_ms"],
-                        "speedup_vs_fp64": f64["pass_ms"] / mx["pass_ms"],
-                        "normwise_error_vs_fp64": errs}
+
+    if not args.no_mixed:
+        ctx, stmx, tmx, kmx, cmx = run_precision(mfm, w, mfm.MIXED, kw, args, stream)
+        del ctx
+        mx_ms = tmx["solve_h"] + tmx["gradients"] + tmx["fluxes"]
+        same = torch.equal(st64.id, stmx.id)
+        errs = None
+        if same:
+            errs = {}
+            for k in ("dp", "dE", "vsig", "grad", "B", "rho", "P", "H"):
+                a = getattr(st64, k).double()
+                b = getattr(stmx, k).double()
+                errs[k] = float((a - b).abs().max() / a.abs().max())
+        pm = torch.tensor([float((st64.dp[c]).sum()) for c in range(3)])
+        out["mixed"] = {"value": cmx["pairs"] / (mx_ms * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
+                        "ms_per_step": mx_ms, "stage_ms": tmx,
+                        "kernel_ms": {k: v["ms_avg"] for k, v in kmx.items()},
+                        "speedup_vs_fp64": pass_ms / mx_ms,
+                        "normwise_error_vs_fp64": errs,
+                        "momentum_sum_mixed": [float(stmx.dp[c].sum()) for c in range(3)],
+                        "momentum_sum_fp64": pm.tolist()}
+        log(f"mixed: " + " ".join(f"{k}={v:.3f}ms" for k, v in tmx.items()) + f" errs={errs}")
+        del stmx
+    del st64
+    torch.cuda.empty_cache()
+
+    if not args.no_adjoint:
+        log("adjoint ...")
+        out["adjoint"] = adjoint_timing()
+        log(f"adjoint: {out['adjoint']['fwd_ms']:.1f} ms fwd + {out['adjoint']['adj_ms']:.1f} ms adj")
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

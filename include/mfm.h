@@ -113,6 +113,7 @@ typedef struct {
     int64_t h_rounds_max;    /* most neighbour scans one kernel-length solve needed */
     int64_t h_fallback;      /* particles solved one by one (very long gather sets) */
     int64_t h_rounds3;       /* particles whose solve needed three or more scans    */
+    int64_t gather_entries;  /* gather-set entries of the last solve_h, self excluded */
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:
@@ -144,7 +145,10 @@ mfm_status mfm_solve_h(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * E_i = sum_j d_ij d_ij^T W(r_ij, H_i) V_i over the gather set;
  * B = E^-1 (FP64 adjugate); least-squares gradients of rho, v, P limited per
  * particle by alpha = min(1, beta min((max-phi)/(|g| d), (phi-min)/(|g| d))),
- * d = half the largest gather distance.  Requires mfm_solve_h. */
+ * d = half the largest gather distance.  Requires mfm_solve_h.
+ * MFM_MIXED: the pairwise kernel weights W are FP32; the moments E, the
+ * gradient sums and the inverse stay FP64; the per-particle record that the
+ * flux kernel reads (state, B, limited gradients) is stored in FP32. */
 mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* Fluxes (readings R9, R11-R16, R18): per unordered pair in canonical order
@@ -153,7 +157,9 @@ mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * moving with the mean particle velocity, HLLC star state with Davis speeds,
  * zero mass flux, momentum P* A, energy P* (S* + w.n)|A|, applied with
  * opposite signs to both particles.  vsig_i = max_j [c_i + c_j
- * - min(0, (v_i - v_j).(x_i - x_j)/r)].  Requires mfm_gradients. */
+ * - min(0, (v_i - v_j).(x_i - x_j)/r)].  Requires mfm_gradients.
+ * MFM_MIXED: displacements from FP64 positions, then kernel weights, faces,
+ * reconstruction and HLLC in FP32; the per-particle sums of dp and dE in FP64. */
 mfm_status mfm_hydro_fluxes(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* solve_h + gradients + hydro_fluxes on already-ordered particles. */
@@ -210,6 +216,24 @@ mfm_status mfm_copy_flux_lists(mfm_ctx *ctx, int32_t *counts, int32_t *list, voi
 
 /* Flux-list slot count chosen at creation (max_ngb). */
 int32_t mfm_max_ngb(const mfm_ctx *ctx);
+
+/*
+ * Kernel timing, a measurement aid outside the method itself.  While enabled,
+ * every launch of the three pass kernels (the kernel-length scan of
+ * mfm_solve_h, the gradient kernel of mfm_gradients, the flux kernel of
+ * mfm_hydro_fluxes) is bracketed by a pair of HIP events recorded on the
+ * call's stream, so the elapsed time is that kernel's alone.
+ *  - mfm_set_kernel_timing(ctx, 1) enables timing and zeroes the totals;
+ *    mfm_set_kernel_timing(ctx, 0) disables it.  Events are created by the
+ *    library on first use and released by mfm_destroy.
+ *  - mfm_kernel_time() waits for the recorded events and returns the summed
+ *    duration in milliseconds and the number of timed launches of one
+ *    kernel (an mfm_kernel value) since timing was last enabled.
+ *  - MFM_E_INVALID for a null pointer or an unknown kernel.
+ */
+typedef enum { MFM_KERNEL_SOLVE_H = 0, MFM_KERNEL_GRADIENTS = 1, MFM_KERNEL_FLUXES = 2 } mfm_kernel;
+mfm_status mfm_set_kernel_timing(mfm_ctx *ctx, int enable);
+mfm_status mfm_kernel_time(mfm_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
 
 const char *mfm_status_str(mfm_status s);
 const char *mfm_last_error(const mfm_ctx *ctx);

@@ -4,12 +4,21 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/mfm.h"
 #include "device.h"
 #include "kernels.h"
 
 using namespace mfm;
+
+// Optional per-kernel timing: HIP event pairs recorded around each launch of a
+// pass kernel on the caller's stream, summed when the caller asks for them.
+struct KernelClock {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, spare;
+    double total_ms = 0.0;
+    long long launches = 0;
+};
 
 struct mfm_ctx {
     mfm_params p;
@@ -35,8 +44,46 @@ struct mfm_ctx {
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
+    int timing = 0;
+    KernelClock clk[3];                   // indexed by mfm_kernel
     std::string err;
 };
+
+static void clock_drain(KernelClock& k) {
+    for (auto& e : k.pending) {
+        float ms = 0.0f;
+        hipEventSynchronize(e.second);
+        hipEventElapsedTime(&ms, e.first, e.second);
+        k.total_ms += ms;
+        k.launches++;
+        k.spare.push_back(e);
+    }
+    k.pending.clear();
+}
+
+// event pair for the next launch of kernel k (both null when timing is off)
+static std::pair<hipEvent_t, hipEvent_t> clock_take(mfm_ctx* c, int k) {
+    if (!c->timing) return {nullptr, nullptr};
+    KernelClock& kc = c->clk[k];
+    if (kc.pending.size() >= 256) clock_drain(kc);
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    if (!kc.spare.empty()) {
+        e = kc.spare.back();
+        kc.spare.pop_back();
+    } else if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) {
+        return {nullptr, nullptr};
+    }
+    kc.pending.push_back(e);
+    return e;
+}
+
+static void clock_reset(mfm_ctx* c) {
+    for (KernelClock& k : c->clk) {
+        clock_drain(k);
+        k.total_ms = 0.0;
+        k.launches = 0;
+    }
+}
 
 static mfm_status fail(mfm_ctx* c, mfm_status s, const std::string& m) {
     if (c) c->err = m;
@@ -135,6 +182,13 @@ void mfm_destroy(mfm_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
+    for (KernelClock& k : c->clk) {
+        clock_drain(k);
+        for (auto& e : k.spare) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+    }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
                     c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
@@ -302,8 +356,9 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->nk || !p->V) return fail(c, MFM_E_INVALID, "nk and V are required");
     if (c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_build_neighbours must run on these particles first");
     PassArrays a = arrays_of(p);
+    const auto ev = clock_take(c, MFM_KERNEL_SOLVE_H);
     launch_solve_h(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
-                   c->fb_list, c->fb_count, s);
+                   c->fb_list, c->fb_count, ev.first, ev.second, s);
     c->have_h = 1;
     c->have_grad = 0;
     c->last = s;
@@ -316,7 +371,10 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!c->have_h || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_solve_h must run first");
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
+    const auto ev = clock_take(c, MFM_KERNEL_GRADIENTS);
+    if (ev.first) hipEventRecord(ev.first, s);
     launch_gradients(a, c->ph, c->gcount, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    if (ev.second) hipEventRecord(ev.second, s);
     c->have_grad = 1;
     c->last = s;
     return launched(c, "gradients");
@@ -326,7 +384,10 @@ static mfm_status do_fluxes(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->dp || !p->dE || !p->vsig) return fail(c, MFM_E_INVALID, "dp, dE and vsig are required");
     if (!c->have_grad || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_gradients must run first");
     PassArrays a = arrays_of(p);
+    const auto ev = clock_take(c, MFM_KERNEL_FLUXES);
+    if (ev.first) hipEventRecord(ev.first, s);
     launch_fluxes(a, c->ph, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    if (ev.second) hipEventRecord(ev.second, s);
     c->have_flux = 1;
     c->last = s;
     return launched(c, "hydro_fluxes");
@@ -406,6 +467,23 @@ mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, vo
     return launched(c, "step");
 }
 
+mfm_status mfm_set_kernel_timing(mfm_ctx* c, int enable) {
+    if (!c) return MFM_E_INVALID;
+    hipSetDevice(c->device);
+    clock_reset(c);
+    c->timing = enable ? 1 : 0;
+    return MFM_OK;
+}
+
+mfm_status mfm_kernel_time(mfm_ctx* c, int kernel, double* total_ms, int64_t* launches) {
+    if (!c || kernel < 0 || kernel > 2 || !total_ms || !launches) return fail(c, MFM_E_INVALID, "bad kernel timing query");
+    hipSetDevice(c->device);
+    clock_drain(c->clk[kernel]);
+    *total_ms = c->clk[kernel].total_ms;
+    *launches = c->clk[kernel].launches;
+    return MFM_OK;
+}
+
 mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     if (!c || !out) return MFM_E_INVALID;
     hipSetDevice(c->device);
@@ -433,6 +511,7 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     out->h_rounds_max = (int64_t)h.h_rounds_max;
     out->h_fallback = (int64_t)h.h_fallback;
     out->h_rounds3 = (int64_t)h.h_rounds3;
+    out->gather_entries = (int64_t)h.gather_entries;
     return MFM_OK;
 }
 

@@ -58,6 +58,7 @@ struct Counters {
     unsigned long long h_rounds_max; // most group scans a kernel-length solve needed
     unsigned long long h_fallback;   // particles solved by the per-particle kernel
     unsigned long long h_rounds3;    // particles that needed three or more scans
+    unsigned long long gather_entries;  // sum of the gather-list lengths
 };
 
 // ---------------------------------------------------------------- kernel

@@ -509,9 +509,10 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
                                                      int* __restrict__ counts, int* __restrict__ list,
                                                      Counters* cnt) {
     const int i = xcd_block() * 256 + threadIdx.x;
-    unsigned long long c = 0, over = 0;
+    unsigned long long c = 0, over = 0, gsum = 0;
     if (i < n) {
         const int g = gcount[i];
+        gsum = (unsigned long long)g;
         int e = counts[i];
         c = (unsigned long long)e;
         if (e > cap) {
@@ -531,6 +532,7 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
         }
     }
     count_add(&cnt->list_entries, c);
+    count_add(&cnt->gather_entries, gsum);
     count_max(&cnt->list_max, c);
     count_add(&cnt->overflow, over);
 }
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
         for (int f = 0; f < 5; f++) pmax[f] = pmin[f] = phi_i[f];
         double rmax = 0.0;
         const double norm = kernel_norm(Hi), iH = 1.0 / Hi;
-        const float normf = (float)norm, iHf = (float)iH, Vif = (float)Vi;
+        const float normf = (float)norm, iHf = (float)iH;
         const int cnum = counts[i];
         for (int k = 0; k < cnum; k++) {
             const int j = list[(long long)k * n + i];
@@ -589,20 +591,22 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
                     S[3 * f + 2] += df * d[2];
                 }
             } else {
-                const float df3[3] = {(float)d[0], (float)d[1], (float)d[2]};
-                const float psi = normf * spline_w((float)r * iHf) * Vif;
-                E[0] += (double)(df3[0] * df3[0] * psi);
-                E[1] += (double)(df3[0] * df3[1] * psi);
-                E[2] += (double)(df3[0] * df3[2] * psi);
-                E[3] += (double)(df3[1] * df3[1] * psi);
-                E[4] += (double)(df3[1] * df3[2] * psi);
-                E[5] += (double)(df3[2] * df3[2] * psi);
+                // the pairwise kernel weight in FP32; the moments and sums in FP64, so
+                // that E and the gradient sums share one set of weights and the
+                // conditioning of E does not amplify per-product rounding
+                const double psi = (double)(normf * spline_w((float)r * iHf)) * Vi;
+                E[0] += d[0] * d[0] * psi;
+                E[1] += d[0] * d[1] * psi;
+                E[2] += d[0] * d[2] * psi;
+                E[3] += d[1] * d[1] * psi;
+                E[4] += d[1] * d[2] * psi;
+                E[5] += d[2] * d[2] * psi;
 #pragma unroll
                 for (int f = 0; f < 5; f++) {
-                    const float df = (float)(phi_j[f] - phi_i[f]) * psi;
-                    S[3 * f + 0] += (double)(df * df3[0]);
-                    S[3 * f + 1] += (double)(df * df3[1]);
-                    S[3 * f + 2] += (double)(df * df3[2]);
+                    const double df = (phi_j[f] - phi_i[f]) * psi;
+                    S[3 * f + 0] += df * d[0];
+                    S[3 * f + 1] += df * d[1];
+                    S[3 * f + 2] += df * d[2];
                 }
             }
 #pragma unroll
@@ -917,10 +921,13 @@ constexpr int kFallbackWaves = 1024;
 
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
-                    int* counts, int* fb_list, unsigned long long* fb_count, hipStream_t s) {
+                    int* counts, int* fb_list, unsigned long long* fb_count, hipEvent_t t0, hipEvent_t t1,
+                    hipStream_t s) {
     launch_fill_u64(1, fb_count, 0ull, s);
+    if (t0) hipEventRecord(t0, s);
     k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
                                                   fb_list, fb_count);
+    if (t1) hipEventRecord(t1, s);
     // one wave per handed-over particle, striding over the count the solve left on the device
     k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, list, gcount,
                                                      counts);

@@ -23,7 +23,10 @@ STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV",
 EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "mfm_gradients",
            "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
-           "mfm_hydro_pass_adjoint", "mfm_step_adjoint")
+           "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_set_kernel_timing", "mfm_kernel_time")
+
+# kernels that mfm_kernel_time can report (mfm_kernel)
+KERNELS = {"solve_h": 0, "gradients": 1, "hydro_fluxes": 2}
 
 
 class Params(C.Structure):
@@ -49,7 +52,7 @@ class Counters(C.Structure):
                                          "noconv", "minimage", "overflow", "illcond", "fallbacks",
                                          "clamps", "nonfinite", "floors", "first_bad")] + \
                [("cond_max_seen", C.c_double), ("h_rounds_max", C.c_int64), ("h_fallback", C.c_int64),
-                ("h_rounds3", C.c_int64)]
+                ("h_rounds3", C.c_int64), ("gather_entries", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +94,8 @@ def lib() -> C.CDLL:
         L.mfm_hydro_pass_adjoint.argtypes = [vp, C.POINTER(Particles), vp, vp, vp, vp, vp, vp]
         L.mfm_step_adjoint.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.c_double, vp, vp, vp,
                                        vp, vp, vp]
+        L.mfm_set_kernel_timing.argtypes = [vp, C.c_int]
+        L.mfm_kernel_time.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -254,6 +259,17 @@ class Context:
         c = Counters()
         self._rc(self._L.mfm_get_counters(self.h, C.byref(c)))
         return c.as_dict()
+
+    def set_kernel_timing(self, enable: bool = True):
+        """Bracket every launch of the three pass kernels with HIP events on the
+        call's stream (enabling also zeroes the totals)."""
+        self._rc(self._L.mfm_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, kernel: str):
+        """(total milliseconds, launches) of one pass kernel since timing was enabled."""
+        ms, k = C.c_double(), C.c_int64()
+        self._rc(self._L.mfm_kernel_time(self.h, KERNELS[kernel], C.byref(ms), C.byref(k)))
+        return ms.value, k.value
 
     def check(self, allow_illcond: bool = False):
         """Raise on device-side conditions.  With allow_illcond, ill-conditioned

@@ -166,6 +166,41 @@ def test_error_paths_forced_from_host(sine16):
     torch.cuda.synchronize()
 
 
+def test_kernel_timing_brackets_each_pass_kernel(sine16):
+    """The library's per-kernel event pairs: one timed launch per kernel and pass,
+    each kernel's time inside its stage's time, zero launches once disabled."""
+    import torch
+
+    from paper_1712_01294_amd import mfm
+    w, _ = sine16
+    ctx = mfm.Context(mfm.config_of(w), w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.set_kernel_timing(True)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(3):
+        ev[0].record(stream)
+        ctx.solve_h(st)
+        ev[1].record(stream)
+        ctx.gradients(st)
+        ev[2].record(stream)
+        ctx.hydro_fluxes(st)
+        ev[3].record(stream)
+    torch.cuda.synchronize()
+    stage = [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
+    for k, name in enumerate(("solve_h", "gradients", "hydro_fluxes")):
+        ms, launches = ctx.kernel_time(name)
+        assert launches == 3, (name, launches)
+        assert 0.0 < ms / 3 <= stage[k] * 1.05 + 0.05, (name, ms, stage[k])
+    ctx.set_kernel_timing(False)
+    ctx.hydro_pass(st)
+    assert ctx.kernel_time("solve_h") == (0.0, 0)
+    with pytest.raises(KeyError):
+        ctx.kernel_time("step")
+    ctx.check()
+
+
 def test_turbulence_full_size_sampled():
     """2,097,152 particles (128^3 Mach-2 turbulence): sampled oracle outputs at 24
     particles, and conservation over the whole set."""
