@@ -169,9 +169,13 @@ def cpu_baseline(w, budget_s):
         h = H[H > 0]
         return float(h.max()) * 1.5
 
-    t, out = run(2000)
-    k = int(min(w.n, max(2000, 2000 * budget_s / max(t, 1e-3))))
+    # grow the sample until one run takes a third of the budget (the cost per
+    # target rises with the sample, so a linear extrapolation overshoots)
+    k = 500
     t, out = run(k)
+    while t < budget_s / 3 and k < w.n:
+        k = int(min(w.n, 2 * k))
+        t, out = run(k)
     pairs = out["pair_entries"] / 2.0
     return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} targets nearest one box corner of the same {w.n}-particle set, with every "
