@@ -169,13 +169,17 @@ def cpu_baseline(w, budget_s):
         h = H[H > 0]
         return float(h.max()) * 1.5
 
-    # grow the sample until one run takes a third of the budget (the cost per
-    # target rises with the sample, so a linear extrapolation overshoots)
+    # double the sample while the next run, extrapolated with the growth of the
+    # last doubling, stays within the budget (the dependency closure, and so the
+    # cost per target, grows with the largest kernel length in the sample)
     k = 500
     t, out = run(k)
-    while t < budget_s / 3 and k < w.n:
-        k = int(min(w.n, 2 * k))
-        t, out = run(k)
+    growth = 2.0
+    while k < w.n and t * growth <= budget_s:
+        t_prev = t
+        t_new, out_new = run(int(min(w.n, 2 * k)))
+        k, t, out = int(min(w.n, 2 * k)), t_new, out_new
+        growth = max(2.0, t / max(t_prev, 1e-9))
     pairs = out["pair_entries"] / 2.0
     return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} targets nearest one box corner of the same {w.n}-particle set, with every "
