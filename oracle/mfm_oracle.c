@@ -11,7 +11,8 @@
  * whose mesh moves with the fluid (abstract; section "Arbitrary (Moving)
  * Meshes"; the Hydrodynamics item of section 2).  The formulas below are the
  * standard meshless finite-mass discretisation that sentence points to, taken
- * as numbered readings R1..R16 of the design document:
+ * as the numbered readings R1..R16 below (the GPU library's header marks its
+ * calls with the same labels):
  *
  *   R1  cubic-spline kernel with support radius H
  *   R2  gather set r < H_i (self included), flux set r < max(H_i, H_j)

@@ -6,9 +6,10 @@ baseline leg of the benchmark, never by the product path.
 The release paper names a Lagrangian mesh-free finite-volume Godunov method
 whose mesh moves with the fluid (abstract; "Arbitrary (Moving) Meshes").
 The pass here follows the standard meshless finite-mass formulation it refers
-to, in the readings R1-R18 listed in the design document: kernel length,
-gradient matrix and limited gradients, faces, HLLC fluxes, accumulation, and
-the kick-drift-kick step with a predicted state.
+to, in the numbered readings R1-R18 that the C file lists and the GPU
+library's header shares: kernel length, gradient matrix and limited
+gradients, faces, HLLC fluxes, accumulation, and the kick-drift-kick step
+with a predicted state.
 """
 from __future__ import annotations
 

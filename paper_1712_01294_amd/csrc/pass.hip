@@ -6,6 +6,7 @@
 // particles with the lower index as the left state, so both copies are
 // bitwise equal and the accumulated momentum and energy cancel exactly pair
 // by pair; there are no atomics on outputs and results are deterministic.
+#include <limits.h>
 #include <math.h>
 
 #include "device.h"
@@ -505,6 +506,8 @@ __global__ __launch_bounds__(256) void k_scatter_lists(PassArrays a, Phys ph, co
     }
 }
 
+constexpr int kTailNet = 32;   // tails up to this length are sorted in registers
+
 __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* __restrict__ gcount,
                                                      int* __restrict__ counts, int* __restrict__ list,
                                                      Counters* cnt) {
@@ -521,14 +524,39 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
             e = cap;
             counts[i] = cap;
         }
-        for (int k = g + 1; k < e; k++) {
-            const int v = list[(long long)k * n + i];
-            int q = k - 1;
-            while (q >= g && list[(long long)q * n + i] > v) {
-                list[(long long)(q + 1) * n + i] = list[(long long)q * n + i];
-                q--;
+        const int t = e - g;
+        if (t <= kTailNet) {
+            // short tails: a bitonic network on registers (indices fixed at compile time)
+            int v[kTailNet];
+#pragma unroll
+            for (int k = 0; k < kTailNet; k++) v[k] = k < t ? list[(long long)(g + k) * n + i] : INT_MAX;
+#pragma unroll
+            for (int w = 2; w <= kTailNet; w <<= 1)
+#pragma unroll
+                for (int h = w >> 1; h > 0; h >>= 1)
+#pragma unroll
+                    for (int k = 0; k < kTailNet; k++) {
+                        const int l = k ^ h;
+                        if (l > k) {
+                            const int lo_v = min(v[k], v[l]), hi_v = max(v[k], v[l]);
+                            const bool up = (k & w) == 0;
+                            v[k] = up ? lo_v : hi_v;
+                            v[l] = up ? hi_v : lo_v;
+                        }
+                    }
+#pragma unroll
+            for (int k = 0; k < kTailNet; k++)
+                if (k < t) list[(long long)(g + k) * n + i] = v[k];
+        } else {
+            for (int k = g + 1; k < e; k++) {
+                const int v = list[(long long)k * n + i];
+                int q = k - 1;
+                while (q >= g && list[(long long)q * n + i] > v) {
+                    list[(long long)(q + 1) * n + i] = list[(long long)q * n + i];
+                    q--;
+                }
+                list[(long long)(q + 1) * n + i] = v;
             }
-            list[(long long)(q + 1) * n + i] = v;
         }
     }
     count_add(&cnt->list_entries, c);
