@@ -86,10 +86,16 @@ def test_fixed_dt_steps_conserve_on_jittered_box():
 
 def test_shock_tube_full_size_against_exact_riemann():
     """The 294,912-particle tube (left 256 x 32 x 32 at spacing 1/256, right at
-    1/128), 50 CFL steps: between the contact and the shock the particles carry
-    the exact star velocity, pressure and density to a few per cent, the shock
-    sits within two right-hand spacings of the exact one, and momentum along the
-    tube stays at round-off (reported convergence check, not parity)."""
+    1/128), 50 CFL steps: a convergence check against the exact Riemann solution
+    (reported, not parity).  At t = 0.036 the post-shock gas between the contact
+    and the shock spans about eight lattice planes, and the run is sensitive to
+    round-off there: a 1e-14 perturbation of the initial velocities moves the
+    mean over the middle 40% of that region between v = 0.836 and 0.886 and
+    between P = 0.294 and 0.321 (measured; exact 0.841 and 0.294).  The bands
+    are therefore 8% on v and rho and 12% on P.  The binned velocity profile on
+    0.9 <= x <= 1.15 must stay within a mean absolute error of 0.07 (measured
+    0.028-0.045).  The shock sits within two right-hand spacings of the exact
+    one, and momentum along the tube stays at round-off."""
     w = W.shock_tube()
     ctx, st, dts = _gpu_run(w, 50)
     t = float(np.sum(dts))
@@ -104,12 +110,19 @@ def test_shock_tube_full_size_against_exact_riemann():
     lo = 1.0 + (u + 0.3 * (S - u)) * t
     hi = 1.0 + (S - 0.3 * (S - u)) * t
     sel = (x > lo) & (x < hi)
+    bins = np.linspace(0.9, 1.15, 26)
+    xc = 0.5 * (bins[1:] + bins[:-1])
+    exact_v = R.sample(LEFT, RIGHT, gam, (xc - 1.0) / t)[1]
+    b = np.digitize(x, bins) - 1
+    prof = np.array([vx[b == k].mean() for k in range(len(xc))])
+    l1 = float(np.mean(np.abs(prof - exact_v)))
     print(f"t={t:.5f} n_sel={sel.sum()} v={vx[sel].mean():.4f} (exact {u:.4f}) "
-          f"P={P[sel].mean():.4f} ({p:.4f}) rho={rho[sel].mean():.4f} ({rr:.4f})", flush=True)
+          f"P={P[sel].mean():.4f} ({p:.4f}) rho={rho[sel].mean():.4f} ({rr:.4f}) L1(v)={l1:.4f}", flush=True)
     assert sel.sum() > 300
-    assert vx[sel].mean() == pytest.approx(u, rel=0.05)
-    assert P[sel].mean() == pytest.approx(p, rel=0.08)
+    assert vx[sel].mean() == pytest.approx(u, rel=0.08)
+    assert P[sel].mean() == pytest.approx(p, rel=0.12)
     assert rho[sel].mean() == pytest.approx(rr, rel=0.08)
+    assert l1 <= 0.07
     order = np.argsort(x)
     xs, rs = x[order], rho[order]
     win = (xs > 1.0 + u * t) & (xs < 1.5)
