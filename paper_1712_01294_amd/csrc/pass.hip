@@ -567,8 +567,13 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 
 // ---------------------------------------------------------------- gradients
 // Record of one particle for the flux kernel (32 slots, one or two cache lines):
-// 0-2 x, y, z (FP64 record only) | 3 H | 4 V | 5 rho | 6 P | 7-9 v | 10-15 B | 16-30 grad | 31 c
-enum { R_X = 0, R_H = 3, R_V = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
+// 0-2 x, y, z (FP64 record only) | 3 1/H | 4 K = V^2 8/(pi H^3) | 5 rho | 6 P | 7-9 v | 10-15 B |
+// 16-30 grad | 31 c.  With 1/H and K per particle a face needs no division for its kernel weights:
+// V^2 W(r, H) = K w(r/H).
+#ifndef MFM_FLUX32_WAVES
+#define MFM_FLUX32_WAVES 4
+#endif
+enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ counts,
@@ -717,8 +722,8 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
             v[0] = xi[0];
             v[1] = xi[1];
             v[2] = xi[2];
-            v[R_H] = Hi;
-            v[R_V] = Vi;
+            v[R_IH] = iH;
+            v[R_K] = Vi * Vi * norm;
             v[R_RHO] = rho_i;
             v[R_P] = P_i;
             v[R_V0 + 0] = phi_i[1];
@@ -736,8 +741,8 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
             float* rec = (float*)recp + (long long)i * 32;
             float v[32];
             v[0] = v[1] = v[2] = 0.0f;
-            v[R_H] = (float)Hi;
-            v[R_V] = (float)Vi;
+            v[R_IH] = (float)iH;
+            v[R_K] = (float)(Vi * Vi * norm);
             v[R_RHO] = (float)rho_i;
             v[R_P] = (float)P_i;
             v[R_V0 + 0] = (float)phi_i[1];
@@ -774,67 +779,91 @@ template <>
 __device__ __forceinline__ float tsqrt<float>(float v) { return sqrtf(v); }
 
 // One unordered pair, left state a (lower index), right state b, d = x_b - x_a.
+// products and sums rounded one by one (contraction into fma is switched off
+// here): the face sum is then the same bits whichever owner evaluates it
 template <typename T>
-__device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ a, const T* __restrict__ b, const T d[3],
-                                                T r, T gamma) {
-    PairOut<T> o;
-    o.Fp[0] = o.Fp[1] = o.Fp[2] = o.FE = T(0);
-    o.fallback = o.clamp = 0;
-    const T Ha = a[R_H], Hb = b[R_H];
-    const T Wa = kernel_norm(Ha) * spline_w(r / Ha);
-    const T Wb = kernel_norm(Hb) * spline_w(r / Hb);
-    const T* Ba = a + R_B;
-    const T* Bb = b + R_B;
-    const T ta[3] = {Ba[0] * d[0] + Ba[1] * d[1] + Ba[2] * d[2], Ba[1] * d[0] + Ba[3] * d[1] + Ba[4] * d[2],
-                     Ba[2] * d[0] + Ba[4] * d[1] + Ba[5] * d[2]};
-    const T tb[3] = {Bb[0] * d[0] + Bb[1] * d[1] + Bb[2] * d[2], Bb[1] * d[0] + Bb[3] * d[1] + Bb[4] * d[2],
-                     Bb[2] * d[0] + Bb[4] * d[1] + Bb[5] * d[2]};
-    const T ka = a[R_V] * a[R_V] * Wa, kb = b[R_V] * b[R_V] * Wb;
+__device__ __forceinline__ T mul_rn(T x, T y) {
+#pragma clang fp contract(off)
+    return x * y;
+}
+template <typename T>
+__device__ __forceinline__ T add_rn(T x, T y) {
+#pragma clang fp contract(off)
+    return x + y;
+}
+
+// One unordered pair in canonical order (the lower index is the left state),
+// evaluated by the owner `m` of one side with the record `o` of the other; mL
+// says whether m is the left side, d = x_R - x_L is the canonical displacement
+// and r its length.  Every per-side quantity is written with one expression
+// for that side (left: +1/2, right: -1/2 along d), and the sum of the two
+// face halves is commutative and unfused, so both owners produce the same
+// bits; only the reconstructed face states are put in left/right order.
+template <typename T>
+__device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T* __restrict__ o, bool mL,
+                                                const T d[3], T r, T gamma) {
+    PairOut<T> out;
+    out.Fp[0] = out.Fp[1] = out.Fp[2] = out.FE = T(0);
+    out.fallback = out.clamp = 0;
+    // face A = V_m^2 W_m B_m d + V_o^2 W_o B_o d (the kernel factor K = V^2 8/(pi H^3))
+    const T km = m[R_K] * spline_w(r * m[R_IH]);
+    const T ko = o[R_K] * spline_w(r * o[R_IH]);
+    const T* Bm = m + R_B;
+    const T* Bo = o + R_B;
+    const T tm[3] = {Bm[0] * d[0] + Bm[1] * d[1] + Bm[2] * d[2], Bm[1] * d[0] + Bm[3] * d[1] + Bm[4] * d[2],
+                     Bm[2] * d[0] + Bm[4] * d[1] + Bm[5] * d[2]};
+    const T to[3] = {Bo[0] * d[0] + Bo[1] * d[1] + Bo[2] * d[2], Bo[1] * d[0] + Bo[3] * d[1] + Bo[4] * d[2],
+                     Bo[2] * d[0] + Bo[4] * d[1] + Bo[5] * d[2]};
     T A[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) A[c] = ka * ta[c] + kb * tb[c];
+    for (int c = 0; c < 3; c++) A[c] = add_rn(mul_rn(km, tm[c]), mul_rn(ko, to[c]));
     const T Amag = tsqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-    if (!(Amag > T(0))) return o;
-    const T nh[3] = {A[0] / Amag, A[1] / Amag, A[2] / Amag};
+    if (!(Amag > T(0))) return out;
+    const T iA = T(1) / Amag;
+    const T nh[3] = {A[0] * iA, A[1] * iA, A[2] * iA};
 
-    // midpoint reconstruction of rho, vx, vy, vz, P
+    // midpoint reconstruction of rho, vx, vy, vz, P on each side
     const int slot[5] = {R_RHO, R_V0, R_V0 + 1, R_V0 + 2, R_P};
+    const T sm = mL ? T(0.5) : T(-0.5);
     T qL[5], qR[5];
 #pragma unroll
     for (int f = 0; f < 5; f++) {
-        const T* ga = a + R_G + 3 * f;
-        const T* gb = b + R_G + 3 * f;
-        qL[f] = a[slot[f]] + T(0.5) * (ga[0] * d[0] + ga[1] * d[1] + ga[2] * d[2]);
-        qR[f] = b[slot[f]] - T(0.5) * (gb[0] * d[0] + gb[1] * d[1] + gb[2] * d[2]);
+        const T* gm = m + R_G + 3 * f;
+        const T* go = o + R_G + 3 * f;
+        const T qm = m[slot[f]] + sm * (gm[0] * d[0] + gm[1] * d[1] + gm[2] * d[2]);
+        const T qo = o[slot[f]] + (-sm) * (go[0] * d[0] + go[1] * d[1] + go[2] * d[2]);
+        qL[f] = mL ? qm : qo;
+        qR[f] = mL ? qo : qm;
     }
     if (!(qL[0] > T(0)) || !(qL[4] > T(0)) || !(qR[0] > T(0)) || !(qR[4] > T(0))) {
 #pragma unroll
         for (int f = 0; f < 5; f++) {
-            qL[f] = a[slot[f]];
-            qR[f] = b[slot[f]];
+            qL[f] = mL ? m[slot[f]] : o[slot[f]];
+            qR[f] = mL ? o[slot[f]] : m[slot[f]];
         }
-        o.fallback = 1;
+        out.fallback = 1;
     }
-    const T w[3] = {T(0.5) * (a[R_V0] + b[R_V0]), T(0.5) * (a[R_V0 + 1] + b[R_V0 + 1]),
-                    T(0.5) * (a[R_V0 + 2] + b[R_V0 + 2])};
+    // face frame: the mean of the two particle velocities (commutative)
+    const T w[3] = {T(0.5) * (m[R_V0] + o[R_V0]), T(0.5) * (m[R_V0 + 1] + o[R_V0 + 1]),
+                    T(0.5) * (m[R_V0 + 2] + o[R_V0 + 2])};
     const T uL = (qL[1] - w[0]) * nh[0] + (qL[2] - w[1]) * nh[1] + (qL[3] - w[2]) * nh[2];
     const T uR = (qR[1] - w[0]) * nh[0] + (qR[2] - w[1]) * nh[1] + (qR[3] - w[2]) * nh[2];
     const T rL = qL[0], pL = qL[4], rR = qR[0], pR = qR[4];
     const T cL = tsqrt(gamma * pL / rL), cR = tsqrt(gamma * pR / rR);
     const T SL = (uL - cL < uR - cR) ? uL - cL : uR - cR;
     const T SR = (uL + cL > uR + cR) ? uL + cL : uR + cR;
-    const T mL = rL * (SL - uL), mR = rR * (SR - uR);
-    const T Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
-    T Ps = T(0.5) * (pL + pR + mL * (Ss - uL) + mR * (Ss - uR));
+    const T mLf = rL * (SL - uL), mRf = rR * (SR - uR);
+    const T Ss = (pR - pL + mLf * uL - mRf * uR) / (mLf - mRf);
+    T Ps = T(0.5) * (pL + pR + mLf * (Ss - uL) + mRf * (Ss - uR));
     if (Ps < T(0)) {
         Ps = T(0);
-        o.clamp = 1;
+        out.clamp = 1;
     }
     const T wn = w[0] * nh[0] + w[1] * nh[1] + w[2] * nh[2];
 #pragma unroll
-    for (int c = 0; c < 3; c++) o.Fp[c] = Ps * A[c];
-    o.FE = Ps * (Ss + wn) * Amag;
-    return o;
+    for (int c = 0; c < 3; c++) out.Fp[c] = Ps * A[c];
+    out.FE = Ps * (Ss + wn) * Amag;
+    return out;
 }
 
 template <typename T>
@@ -863,9 +892,9 @@ __device__ __forceinline__ void load_rec<float>(const float* __restrict__ rec, l
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int* __restrict__ counts,
-                                                 const int* __restrict__ list, const T* __restrict__ rec,
-                                                 Counters* cnt) {
+__device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
+                                            const int* __restrict__ list, const T* __restrict__ rec,
+                                            Counters* cnt) {
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
     unsigned long long nfall = 0, nclamp = 0, nonfin = 0;
@@ -898,24 +927,11 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
             displacement(ph, xi, xj[0], xj[1], xj[2], dij);   // x_j - x_i
             const double r = sqrt(dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2]);
             const bool iL = i < j;
-            T L[32], R[32];
-#pragma unroll
-            for (int f = 0; f < 32; f++) {
-                L[f] = iL ? ri[f] : rj[f];
-                R[f] = iL ? rj[f] : ri[f];
-            }
-            // canonical displacement x_R - x_L, computed from the canonical pair
-            double dLR[3];
-            if (iL) {
-                dLR[0] = dij[0];
-                dLR[1] = dij[1];
-                dLR[2] = dij[2];
-            } else {
-                displacement(ph, xj, xi[0], xi[1], xi[2], dLR);
-            }
-            const double rLR = sqrt(dLR[0] * dLR[0] + dLR[1] * dLR[1] + dLR[2] * dLR[2]);
-            const T dT[3] = {(T)dLR[0], (T)dLR[1], (T)dLR[2]};
-            PairOut<T> o = pair_flux<T>(L, R, dT, (T)rLR, gam);
+            // canonical displacement x_R - x_L: the minimum image commutes with
+            // negation exactly, so both owners of the pair hold the same bits
+            const double sg = iL ? 1.0 : -1.0;
+            const T dT[3] = {(T)(sg * dij[0]), (T)(sg * dij[1]), (T)(sg * dij[2])};
+            PairOut<T> o = pair_flux<T>(ri, rj, iL, dT, (T)r, gam);
             const double s = iL ? 1.0 : -1.0;
             acc[0] -= s * (double)o.Fp[0];
             acc[1] -= s * (double)o.Fp[1];
@@ -941,6 +957,20 @@ __global__ __launch_bounds__(256) void k_fluxes(PassArrays a, Phys ph, const int
     count_add(&cnt->fallbacks, nfall);
     count_add(&cnt->clamps, nclamp);
     count_add(&cnt->nonfinite, nonfin);
+}
+
+// One kernel per record precision: each pair holds both records in registers,
+// and the FP32 form fits four waves per SIMD where the FP64 form fits two.
+__global__ __launch_bounds__(256) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                    const int* __restrict__ list, const double* __restrict__ rec,
+                                                    Counters* cnt) {
+    fluxes_body<double>(a, ph, counts, list, rec, cnt);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
+void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
+                  const float* __restrict__ rec, Counters* cnt) {
+    fluxes_body<float>(a, ph, counts, list, rec, cnt);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -974,9 +1004,9 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, co
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
                    const void* rec, Counters* cnt, hipStream_t s) {
     if (mixed)
-        k_fluxes<float><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+        k_fluxes_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
     else
-        k_fluxes<double><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+        k_fluxes_f64<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
 }
 
 }  // namespace mfm
