@@ -42,9 +42,10 @@ PEAK_FP32_VALU = 157.3e12  # flop/s, FP32 vector (packed)
 #              out; one 4 B index per gather entry.  Flops: distance and root
 #              (sqrt) 9 + two spline evaluations (f, f') 24 per gather entry.
 #   gradients: x, H, V, n, m, v, u (88 B) and the gather list in; B (48 B),
-#              rho, P (16 B), five gradients (120 B) out.  Flops: about 75 per
-#              gather entry (distance, W, E and the 15 weighted differences,
-#              extrema) and 200 per particle (inverse, products, limiter).
+#              rho, P (16 B), five gradients (120 B) and the transposed flux-list
+#              entries (4 B each) out.  Flops: about 75 per gather entry
+#              (distance, W, E and the 15 weighted differences, extrema) and 200
+#              per particle (inverse, products, limiter).
 #   fluxes:    x, H, V, B, rho, P, v, gradients (248 B) and the flux list in;
 #              dp, dE, vsig (40 B) out.  Flops: 236 per unordered pair (kernel
 #              weights 20, faces 52, reconstruction 70, frame 22, HLLC 31, flux
@@ -54,7 +55,7 @@ def algorithmic(kernel, n, G, F, P):
     if kernel == "solve_h":
         return 64.0 * n + 4.0 * G, 33.0 * G
     if kernel == "gradients":
-        return 272.0 * n + 4.0 * G, 75.0 * G + 200.0 * n
+        return 272.0 * n + 4.0 * F, 75.0 * G + 200.0 * n
     if kernel == "hydro_fluxes":
         return 288.0 * n + 4.0 * F, 236.0 * P
     raise KeyError(kernel)

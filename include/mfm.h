@@ -137,8 +137,9 @@ mfm_status mfm_build_neighbours(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * (4 pi/3) H^3 n_i(H) = n_ngb, n_i(H) = sum_{r_ij < H} W(r_ij, H) with the
  * cubic spline of support H; nk = n_i(H_i), V = 1/nk.  FP64 in both
  * precisions.  H in: a guess (<= 0: from the local cell density).
- * Requires mfm_build_neighbours on the current positions.  Also builds the
- * flux lists (r < max(H_i, H_j)) used by the next two calls. */
+ * Requires mfm_build_neighbours on the current positions.  Also builds each
+ * particle's gather list (r < H_i, self excluded), which mfm_gradients
+ * completes into the flux list (r < max(H_i, H_j)) used by mfm_hydro_fluxes. */
 mfm_status mfm_solve_h(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* Gradients (readings R5-R8, R10): rho = m nk, P = (gamma-1) rho u;
@@ -209,7 +210,8 @@ mfm_status mfm_get_counters(mfm_ctx *ctx, mfm_counters *out);
  * MFM_E_ILLCOND, in that order of precedence; MFM_OK otherwise. */
 mfm_status mfm_check(mfm_ctx *ctx);
 
-/* Copy the flux lists of the last mfm_solve_h into caller device buffers:
+/* Copy the flux lists (complete once mfm_gradients has run after the last
+ * mfm_solve_h; MFM_E_STATE before) into caller device buffers:
  * counts[i] (int32, n) and list[k * n + i] (int32, max_ngb x n) = index j of
  * the k-th entry of particle i, in the current particle order. */
 mfm_status mfm_copy_flux_lists(mfm_ctx *ctx, int32_t *counts, int32_t *list, void *stream);

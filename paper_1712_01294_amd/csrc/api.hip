@@ -372,9 +372,8 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
     const auto ev = clock_take(c, MFM_KERNEL_GRADIENTS);
-    if (ev.first) hipEventRecord(ev.first, s);
-    launch_gradients(a, c->ph, c->gcount, c->list, c->rec_mixed, c->rec, c->cnt, s);
-    if (ev.second) hipEventRecord(ev.second, s);
+    launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, ev.first, ev.second,
+                     s);
     c->have_grad = 1;
     c->last = s;
     return launched(c, "gradients");
@@ -550,7 +549,7 @@ mfm_status mfm_check(mfm_ctx* c) {
 
 mfm_status mfm_copy_flux_lists(mfm_ctx* c, int32_t* counts, int32_t* list, void* stream) {
     if (!c || !counts || !list) return MFM_E_INVALID;
-    if (!c->have_h) return fail(c, MFM_E_STATE, "no flux lists yet");
+    if (!c->have_grad) return fail(c, MFM_E_STATE, "no flux lists yet (they are complete after mfm_gradients)");
     hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     const long long n = c->n_tree;

@@ -480,32 +480,10 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
 
 // --------------------------------------------------------------- flux lists
 // The flux set r < max(H_i, H_j) is the gather set of i plus every j that has
-// i in its gather set with r >= H_i.  Each j walks its own gather list and
-// appends itself to such i (atomic slot), then each list sorts its appended
-// tail by index so the list, and every sum over it, is deterministic.
-__global__ __launch_bounds__(256) void k_scatter_lists(PassArrays a, Phys ph, const double4* __restrict__ pos,
-                                                        const int* __restrict__ gcount, int* __restrict__ counts,
-                                                        int* __restrict__ list) {
-    const int j = xcd_block() * 256 + threadIdx.x;
-    if (j >= a.n) return;
-    const long long n = a.n;
-    const int cap = ph.max_ngb;
-    const double4 pj = pos[j];
-    const double xj[3] = {pj.x, pj.y, pj.z};
-    const int g = gcount[j];
-    for (int k = 0; k < g; k++) {
-        const int i = list[(long long)k * n + j];
-        const double4 p = pos[i];
-        double d[3];
-        displacement(ph, xj, p.x, p.y, p.z, d);
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        if (!(r < a.H[i])) {
-            const int slot = atomicAdd(&counts[i], 1);
-            if (slot < cap) list[(long long)slot * n + i] = j;
-        }
-    }
-}
-
+// i in its gather set with r >= H_i.  The gradient kernel, which walks every
+// gather list anyway, appends each such j to i's list (atomic slot); then each
+// list sorts its appended tail by index so the list, and every sum over it, is
+// deterministic.
 constexpr int kTailNet = 32;   // tails up to this length are sorted in registers
 
 __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* __restrict__ gcount,
@@ -576,9 +554,9 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ counts,
-                                                    const int* __restrict__ list, void* __restrict__ recp,
-                                                    Counters* cnt) {
+__global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                                                    int* __restrict__ counts, int* __restrict__ list,
+                                                    void* __restrict__ recp, Counters* cnt) {
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
     unsigned long long ill = 0, nonfin = 0, condbits = 0;
@@ -599,13 +577,19 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
         double rmax = 0.0;
         const double norm = kernel_norm(Hi), iH = 1.0 / Hi;
         const float normf = (float)norm, iHf = (float)iH;
-        const int cnum = counts[i];
+        const int cnum = gcount[i];
+        const int cap = ph.max_ngb;
         for (int k = 0; k < cnum; k++) {
             const int j = list[(long long)k * n + i];
             double d[3];
             displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < Hi)) continue;   // flux-only neighbour: outside the gather set
+            if (!(r < a.H[j])) {
+                // i is outside j's gather set: the pair enters j's flux list as a
+                // tail entry (slots past the gather part, sorted afterwards)
+                const int slot = atomicAdd(&counts[j], 1);
+                if (slot < cap) list[(long long)slot * n + j] = i;
+            }
             const double rho_j = a.m[j] * a.nk[j];
             const double phi_j[5] = {rho_j, a.vx[j], a.vy[j], a.vz[j], (ph.gamma - 1.0) * rho_j * a.u[j]};
             if (!MIXED) {
@@ -989,16 +973,17 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
     // one wave per handed-over particle, striding over the count the solve left on the device
     k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, list, gcount,
                                                      counts);
-    k_scatter_lists<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, pos, gcount, counts, list);
-    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
 }
 
-void launch_gradients(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
-                      void* rec, Counters* cnt, hipStream_t s) {
+void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
+                      void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+    if (t0) hipEventRecord(t0, s);
     if (mixed)
-        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, rec, cnt);
+        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, rec, cnt);
     else
-        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, rec, cnt);
+        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, rec, cnt);
+    if (t1) hipEventRecord(t1, s);
+    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
 }
 
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
