@@ -143,6 +143,8 @@ __device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, c
     return cbrt(3.0 * n_ngb * b.vol / (4.0 * M_PI * fmax(b.count, 1.0)));
 }
 
+constexpr double kNewtonTail = 1e-9;   // last Newton step accepted without a check pass
+
 // safeguarded Newton on the m radii rl[k * n + i]; returns converged
 __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int m, double n_ngb, int maxit,
                          double& lo, double& hi, double& Hc, unsigned long long& iters) {
@@ -163,9 +165,13 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
         else hi = Hc;
         const double fp = -c32 * sq * iH;
         double Hn = Hc - f / fp;
-        // a converged step is taken even at a bracket edge: an earlier iterate
-        // can land on the root and become lo or hi
-        if (fabs(Hn - Hc) <= 1e-14 * Hc) {
+        // The sum is twice continuously differentiable in H (so is the spline),
+        // so Newton converges quadratically: after a step below kNewtonTail H the
+        // new iterate is within a small multiple of kNewtonTail^2 H (a few 1e-18
+        // relative) of the root and is returned without another pass.  It is
+        // taken even at a bracket edge: an earlier iterate can land on the root
+        // and become lo or hi.
+        if (fabs(Hn - Hc) <= kNewtonTail * Hc) {
             Hc = fmin(hi, fmax(lo, Hn));
             return true;
         }
@@ -182,6 +188,16 @@ constexpr int kScanRounds = 12;   // scans per particle before the fallback take
 #define MFM_COLD_PAD 1.25
 #endif
 constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
+// a scan pass takes the lanes with R >= kClassRatio Rref within kClassWindow Rref
+// of the first of them on every axis (Rref: the largest trial radius pending)
+#ifndef MFM_CLASS_RATIO
+#define MFM_CLASS_RATIO 0.5
+#endif
+#ifndef MFM_CLASS_WINDOW
+#define MFM_CLASS_WINDOW 2.0
+#endif
+constexpr double kClassRatio = MFM_CLASS_RATIO;
+constexpr double kClassWindow = MFM_CLASS_WINDOW;
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
@@ -230,12 +246,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (__ballot(need) == 0) break;
         // this pass: lanes within 2x of the largest radius and within 2 Rref of the first such lane
         const double Rref = uniform_d(wave_max_d(need ? R : 0.0));
-        const bool big = need && R >= 0.5 * Rref;
+        const bool big = need && R >= kClassRatio * Rref;
         const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)__ballot(big)) - 1);
         const double xl0 = uniform_d(__shfl(xi[0], leader, kWave)), xl1 = uniform_d(__shfl(xi[1], leader, kWave)),
                      xl2 = uniform_d(__shfl(xi[2], leader, kWave));
-        const bool cls = big && fabs(xi[0] - xl0) <= 2.0 * Rref && fabs(xi[1] - xl1) <= 2.0 * Rref &&
-                         fabs(xi[2] - xl2) <= 2.0 * Rref;
+        const double win = kClassWindow * Rref;
+        const bool cls = big && fabs(xi[0] - xl0) <= win && fabs(xi[1] - xl1) <= win && fabs(xi[2] - xl2) <= win;
         const double Rq = uniform_d(wave_max_d(cls ? R : 0.0));
         double bmin[3], bmax[3];
         for (int d = 0; d < 3; d++) {
@@ -420,7 +436,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
                 if (f < 0.0) lo = Hc;
                 else hi = Hc;
                 double Hn = Hc - f / fp;
-                if (fabs(Hn - Hc) <= 1e-14 * Hc) {
+                if (fabs(Hn - Hc) <= kNewtonTail * Hc) {
                     Hc = fmin(hi, fmax(lo, Hn));
                     conv = true;
                     break;
