@@ -42,3 +42,26 @@ PASS_FIELDS = ("H", "nk", "V", "B", "rho", "P", "grad", "dp", "dE", "vsig")
 def compare_pass(st, ref, fields=PASS_FIELDS):
     """dict field -> normwise error of the GPU pass against oracle outputs `ref`."""
     return {f: nerr(in_input_order(st, f), ref[f]) for f in fields}
+
+
+class ClosureUnsettled(AssertionError):
+    pass
+
+
+def oracle_sample(w, targets, pad: float = 1.5, doublings: int = 5, setup=None):
+    """Oracle outputs at ``targets`` of workload ``w``, from oracle inputs only.
+    The closure bound starts at ``pad`` times the largest oracle kernel length
+    of the targets and is doubled (at most ``doublings`` times) until no kernel
+    length the oracle solved inside the closure exceeds it."""
+    from oracle import oracle as O
+    s = setup or O.Setup.of(w)
+    mask = np.zeros(w.n, dtype=bool)
+    mask[np.asarray(targets)] = True
+    H, _, _, _ = O.solve_h(s, w.x, w.y, w.z, None, mask=mask)
+    h = pad * float(H[mask].max())
+    for _ in range(doublings + 1):
+        out = O.sampled_pass(s, w.arrays(), targets, h_bound=h)
+        if float(out["H"].max()) <= h:
+            return out
+        h *= 2.0
+    raise ClosureUnsettled("oracle closure bound did not settle")

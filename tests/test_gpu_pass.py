@@ -5,7 +5,7 @@ import pytest
 from oracle import oracle as O
 from paper_1712_01294_amd import workloads as W
 
-from .gpu_util import compare_pass, elem_rel, in_input_order, nerr, run_pass
+from .gpu_util import compare_pass, elem_rel, in_input_order, nerr, oracle_sample, run_pass
 
 pytestmark = pytest.mark.gpu
 
@@ -212,7 +212,7 @@ def test_turbulence_full_size_sampled():
     H = in_input_order(st, "H")
     rng = np.random.default_rng(5)
     targets = rng.choice(w.n, 24, replace=False)
-    ref = O.sampled_pass(O.Setup.of(w), w.arrays(), targets, h_bound=float(H.max()) * 1.0001)
+    ref = oracle_sample(w, targets)
     for k in ("H", "nk"):
         assert elem_rel(H[targets] if k == "H" else in_input_order(st, k)[targets], ref[k][targets]) <= TOL_FP64
     for k in ("dp", "grad", "B"):
@@ -254,3 +254,113 @@ def test_clustered_small_adaptive_h():
     assert np.all(per <= np.maximum(TOL_FP64, 32 * eps * cond))
     assert elem_rel(in_input_order(st, "H"), ref["H"]) <= TOL_FP64
     assert c["pairs"] == ref["pairs"]
+
+
+def test_clustered_full_size_properties():
+    """The benchmark's own set and launch configuration (16,777,216 particles from
+    the log-normal density, cold start), checked by properties that hold at any
+    size, independently of the oracle (whose dependency closures near the voids
+    of this set span much of the box):
+
+    * at 2000 random particles the gather part of the flux list equals the
+      exact set r < H_i (self excluded) from a periodic KD-tree (integer sets);
+    * H_i solves (32/3) sum_j w(r_ij/H_i) = n_ngb over that exact set, the sum
+      taken here in FP64 from the positions (relative residual <= 1e-12);
+    * every flux list is symmetric at those particles (j lists i iff i lists j),
+      and each tail entry j has r_ij < H_j;
+    * momentum and energy are conserved over the whole set to round-off."""
+    from scipy.spatial import cKDTree
+    w = W.clustered()
+    ctx, st = run_pass(w, alpha=False)
+    ctx.check(allow_illcond=True)
+    c = ctx.counters()
+    print("clustered full pairs", c["pairs"], "list max", c["list_max"], "fallback", c["h_fallback"], flush=True)
+    n = w.n
+    X = np.stack([st.x.cpu().numpy(), st.y.cpu().numpy(), st.z.cpu().numpy()], 1)
+    H = st.H.cpu().numpy()
+    counts, lst = ctx.flux_lists(n)
+    counts = counts.cpu().numpy()
+    print("kd-tree build", flush=True)
+    tree = cKDTree(X, boxsize=1.0)
+    rng = np.random.default_rng(W.SEED_BASE + 303)
+    samp = rng.choice(n, 2000, replace=False)
+    rows = lst[:, samp].cpu().numpy()
+    def w_spline(q):
+        return np.where(q <= 0.5, 1.0 + q * q * (6.0 * q - 6.0), np.where(q <= 1.0, 2.0 * (1.0 - q) ** 3, 0.0))
+    def dist(i, js):
+        d = X[js] - X[i]
+        d -= np.round(d)
+        return np.sqrt((d * d).sum(1))
+    worst = 0.0
+    for k, i in enumerate(samp):
+        ent = rows[: counts[i], k]
+        r = dist(i, ent)
+        gather = set(ent[r < H[i]].tolist())
+        exact = set(tree.query_ball_point(X[i], H[i] * (1 + 1e-12))) - {int(i)}
+        exact = {j for j in exact if dist(i, np.array([j]))[0] < H[i]}
+        assert gather == exact, (int(i), len(gather), len(exact))
+        js = np.array(sorted(exact | {int(i)}))
+        f = (32.0 / 3.0) * w_spline(dist(i, js) / H[i]).sum()
+        worst = max(worst, abs(f - w.n_ngb) / w.n_ngb)
+        tail = ent[~(r < H[i])]
+        assert np.all(dist(i, tail) < H[tail])
+    print("max relative residual of the neighbour-number equation", worst, flush=True)
+    assert worst <= 1e-12
+    # symmetry of the flux lists at the sampled particles
+    for k, i in enumerate(samp[:300]):
+        for j in rows[: counts[i], k]:
+            assert int(i) in set(lst[: counts[j], j].cpu().numpy().tolist())
+    dp = st.dp.cpu().numpy()
+    dE = st.dE.cpu().numpy()
+    eps = np.finfo(np.float64).eps
+    for comp in range(3):
+        assert abs(dp[comp].sum()) <= 10 * eps * np.abs(dp).sum()
+    assert abs(dE.sum()) <= 10 * eps * np.abs(dE).sum()
+
+
+def test_empty_and_single_particle_inputs():
+    """n = 0 is rejected before any launch; a lone particle in a periodic box can
+    never reach n_ngb neighbours, so its kernel length runs into half the box and
+    the pass reports the minimum-image error."""
+    import torch
+
+    from paper_1712_01294_amd import mfm
+    w = W.jittered_sine(n_side=4, seed=W.SEED_BASE + 500)
+    ctx = mfm.Context(mfm.config_of(w), 64)
+    empty = mfm.State(0)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.build_neighbours(empty)
+    assert e.value.status == -1
+    one = w.subset(np.array([5]))
+    st = mfm.State.from_arrays(one.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.check()
+    assert e.value.status == -5
+    torch.cuda.synchronize()
+
+
+def test_planar_set_flags_singular_gradient_matrix():
+    """A single 16 x 16 layer (all z equal) in a periodic unit box: no neighbour
+    has a z offset, E_i has a zero row and column, det E = 0 on every particle,
+    and the pass flags all of them as ill-conditioned (the gradients built from
+    a singular E are not finite, which is reported first)."""
+    from paper_1712_01294_amd import mfm
+    n_side = 16
+    sites = (np.arange(n_side) + 0.5) / n_side
+    X, Y = np.meshgrid(sites, sites, indexing="ij")
+    n = n_side * n_side
+    arr = {"x": X.ravel(), "y": Y.ravel(), "z": np.full(n, 0.5), "m": np.full(n, 1.0 / n),
+           "vx": np.zeros(n), "vy": np.zeros(n), "vz": np.zeros(n), "u": np.full(n, 1.5)}
+    cfg = mfm.Config(gamma=5.0 / 3.0, box=(1.0, 1.0, 1.0), periodic=(1, 1, 1), n_ngb=32.0, cfl=0.25,
+                     precision=mfm.FP64, u_floor=1e-10)
+    ctx = mfm.Context(cfg, n)
+    st = mfm.State.from_arrays(arr)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    c = ctx.counters()
+    assert c["illcond"] == n
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.check()
+    assert e.value.status in (-4, -7)
