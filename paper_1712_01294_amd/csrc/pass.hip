@@ -188,6 +188,10 @@ constexpr int kScanRounds = 12;   // scans per particle before the fallback take
 #define MFM_COLD_PAD 1.25
 #endif
 constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
+#ifndef MFM_STORE_COLD
+#define MFM_STORE_COLD 1.1
+#endif
+constexpr double kStoreCold = MFM_STORE_COLD;   // radii listed by a cold first scan, over the guess
 // a scan pass takes the lanes with R >= kClassRatio Rref within kClassWindow Rref
 // of the first of them on every axis (Rref: the largest trial radius pending)
 #ifndef MFM_CLASS_RATIO
@@ -259,9 +263,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             bmax[d] = uniform_d(wave_max_d(cls ? xi[d] : -INFINITY));
         }
         const double R2 = R * R;
-        // weighted counts at R and at two trial lengths around the expected root
+        // Weighted counts at R and at two trial lengths.  The first scan of a
+        // cold start lists only the radii below kStoreCold times the guess (the
+        // scan radius pads the guess further, to bracket the root in one scan),
+        // with the trial lengths at the guess and at that limit; if the root lies
+        // above the limit, the bracket is kept and one more scan lists them all.
+        const bool part = !warm && rounds == 0 && kStoreCold > 0.0;
         const double Hg = R * (warm ? 1.0 / 1.1 : 1.0 / kColdPad);
-        const double Ht[2] = {0.97 * Hg, 1.03 * Hg};
+        const double Ht[2] = {part ? Hg : 0.97 * Hg, part ? kStoreCold * Hg : 1.03 * Hg};
+        const double Sl = part ? Ht[1] : R;   // radii below Sl are listed
         const double iR = 1.0 / R, iT0 = 1.0 / Ht[0], iT1 = 1.0 / Ht[1];
         double sw = 0.0, st0 = 0.0, st1 = 0.0;
         if (cls) {
@@ -270,11 +280,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
         group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, R2, cls, [&](int j, double r2) {
             const double r = sqrt(r2);
-            if (m < cap) {
-                rl[(long long)m * n + i] = r;
-                jl[(long long)m * n + i] = j;
+            if (r < Sl) {
+                if (m < cap) {
+                    rl[(long long)m * n + i] = r;
+                    jl[(long long)m * n + i] = j;
+                }
+                m++;
             }
-            m++;
             sw += spline_w(r * iR);
             st0 += spline_w(r * iT0);
             st1 += spline_w(r * iT1);
@@ -313,7 +325,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     if (f0 >= 0.0) hi = Ht[0], neff_hi = f0 + ph.n_ngb;
                     else lo = Ht[0], fa = f0;
                 }
-                state = 1;
+                if (hi > Sl) {
+                    // the root lies above the listed radii: list them all up to hi
+                    R = hi;
+                } else {
+                    state = 1;
+                }
             }
         }
     }
