@@ -37,6 +37,7 @@ struct mfm_ctx {
     int* fb_list = nullptr;               // particles handed to the per-particle kernel-length solve
     unsigned long long* fb_count = nullptr;
     void* rec = nullptr;                  // 32 x 8 B per particle
+    double4* prim = nullptr;              // 128 B per particle: what gradients read of a neighbour
     double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
     double *dt_part = nullptr, *dt_out = nullptr;
     Counters* cnt = nullptr;
@@ -190,7 +191,7 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -245,6 +246,7 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->fb_list, sizeof(int) * n, "fallback list");
     alloc((void**)&c->fb_count, sizeof(unsigned long long), "fallback count");
     alloc((void**)&c->rec, sizeof(double) * 32 * n, "records");
+    alloc((void**)&c->prim, sizeof(double4) * 4 * n, "neighbour records");
     alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
     alloc((void**)&c->up, sizeof(double) * n, "predicted u");
     alloc((void**)&c->Ehalf, sizeof(double) * n, "half-step energy");
@@ -372,8 +374,8 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
     const auto ev = clock_take(c, MFM_KERNEL_GRADIENTS);
-    launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, ev.first, ev.second,
-                     s);
+    launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->rec_mixed, c->prim, c->rec, c->cnt, ev.first,
+                     ev.second, s);
     c->have_grad = 1;
     c->last = s;
     return launched(c, "gradients");

@@ -47,7 +47,7 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     int* counts, int* fb_list, unsigned long long* fb_count, hipEvent_t t0, hipEvent_t t1,
                     hipStream_t s);
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
-                      void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
+                      double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
                    int mixed, const void* rec, Counters* cnt, hipStream_t s);
 

@@ -586,10 +586,22 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 #endif
 enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
+// What the gradient kernel reads of a neighbour, packed into one 128-byte line
+// per particle: (x, y, z, H), (rho, vx, vy, vz), (P, -, -, -), unused.
+__global__ void k_pack_prim(PassArrays a, Phys ph, double4* __restrict__ prim) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double rho = a.m[i] * a.nk[i];
+    prim[4 * (long long)i + 0] = make_double4(a.x[i], a.y[i], a.z[i], a.H[i]);
+    prim[4 * (long long)i + 1] = make_double4(rho, a.vx[i], a.vy[i], a.vz[i]);
+    prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], 0.0, 0.0, 0.0);
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
                                                     int* __restrict__ counts, int* __restrict__ list,
-                                                    void* __restrict__ recp, Counters* cnt) {
+                                                    const double4* __restrict__ prim, void* __restrict__ recp,
+                                                    Counters* cnt) {
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
     unsigned long long ill = 0, nonfin = 0, condbits = 0;
@@ -614,17 +626,19 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
         const int cap = ph.max_ngb;
         for (int k = 0; k < cnum; k++) {
             const int j = list[(long long)k * n + i];
+            const double4 pj = prim[4 * (long long)j + 0];
+            const double4 qj = prim[4 * (long long)j + 1];
+            const double Pj = prim[4 * (long long)j + 2].x;
             double d[3];
-            displacement(ph, xi, a.x[j], a.y[j], a.z[j], d);
+            displacement(ph, xi, pj.x, pj.y, pj.z, d);
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < a.H[j])) {
+            if (!(r < pj.w)) {
                 // i is outside j's gather set: the pair enters j's flux list as a
                 // tail entry (slots past the gather part, sorted afterwards)
                 const int slot = atomicAdd(&counts[j], 1);
                 if (slot < cap) list[(long long)slot * n + j] = i;
             }
-            const double rho_j = a.m[j] * a.nk[j];
-            const double phi_j[5] = {rho_j, a.vx[j], a.vy[j], a.vz[j], (ph.gamma - 1.0) * rho_j * a.u[j]};
+            const double phi_j[5] = {qj.x, qj.y, qj.z, qj.w, Pj};
             if (!MIXED) {
                 const double psi = norm * spline_w(r * iH) * Vi;
                 E[0] += d[0] * d[0] * psi;
@@ -1009,12 +1023,13 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
 }
 
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
-                      void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+                      double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, prim);
     if (t0) hipEventRecord(t0, s);
     if (mixed)
-        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, rec, cnt);
+        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, prim, rec, cnt);
     else
-        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, rec, cnt);
+        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, prim, rec, cnt);
     if (t1) hipEventRecord(t1, s);
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
 }
