@@ -64,23 +64,26 @@ struct Counters {
 // ---------------------------------------------------------------- kernel
 // Cubic spline with support radius H: W = 8/(pi H^3) w(q), q = r/H,
 // w = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1), 0 beyond.
-// Both branches are evaluated and one is selected, so lanes of a wave with q
-// on different pieces do not diverge; the arithmetic of each piece is as written.
+// With t = max(1 - q, 0) and u = max(1/2 - q, 0) both pieces are one
+// expression, w = 2 t^3 - 8 u^3 (expanding 2(1-q)^3 - (1-2q)^3 gives the inner
+// piece), and q w'(q) = q (24 u^2 - 6 t^2): no selects or branches, so lanes
+// with q on different pieces run the same instructions.
+__device__ __forceinline__ double spline_pos(double a) { return fmax(a, 0.0); }
+__device__ __forceinline__ float spline_pos(float a) { return fmaxf(a, 0.0f); }
+
 template <typename T>
 __device__ __forceinline__ T spline_w(T q) {
-    const T t = T(1) - q;
-    const T inner = T(1) + q * q * (T(6) * q - T(6));
-    const T outer = T(2) * t * t * t;
-    return q <= T(0.5) ? inner : (q <= T(1) ? outer : T(0));
+    const T t = spline_pos(T(1) - q);
+    const T u = spline_pos(T(0.5) - q);
+    return T(2) * (t * t) * t - T(8) * (u * u) * u;
 }
 
 // q * dw/dq
 template <typename T>
 __device__ __forceinline__ T spline_qdw(T q) {
-    const T t = T(1) - q;
-    const T inner = q * q * (T(18) * q - T(12));
-    const T outer = T(-6) * q * t * t;
-    return q <= T(0.5) ? inner : (q <= T(1) ? outer : T(0));
+    const T t = spline_pos(T(1) - q);
+    const T u = spline_pos(T(0.5) - q);
+    return q * (T(24) * (u * u) - T(6) * (t * t));
 }
 
 template <typename T>
@@ -114,10 +117,11 @@ __device__ __forceinline__ double min_image(double d, double L, int periodic) {
 #endif
 constexpr double kScanScale = MFM_SCAN_SCALE;
 
-// scatter the low bits of v into the set bits of mask (lowest first)
+// scatter the low bits of v into the set bits of mask (lowest first); bits of v
+// beyond the mask's population are dropped, which reduces v modulo 2^popcount
 __device__ __forceinline__ unsigned long long deposit_bits(unsigned v, unsigned long long mask) {
     unsigned long long r = 0;
-    while (mask) {
+    while (mask && v) {
         const unsigned long long low = mask & (~mask + 1);
         if (v & 1u) r |= low;
         v >>= 1;
@@ -126,12 +130,27 @@ __device__ __forceinline__ unsigned long long deposit_bits(unsigned v, unsigned 
     return r;
 }
 
+// Sum of two deposited values modulo 2^popcount(mask): with the bits outside the
+// mask set to one, carries run through them to the next mask bit.
+__device__ __forceinline__ unsigned long long dilated_add(unsigned long long x, unsigned long long y,
+                                                          unsigned long long mask) {
+    return ((x | ~mask) + y) & mask;
+}
+
+// Difference of two deposited values modulo 2^popcount(mask): borrows run
+// through the zero bits outside the mask.
+__device__ __forceinline__ unsigned long long dilated_sub(unsigned long long x, unsigned long long y,
+                                                          unsigned long long mask) {
+    return (x - y) & mask;
+}
+
 // per-wave LDS of the cooperative scan
 struct ScanLds {
     double4 cand[kWave];    // staged particles: image position, index bits in w
     int excl[kWave];        // exclusive prefix of the batch cells' particle counts
     int start[kWave];       // first particle of each batch cell
     double sh[3][kWave];    // periodic image shift of each batch cell
+    unsigned long long key[3][kWave];   // key bits of cell coordinate a + t, t = 0..63, per axis
 };
 
 // order the LDS traffic of one wave (lanes read what other lanes wrote)
@@ -151,18 +170,23 @@ __device__ __forceinline__ double sq_disp(const double4& q, const double xi[3], 
     return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
+// Bit 63 - k of the mask is set when staged particle k lies inside the sphere,
+// so the hit loop takes hits in staging order from the top bit down.  The tests
+// go four at a time (a group shifted in below the previous ones); slots past nb
+// hold a far-away point, so a group may run past nb.
 template <bool kWrap>
 __device__ __forceinline__ unsigned long long batch_mask(const ScanLds& S, int nb, const double xi[3], double R2,
                                                          int wrap, const double box[3]) {
     unsigned long long mk = 0;
-    for (int k0 = 0; k0 < nb; k0 += 4) {
+    int k0 = 0;
+    for (; k0 < nb; k0 += 4) {
+        unsigned b = 0;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const double r2 = sq_disp(S.cand[k0 + k], xi, kWrap ? wrap : 0, box);
-            mk |= (r2 < R2 ? 1ull : 0ull) << (k0 + k);
-        }
+        for (int k = 0; k < 4; k++)
+            b = (b << 1) + (sq_disp(S.cand[k0 + k], xi, kWrap ? wrap : 0, box) < R2 ? 1u : 0u);
+        mk = (mk << 4) | b;
     }
-    return mk;
+    return k0 >= 64 ? mk : (k0 == 0 ? 0ull : mk << (64 - k0));
 }
 
 // Cell enumeration and staging shared by the cooperative scans: the cells of
@@ -207,6 +231,14 @@ __device__ __forceinline__ void scan_cells(const TreeDesc& td, const int2* __res
     wrap = __builtin_amdgcn_readfirstlane(wrap);
     if (cnt[0] <= 0 || cnt[1] <= 0 || cnt[2] <= 0) return;
     const int ncells = cnt[0] * cnt[1] * cnt[2];
+    // key bits of the range's cell coordinates (modulo the cells per axis) for
+    // offsets 0..63 along each axis; a wider range deposits per lane
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int w = (a[d] + lane) & (nc[d] - 1);   // nc is a power of two
+        S.key[d][lane] = deposit_bits((unsigned)w, td.mask[L][d]);
+    }
+    wave_lds_sync();
     // slack for the rounding of cell edges and of the keys' quantisation
     const double Rg = Rq * (1.0 + 1e-9) + 1e-12 * fmax(td.box[0], fmax(td.box[1], td.box[2]));
     const double Rg2 = Rg * Rg;
@@ -241,7 +273,7 @@ __device__ __forceinline__ void scan_cells(const TreeDesc& td, const int2* __res
                     w -= nc[d];
                     sh[d] = td.box[d];
                 }
-                key |= deposit_bits((unsigned)w, td.mask[L][d]);
+                key |= cnt[d] <= kWave ? S.key[d][u[d] - a[d]] : deposit_bits((unsigned)w, td.mask[L][d]);
             }
             if (g2 < Rg2) {
                 const int2 se = tab[off + (long long)key];
@@ -302,8 +334,8 @@ __device__ __forceinline__ void group_scan(const TreeDesc& td, const int2* __res
                                      : batch_mask<false>(S, nb, xi, R2, 0, td.box);
         if (!sel) mk = 0;
         while (mk) {
-            const int k = __builtin_ctzll(mk);
-            mk &= mk - 1;
+            const int k = __builtin_clzll(mk);
+            mk &= ~(0x8000000000000000ull >> k);
             const double4 qk = S.cand[k];
             hit((int)__double_as_longlong(qk.w), sq_disp(qk, xi, wrap, td.box));
         }

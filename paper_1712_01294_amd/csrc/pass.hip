@@ -92,19 +92,22 @@ __device__ BlockCount block_count(const TreeDesc& td, const int2* __restrict__ t
     for (int d = 0; d < 3; d++) {
         const int nc = td.ncell[l][d];
         const int c = min(nc - 1, max(0, (int)floor(xi[d] / td.cs[l][d])));
+        // the neighbours c - 1 and c + 1 by dilated subtraction and addition of
+        // the deposited 1 (wrapping modulo nc, which only periodic axes use)
+        const unsigned long long m = td.mask[l][d];
+        const unsigned long long one = m & (~m + 1);
+        const unsigned long long dc = deposit_bits((unsigned)c, m);
+        const unsigned long long dn[3] = {dilated_sub(dc, one, m), dc, dilated_add(dc, one, m)};
         ncl[d] = 0;
 #pragma unroll
         for (int o = 0; o < 3; o++) {
-            int w = c + o - 1;
+            const int w = c + o - 1;
             bool in = true;
-            if (w < 0 || w >= nc) {
-                if (td.periodic[d] && nc >= 3) w = (w + nc) % nc;
-                else in = false;
-            }
+            if ((w < 0 || w >= nc) && !(td.periodic[d] && nc >= 3)) in = false;
             if (nc < 3 && o != 1) in = false;   // fewer than 3 cells: count each once
             ok[d][o] = in;
             ncl[d] += in;
-            dil[d][o] = in ? deposit_bits((unsigned)w, td.mask[l][d]) : 0ull;
+            dil[d][o] = in ? dn[o] : 0ull;
         }
     }
     int cnt = 0;
