@@ -188,9 +188,13 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
 
 constexpr int kScanRounds = 12;   // scans per particle before the fallback takes it
 #ifndef MFM_COLD_PAD
-#define MFM_COLD_PAD 1.25
+#define MFM_COLD_PAD 1.1
 #endif
 constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
+#ifndef MFM_WARM_PAD
+#define MFM_WARM_PAD 1.05
+#endif
+constexpr double kWarmPad = MFM_WARM_PAD;   // first scan radius over the previous H
 #ifndef MFM_STORE_COLD
 #define MFM_STORE_COLD 1.1
 #endif
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     // state 0: scanning, 1: bracketed with every radius below hi listed, 2: given up
     int state = act ? 0 : 2;
     double lo = 0.0, hi = INFINITY, top = INFINITY;   // top: smallest R whose list overflowed
-    double R = (warm ? 1.1 : kColdPad) * guess;
+    double R = (warm ? kWarmPad : kColdPad) * guess;
     double neff_hi = 0.0, fa = NAN;                   // residuals at the bracket ends
     int m = 0, rounds = 0;
     unsigned long long iters = 0;
@@ -267,12 +271,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
         const double R2 = R * R;
         // Weighted counts at R and at two trial lengths.  The first scan of a
-        // cold start lists only the radii below kStoreCold times the guess (the
-        // scan radius pads the guess further, to bracket the root in one scan),
+        // cold start lists only the radii below kStoreCold times the guess (a
+        // scan radius padded further brackets more roots in one scan; with the
+        // default pads, equal to kStoreCold, every radius within R is listed),
         // with the trial lengths at the guess and at that limit; if the root lies
         // above the limit, the bracket is kept and one more scan lists them all.
         const bool part = !warm && rounds == 0 && kStoreCold > 0.0;
-        const double Hg = R * (warm ? 1.0 / 1.1 : 1.0 / kColdPad);
+        const double Hg = R * (warm ? 1.0 / kWarmPad : 1.0 / kColdPad);
         const double Ht[2] = {part ? Hg : 0.97 * Hg, part ? kStoreCold * Hg : 1.03 * Hg};
         const double Sl = part ? Ht[1] : R;   // radii below Sl are listed
         const double iR = 1.0 / R, iT0 = 1.0 / Ht[0], iT1 = 1.0 / Ht[1];
