@@ -1,5 +1,6 @@
 // C ABI of the gfx950 MFM hydro pass (declared in include/mfm.h).
 #include <math.h>
+#include <algorithm>
 #include <stdio.h>
 #include <string.h>
 
@@ -252,7 +253,7 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->Ehalf, sizeof(double) * n, "half-step energy");
     alloc((void**)&c->dt_part, sizeof(double) * 1024, "dt partials");
     alloc((void**)&c->dt_out, sizeof(double) * 2, "dt");
-    alloc((void**)&c->cnt, sizeof(Counters), "counters");
+    alloc((void**)&c->cnt, (size_t)kCounterCopies * kCounterStride, "counters");
     if (st != MFM_OK) {
         fprintf(stderr, "mfm_create: %s\n", c->err.c_str());
         mfm_destroy(c);
@@ -262,11 +263,14 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     return MFM_OK;
 }
 
+static Counters* counter_slot(mfm_ctx* c, int k) {
+    return (Counters*)((char*)c->cnt + (size_t)k * kCounterStride);
+}
+
 static void reset_counters(mfm_ctx* c, hipStream_t s) {
-    const int words = sizeof(Counters) / 8;
-    launch_fill_u64(words, (unsigned long long*)c->cnt, 0ull, s);
-    // first_bad starts at "none"
-    launch_fill_u64(1, &c->cnt->first_bad, ~0ull, s);
+    launch_fill_u64(kCounterCopies * kCounterStride / 8, (unsigned long long*)c->cnt, 0ull, s);
+    // first_bad starts at "none" in every copy
+    for (int k = 0; k < kCounterCopies; k++) launch_fill_u64(1, &counter_slot(c, k)->first_bad, ~0ull, s);
 }
 
 static mfm_status check_particles(mfm_ctx* c, const mfm_particles* p) {
@@ -490,8 +494,34 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     hipSetDevice(c->device);
     mfm_status st;
     if ((st = hip_check(c, hipStreamSynchronize(c->last), "sync"))) return st;
+    // combine the per-block-group copies: sums, maxima and the smallest index
+    unsigned char raw[kCounterCopies * kCounterStride];
+    if ((st = hip_check(c, hipMemcpy(raw, c->cnt, sizeof(raw), hipMemcpyDeviceToHost), "counter copy"))) return st;
     Counters h;
-    if ((st = hip_check(c, hipMemcpy(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost), "counter copy"))) return st;
+    memcpy(&h, raw, sizeof(h));
+    for (int k = 1; k < kCounterCopies; k++) {
+        Counters o;
+        memcpy(&o, raw + (size_t)k * kCounterStride, sizeof(o));
+        h.list_entries += o.list_entries;
+        h.list_max = std::max(h.list_max, o.list_max);
+        h.h_iters += o.h_iters;
+        h.h_iters_max = std::max(h.h_iters_max, o.h_iters_max);
+        h.noconv += o.noconv;
+        h.minimage += o.minimage;
+        h.overflow += o.overflow;
+        h.illcond += o.illcond;
+        h.fallbacks += o.fallbacks;
+        h.clamps += o.clamps;
+        h.nonfinite += o.nonfinite;
+        h.floors += o.floors;
+        h.first_bad = std::min(h.first_bad, o.first_bad);
+        h.cond_bits = std::max(h.cond_bits, o.cond_bits);   // positive doubles order as their bits
+        h.h_rounds_max = std::max(h.h_rounds_max, o.h_rounds_max);
+        h.h_fallback += o.h_fallback;
+        h.h_rounds3 += o.h_rounds3;
+        h.gather_entries += o.gather_entries;
+    }
+    static_assert(sizeof(Counters) == 18 * 8, "combine every counter field");
     out->list_entries = (int64_t)h.list_entries;
     out->pairs = (int64_t)(h.list_entries / 2);
     out->list_max = (int64_t)h.list_max;

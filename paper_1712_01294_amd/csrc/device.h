@@ -40,6 +40,10 @@ struct Phys {
 };
 
 // Device counters (all updated with atomics, read by the host after a sync).
+// There are kCounterCopies copies, kCounterStride bytes apart; a block updates
+// the copy of its blockIdx modulo the count, which spreads the atomics of a
+// launch over as many cache lines (all on one line serialise in one L2
+// channel), and the host combines the copies when it reads them.
 struct Counters {
     unsigned long long list_entries;
     unsigned long long list_max;
@@ -60,6 +64,14 @@ struct Counters {
     unsigned long long h_rounds3;    // particles that needed three or more scans
     unsigned long long gather_entries;  // sum of the gather-list lengths
 };
+constexpr int kCounterCopies = 32;
+constexpr int kCounterStride = 256;
+static_assert(sizeof(Counters) <= kCounterStride, "counter copies overlap");
+
+// the copy of the counters the calling block updates
+__device__ __forceinline__ Counters* counter_copy(Counters* base) {
+    return (Counters*)((char*)base + (blockIdx.x & (kCounterCopies - 1)) * kCounterStride);
+}
 
 // ---------------------------------------------------------------- kernel
 // Cubic spline with support radius H: W = 8/(pi H^3) w(q), q = r/H,

@@ -42,9 +42,11 @@ __device__ __forceinline__ void count_add(unsigned long long* c, unsigned long l
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(c, v);
 }
 
+// the atomic is skipped when the counter already holds at least v (a stale
+// read only costs an atomic that changes nothing)
 __device__ __forceinline__ void count_max(unsigned long long* c, unsigned long long v) {
     v = wave_max(v);
-    if ((threadIdx.x & 63) == 0 && v) atomicMax(c, v);
+    if ((threadIdx.x & 63) == 0 && v && v > __atomic_load_n(c, __ATOMIC_RELAXED)) atomicMax(c, v);
 }
 
 __device__ __forceinline__ void flag_index(Counters* cnt, int i) {
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
                                                   int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count) {
+    cnt = counter_copy(cnt);
     __shared__ ScanLds lds[256 / kWave];
     ScanLds& S = lds[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -398,6 +401,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
                                                           const unsigned long long* __restrict__ fb_count,
                                                           int* __restrict__ jl, int* __restrict__ gcount,
                                                           int* __restrict__ counts) {
+    cnt = counter_copy(cnt);
     __shared__ ScanLds S;
     const int lane = threadIdx.x;
     const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
@@ -527,13 +531,66 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
 // deterministic.
 constexpr int kTailNet = 32;   // tails up to this length are sorted in registers
 
+// bitonic sorting network on N registers (indices fixed at compile time)
+template <int N>
+__device__ __forceinline__ void bitonic_net(int* v) {
+#pragma unroll
+    for (int w = 2; w <= N; w <<= 1)
+#pragma unroll
+        for (int h = w >> 1; h > 0; h >>= 1)
+#pragma unroll
+            for (int k = 0; k < N; k++) {
+                const int l = k ^ h;
+                if (l > k) {
+                    const int lo_v = min(v[k], v[l]), hi_v = max(v[k], v[l]);
+                    const bool up = (k & w) == 0;
+                    v[k] = up ? lo_v : hi_v;
+                    v[l] = up ? hi_v : lo_v;
+                }
+            }
+}
+
+// sort the first t entries of the calling thread's LDS column
+template <int N>
+__device__ __forceinline__ void sort_column(int (*col)[256], int t) {
+    int v[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) v[k] = k < t ? col[k][threadIdx.x] : INT_MAX;
+    bitonic_net<N>(v);
+#pragma unroll
+    for (int k = 0; k < N; k++)
+        if (k < t) col[k][threadIdx.x] = v[k];
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// The tail of particle i (entries gcount[i] .. counts[i]-1 of its flux list,
+// appended by other particles in no fixed order) is sorted by index, so every
+// later sum over the list runs in one order.  The list is interleaved
+// (list[k * n + i]) and tails start at different rows, so a wave walks the rows
+// its short tails span once, each access one coalesced row segment of the
+// wave's columns, into each lane's own LDS column; there a network sized to
+// the wave's longest tail sorts in registers.  Longer tails are ranked by the
+// whole wave in LDS.
 __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* __restrict__ gcount,
                                                      int* __restrict__ counts, int* __restrict__ list,
                                                      Counters* cnt) {
+    cnt = counter_copy(cnt);
+    __shared__ int col[kTailNet][256];
     const int i = xcd_block() * 256 + threadIdx.x;
     unsigned long long c = 0, over = 0, gsum = 0;
+    int g = 0, t = 0;
     if (i < n) {
-        const int g = gcount[i];
+        g = gcount[i];
         gsum = (unsigned long long)g;
         int e = counts[i];
         c = (unsigned long long)e;
@@ -543,39 +600,55 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
             e = cap;
             counts[i] = cap;
         }
-        const int t = e - g;
-        if (t <= kTailNet) {
-            // short tails: a bitonic network on registers (indices fixed at compile time)
-            int v[kTailNet];
-#pragma unroll
-            for (int k = 0; k < kTailNet; k++) v[k] = k < t ? list[(long long)(g + k) * n + i] : INT_MAX;
-#pragma unroll
-            for (int w = 2; w <= kTailNet; w <<= 1)
-#pragma unroll
-                for (int h = w >> 1; h > 0; h >>= 1)
-#pragma unroll
-                    for (int k = 0; k < kTailNet; k++) {
-                        const int l = k ^ h;
-                        if (l > k) {
-                            const int lo_v = min(v[k], v[l]), hi_v = max(v[k], v[l]);
-                            const bool up = (k & w) == 0;
-                            v[k] = up ? lo_v : hi_v;
-                            v[l] = up ? hi_v : lo_v;
-                        }
-                    }
-#pragma unroll
-            for (int k = 0; k < kTailNet; k++)
-                if (k < t) list[(long long)(g + k) * n + i] = v[k];
-        } else {
-            for (int k = g + 1; k < e; k++) {
-                const int v = list[(long long)k * n + i];
-                int q = k - 1;
-                while (q >= g && list[(long long)q * n + i] > v) {
-                    list[(long long)(q + 1) * n + i] = list[(long long)q * n + i];
-                    q--;
-                }
-                list[(long long)(q + 1) * n + i] = v;
+        t = e - g;
+    }
+    const bool net = t > 1 && t <= kTailNet;
+    const int rlo = wave_min_i(net ? g : INT_MAX);
+    const int rhi = wave_max_i(net ? g + t : INT_MIN);
+    const int tmax = wave_max_i(net ? t : 0);
+    if (rlo < rhi) {
+        for (int r = rlo; r < rhi; r++)
+            if (net && r >= g && r < g + t) col[r - g][threadIdx.x] = list[(long long)r * n + i];
+        const int tn = net ? t : 0;
+        if (tmax <= 8) sort_column<8>(col, tn);
+        else if (tmax <= 16) sort_column<16>(col, tn);
+        else sort_column<kTailNet>(col, tn);
+        for (int r = rlo; r < rhi; r++)
+            if (net && r >= g && r < g + t) list[(long long)r * n + i] = col[r - g][threadIdx.x];
+    }
+    // Long tails, one at a time per wave: the tail goes to a contiguous LDS
+    // region of the wave, every lane ranks its entries against all of them (ties,
+    // which a list does not hold, by position) and writes each entry to its slot.
+    __syncthreads();   // every wave is done with the columns
+    int* wb = &col[0][0] + (threadIdx.x >> 6) * (kTailNet * kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    unsigned long long lm = __ballot(t > kTailNet && t <= kTailNet * kWave);
+    while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1;
+        const int gs = __shfl(g, src, kWave), ts = __shfl(t, src, kWave), is = __shfl(i, src, kWave);
+        for (int k = lane; k < ts; k += kWave) wb[k] = list[(long long)(gs + k) * n + is];
+        wave_lds_sync();
+        for (int k = lane; k < ts; k += kWave) {
+            const int v = wb[k];
+            int rank = 0;
+            for (int q = 0; q < ts; q++) {
+                const int u = wb[q];
+                rank += (u < v || (u == v && q < k)) ? 1 : 0;
             }
+            list[(long long)(gs + rank) * n + is] = v;
+        }
+        wave_lds_sync();   // the next tail overwrites the region
+    }
+    if (t > kTailNet * kWave) {
+        for (int k = g + 1; k < g + t; k++) {
+            const int v = list[(long long)k * n + i];
+            int q = k - 1;
+            while (q >= g && list[(long long)q * n + i] > v) {
+                list[(long long)(q + 1) * n + i] = list[(long long)q * n + i];
+                q--;
+            }
+            list[(long long)(q + 1) * n + i] = v;
         }
     }
     count_add(&cnt->list_entries, c);
@@ -610,6 +683,7 @@ __global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const 
                                                     int* __restrict__ counts, int* __restrict__ list,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
                                                     Counters* cnt) {
+    cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
     unsigned long long ill = 0, nonfin = 0, condbits = 0;
@@ -934,6 +1008,7 @@ template <typename T>
 __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
                                             const int* __restrict__ list, const T* __restrict__ rec,
                                             Counters* cnt) {
+    cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
     unsigned long long nfall = 0, nclamp = 0, nonfin = 0;

@@ -46,6 +46,7 @@ __global__ void k_kick_drift(PassArrays a, Phys ph, double dt, double u_floor, d
 // second half kick and recovery of u = E/m - |v|^2/2, floored
 __global__ void k_kick2(PassArrays a, double dt, double u_floor, const double* __restrict__ Ehalf,
                         double* __restrict__ u, Counters* cnt) {
+    cnt = counter_copy(cnt);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long fl = 0;
     if (i < a.n) {
