@@ -678,8 +678,14 @@ __global__ void k_pack_prim(PassArrays a, Phys ph, double4* __restrict__ prim) {
     prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], 0.0, 0.0, 0.0);
 }
 
+// Four waves per SIMD (128 VGPRs, no spills): the kernel waits on the gathers
+// of its neighbours' records, and a fourth wave hides more of that than the
+// register budget it takes costs.
+#ifndef MFM_GRAD_WAVES
+#define MFM_GRAD_WAVES 4
+#endif
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WAVES))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
                                                     int* __restrict__ counts, int* __restrict__ list,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
                                                     Counters* cnt) {
@@ -1074,8 +1080,12 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
 }
 
 // One kernel per record precision: each pair holds both records in registers,
-// and the FP32 form fits four waves per SIMD where the FP64 form fits two.
-__global__ __launch_bounds__(256) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
+// and the FP32 form fits four waves per SIMD where the FP64 form fits three
+// (with a few spilled loop invariants, cheaper than the third wave is worth).
+#ifndef MFM_FLUX64_WAVES
+#define MFM_FLUX64_WAVES 3
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
     fluxes_body<double>(a, ph, counts, list, rec, cnt);
