@@ -186,7 +186,7 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * fallback follow the branch the forward took.  Requires that the last pass
  * on this context ran on p (its outputs nk, V, B, rho, P, grad are read).
  * All arrays are device memory in p's current order.  The first adjoint call
- * on a context allocates its adjoint scratch (56 doubles per particle). */
+ * on a context allocates its adjoint scratch (100 doubles per particle). */
 mfm_status mfm_hydro_pass_adjoint(mfm_ctx *ctx, const mfm_particles *p, const double *adj_dp,
                                   const double *adj_dE, double *adj_x, double *adj_v, double *adj_u,
                                   void *stream);

@@ -7,11 +7,14 @@
 // stages backwards at fixed neighbour sets (the kernel is C^2 at its support
 // edge, so set changes are smooth):
 //   k_adj_pairs      each particle reverses the flux of every pair it is in
-//                    (canonical order, as the forward) and keeps its own side;
-//   k_adj_gradients  reverse of limiter (active branch), E^-1, and the E / S
-//                    sums; neighbour contributions are atomic adds;
-//   k_adj_length     reverse of n_i and V_i through W, and of H_i by the
-//                    implicit-function theorem dH = -(dPhi/dx) / (dPhi/dH).
+//                    (canonical order, as the forward) and keeps its own side,
+//                    reading both sides from packed per-particle records;
+//   k_adj_grad_*     reverse of limiter (active branch), E^-1, and the E / S
+//                    sums, split into a per-particle part and a part that
+//                    pulls the neighbour terms through the flux lists;
+//   k_adj_length_*   reverse of n_i and V_i through W, and of H_i by the
+//                    implicit-function theorem dH = -(dPhi/dx) / (dPhi/dH),
+//                    split the same way.
 // Min/max choices (Davis speeds, limiter, P* clamp, first-order fallback)
 // follow the branch the forward took.
 #include <math.h>
@@ -55,20 +58,6 @@ struct SideAdj {
     double H, V, phi[5], B[6], g[15];
 };
 
-__device__ __forceinline__ void load_side(const PassArrays& a, long long n, int i, Side& s) {
-    s.H = a.H[i];
-    s.V = a.V[i];
-    s.phi[0] = a.rho[i];
-    s.phi[1] = a.vx[i];
-    s.phi[2] = a.vy[i];
-    s.phi[3] = a.vz[i];
-    s.phi[4] = a.P[i];
-#pragma unroll
-    for (int k = 0; k < 6; k++) s.B[k] = a.B[k * n + i];
-#pragma unroll
-    for (int k = 0; k < 15; k++) s.g[k] = a.grad[k * n + i];
-}
-
 __device__ __forceinline__ void zero_adj(SideAdj& s) {
     s.H = s.V = 0.0;
 #pragma unroll
@@ -86,26 +75,12 @@ __device__ __forceinline__ void symv(const double B[6], const double d[3], doubl
     y[2] = B[2] * d[0] + B[4] * d[1] + B[5] * d[2];
 }
 
-// adjoint of y = B d: stored-component adjoints of B and the adjoint of d
-__device__ __forceinline__ void symv_adj(const double B[6], const double d[3], const double ly[3], double lB[6],
-                                         double ld[3]) {
-    lB[0] += ly[0] * d[0];
-    lB[1] += ly[0] * d[1] + ly[1] * d[0];
-    lB[2] += ly[0] * d[2] + ly[2] * d[0];
-    lB[3] += ly[1] * d[1];
-    lB[4] += ly[1] * d[2] + ly[2] * d[1];
-    lB[5] += ly[2] * d[2];
-    double t[3];
-    symv(B, ly, t);
-    ld[0] += t[0];
-    ld[1] += t[1];
-    ld[2] += t[2];
-}
-
 // Reverse of one pair (left a, right b, d = x_b - x_a): given the adjoints of
-// the momentum flux Fp (3) and energy flux FE, accumulate into la, lb and ld.
-__device__ void pair_reverse(const Side& a, const Side& b, const double d[3], double gamma, const double lFp[3],
-                             double lFE, SideAdj& la, SideAdj& lb, double ld[3]) {
+// the momentum flux Fp (3) and energy flux FE, accumulate the adjoint of one
+// side (a if own_a, else b) into lo, and the adjoint of d into ld.
+__device__ __forceinline__ void pair_reverse(const Side& a, const Side& b, const double d[3], double gamma,
+                                             const double lFp[3], double lFE, bool own_a, SideAdj& lo,
+                                             double ld[3]) {
     const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double Wa, dWa_r, dWa_H, Wb, dWb_r, dWb_H;
     kernel_wdw(r, a.H, Wa, dWa_r, dWa_H);
@@ -219,18 +194,13 @@ __device__ void pair_reverse(const Side& a, const Side& b, const double d[3], do
         lw[c] -= (luL + luR) * nh[c];
         lnh[c] += luL * (qL[slot_v + c] - w[c]) + luR * (qR[slot_v + c] - w[c]);
     }
-    for (int c = 0; c < 3; c++) {
-        la.phi[slot_v + c] += 0.5 * lw[c];
-        lb.phi[slot_v + c] += 0.5 * lw[c];
-    }
+    for (int c = 0; c < 3; c++) lo.phi[slot_v + c] += 0.5 * lw[c];
     for (int f = 0; f < 5; f++) {
-        la.phi[f] += lqL[f];
-        lb.phi[f] += lqR[f];
+        lo.phi[f] += own_a ? lqL[f] : lqR[f];
         if (!fallback) {
             for (int k = 0; k < 3; k++) {
-                la.g[3 * f + k] += 0.5 * lqL[f] * d[k];
+                lo.g[3 * f + k] += own_a ? 0.5 * lqL[f] * d[k] : -(0.5 * lqR[f] * d[k]);
                 ld[k] += 0.5 * lqL[f] * a.g[3 * f + k];
-                lb.g[3 * f + k] -= 0.5 * lqR[f] * d[k];
                 ld[k] -= 0.5 * lqR[f] * b.g[3 * f + k];
             }
         }
@@ -247,14 +217,25 @@ __device__ void pair_reverse(const Side& a, const Side& b, const double d[3], do
         lta[c] = lA[c] * ka;
         ltb[c] = lA[c] * kb;
     }
-    symv_adj(a.B, d, lta, la.B, ld);
-    symv_adj(b.B, d, ltb, lb.B, ld);
+    // y = B d: the own side's B takes lt d^T (stored components), d takes B lt from both
+    {
+        const double* lt = own_a ? lta : ltb;
+        lo.B[0] += lt[0] * d[0];
+        lo.B[1] += lt[0] * d[1] + lt[1] * d[0];
+        lo.B[2] += lt[0] * d[2] + lt[2] * d[0];
+        lo.B[3] += lt[1] * d[1];
+        lo.B[4] += lt[1] * d[2] + lt[2] * d[1];
+        lo.B[5] += lt[2] * d[2];
+        double t[3];
+        symv(a.B, lta, t);
+        for (int c = 0; c < 3; c++) ld[c] += t[c];
+        symv(b.B, ltb, t);
+        for (int c = 0; c < 3; c++) ld[c] += t[c];
+    }
     const double lWa = lka * a.V * a.V, lWb = lkb * b.V * b.V;
-    la.V += lka * 2.0 * a.V * Wa;
-    lb.V += lkb * 2.0 * b.V * Wb;
+    lo.V += own_a ? lka * 2.0 * a.V * Wa : lkb * 2.0 * b.V * Wb;
     const double lr = lWa * dWa_r + lWb * dWb_r;
-    la.H += lWa * dWa_H;
-    lb.H += lWb * dWb_H;
+    lo.H += own_a ? lWa * dWa_H : lWb * dWb_H;
     if (r > 0.0)
         for (int k = 0; k < 3; k++) ld[k] += lr * d[k] / r;
 }
@@ -265,43 +246,82 @@ struct AdjArrays {
     double *acc_x, *acc_phi, *acc_H, *acc_V, *acc_B, *acc_g;
 };
 
-__global__ __launch_bounds__(256) void k_adj_pairs(PassArrays a, Phys ph, const int* __restrict__ counts,
-                                                    const int* __restrict__ list, const double* __restrict__ lam_dp,
-                                                    const double* __restrict__ lam_dE, AdjArrays aj) {
+// Side record of the pair reverse, one per particle (kAdjRec doubles, in the
+// region the gradient reverse later fills with its own records): x, y, z, H,
+// V, phi (5), B (6), grad (15), then the adjoints of dp (3) and dE it receives.
+enum { S_X = 0, S_H = 3, S_V = 4, S_PHI = 5, S_B = 10, S_G = 16, S_LP = 31, S_LE = 34 };
+
+__global__ void k_adj_side_pack(PassArrays a, const double* __restrict__ lam_dp, const double* __restrict__ lam_dE,
+                                double* __restrict__ rec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const long long n = a.n;
+    double* rc = rec + (long long)i * kAdjRec;
+    rc[S_X] = a.x[i];
+    rc[S_X + 1] = a.y[i];
+    rc[S_X + 2] = a.z[i];
+    rc[S_H] = a.H[i];
+    rc[S_V] = a.V[i];
+    rc[S_PHI] = a.rho[i];
+    rc[S_PHI + 1] = a.vx[i];
+    rc[S_PHI + 2] = a.vy[i];
+    rc[S_PHI + 3] = a.vz[i];
+    rc[S_PHI + 4] = a.P[i];
+    for (int k = 0; k < 6; k++) rc[S_B + k] = a.B[k * n + i];
+    for (int k = 0; k < 15; k++) rc[S_G + k] = a.grad[k * n + i];
+    for (int c = 0; c < 3; c++) rc[S_LP + c] = lam_dp[c * n + i];
+    rc[S_LE] = lam_dE[i];
+}
+
+__device__ __forceinline__ void side_of(const double* __restrict__ rc, Side& s) {
+    s.H = rc[S_H];
+    s.V = rc[S_V];
+#pragma unroll
+    for (int k = 0; k < 5; k++) s.phi[k] = rc[S_PHI + k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) s.B[k] = rc[S_B + k];
+#pragma unroll
+    for (int k = 0; k < 15; k++) s.g[k] = rc[S_G + k];
+}
+
+// Each particle reverses the flux of every pair in its flux list (with the
+// pair's canonical left/right order, as the forward) and keeps its own side.
+// Both records are loaded per pair in left/right order (the own one stays in
+// cache), so one inlined reverse serves both orders.
+#ifndef MFM_ADJ_PAIR_WAVES
+#define MFM_ADJ_PAIR_WAVES 1
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_ADJ_PAIR_WAVES))) void k_adj_pairs(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                    const int* __restrict__ list, const double* __restrict__ rec,
+                                                    AdjArrays aj) {
     const int i = xcd_block_adj() * 256 + threadIdx.x;
     if (i >= a.n) return;
     const long long n = a.n;
-    Side si, sj;
-    load_side(a, n, i, si);
-    const double xi[3] = {a.x[i], a.y[i], a.z[i]};
-    SideAdj own, other;
+    SideAdj own;
     zero_adj(own);
     double lx[3] = {0.0, 0.0, 0.0};
     const int cnum = counts[i];
     for (int k = 0; k < cnum; k++) {
         const int j = list[(long long)k * n + i];
-        load_side(a, n, j, sj);
         const bool iL = i < j;
+        const double* rL = rec + (long long)(iL ? i : j) * kAdjRec;
+        const double* rR = rec + (long long)(iL ? j : i) * kAdjRec;
+        Side sL, sR;
+        side_of(rL, sL);
+        side_of(rR, sR);
         // canonical displacement x_R - x_L as in the forward
+        const double xL[3] = {rL[S_X], rL[S_X + 1], rL[S_X + 2]};
         double d[3];
-        if (iL) {
-            disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
-        } else {
-            const double xj[3] = {a.x[j], a.y[j], a.z[j]};
-            disp(ph, xj, xi[0], xi[1], xi[2], d);
-        }
+        disp(ph, xL, rR[S_X], rR[S_X + 1], rR[S_X + 2], d);
         // dp_L -= Fp, dp_R += Fp
-        const int L = iL ? i : j, R = iL ? j : i;
         double lFp[3];
-        for (int c = 0; c < 3; c++) lFp[c] = lam_dp[c * n + R] - lam_dp[c * n + L];
-        const double lFE = lam_dE[R] - lam_dE[L];
-        zero_adj(other);
+        for (int c = 0; c < 3; c++) lFp[c] = rR[S_LP + c] - rL[S_LP + c];
+        const double lFE = rR[S_LE] - rL[S_LE];
         double ld[3] = {0.0, 0.0, 0.0};
-        if (iL) pair_reverse(si, sj, d, ph.gamma, lFp, lFE, own, other, ld);
-        else pair_reverse(sj, si, d, ph.gamma, lFp, lFE, other, own, ld);
+        pair_reverse(sL, sR, d, ph.gamma, lFp, lFE, iL, own, ld);
         // d = x_R - x_L
-        const double s = iL ? -1.0 : 1.0;
-        for (int c = 0; c < 3; c++) lx[c] += s * ld[c];
+        const double sg = iL ? -1.0 : 1.0;
+        for (int c = 0; c < 3; c++) lx[c] += sg * ld[c];
     }
     for (int c = 0; c < 3; c++) aj.acc_x[c * n + i] = lx[c];
     for (int f = 0; f < 5; f++) aj.acc_phi[f * n + i] = own.phi[f];
@@ -312,8 +332,59 @@ __global__ __launch_bounds__(256) void k_adj_pairs(PassArrays a, Phys ph, const 
 }
 
 // ------------------------------------------------------- gradient reverse
-__global__ __launch_bounds__(256) void k_adj_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
-                                                        const int* __restrict__ list, AdjArrays aj) {
+// The gradient stage of particle i sums over its gather set (j with r_ij < H_i).
+// Its reverse gives each such pair a term for i and a term for j.  Part one
+// (one thread per i) rebuilds the sums, reverses the limiter, E^-1 and the
+// sums, keeps the terms for i, and writes a record of what the terms for the
+// neighbours need; part two (one thread per j) walks j's flux list, which holds
+// every i whose gather set contains j, and adds the terms for j from the
+// records.  No thread writes another particle's sums except for the few
+// limiter extrema and the farthest neighbour, which take atomics in part one.
+//
+// Record per particle (kRec doubles): x, y, z, H, V, phi (5), the adjoint of
+// E as a full 3x3 matrix (9), the adjoints of the gradient sums S (15).
+constexpr int kRec = kAdjRec;
+enum { P_X = 0, P_H = 3, P_V = 4, P_PHI = 5, P_LE = 10, P_LS = 19 };
+static_assert(P_LS + 15 <= kRec, "record slots");
+// own-side adjoints of part one, read back by part two: phi (5), x (3)
+static_assert(kAdjOwn == 8, "own-side slots");
+
+struct PullArrays {
+    double* rec;   // kRec x n, particle-major
+    double* own;   // kOwn x n, field-major
+};
+
+// the term that pair (i -> j) of i's gather set gives j: adds to lphi (5) and
+// ld (3, the adjoint of d = x_j - x_i); the same expression serves part one
+__device__ __forceinline__ void grad_pair_terms(const double d[3], double r, double Hi, double Vi,
+                                                const double* LE, const double* lS, const double dphi[5],
+                                                double t[5], double ld[3], double& lpsi_out, double& W,
+                                                double& dWH) {
+    double dWr;
+    kernel_wdw(r, Hi, W, dWr, dWH);
+    const double psi = W * Vi;
+    double Ld[3], LTd[3];
+    for (int c = 0; c < 3; c++) {
+        Ld[c] = LE[3 * c] * d[0] + LE[3 * c + 1] * d[1] + LE[3 * c + 2] * d[2];
+        LTd[c] = LE[c] * d[0] + LE[3 + c] * d[1] + LE[6 + c] * d[2];
+    }
+    double lpsi = d[0] * Ld[0] + d[1] * Ld[1] + d[2] * Ld[2];
+    for (int c = 0; c < 3; c++) ld[c] = (Ld[c] + LTd[c]) * psi;
+    for (int f = 0; f < 5; f++) {
+        const double* ls = lS + 3 * f;
+        const double dl = d[0] * ls[0] + d[1] * ls[1] + d[2] * ls[2];
+        lpsi += dphi[f] * dl;
+        for (int c = 0; c < 3; c++) ld[c] += dphi[f] * psi * ls[c];
+        t[f] = psi * dl;
+    }
+    const double lW = lpsi * Vi;
+    if (r > 0.0)
+        for (int c = 0; c < 3; c++) ld[c] += lW * dWr * d[c] / r;
+    lpsi_out = lpsi;
+}
+
+__global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                                                       const int* __restrict__ list, AdjArrays aj, PullArrays pa) {
     const int i = xcd_block_adj() * 256 + threadIdx.x;
     if (i >= a.n) return;
     const long long n = a.n;
@@ -437,12 +508,23 @@ __global__ __launch_bounds__(256) void k_adj_gradients(PassArrays a, Phys ph, co
             for (int q = 0; q < 3; q++) Lam[c][q] += lg[c] * s[q];
         for (int q = 0; q < 3; q++) lS[3 * f + q] = Bf[q][0] * lg[0] + Bf[q][1] * lg[1] + Bf[q][2] * lg[2];
     }
-    // E^-1: lE = -B Lam B
-    double T[3][3], LE[3][3];
+    // E^-1: lE = -B Lam B (row-major 3x3)
+    double T[3][3], LE[9];
     for (int c = 0; c < 3; c++)
         for (int q = 0; q < 3; q++) T[c][q] = Lam[c][0] * Bf[0][q] + Lam[c][1] * Bf[1][q] + Lam[c][2] * Bf[2][q];
     for (int c = 0; c < 3; c++)
-        for (int q = 0; q < 3; q++) LE[c][q] = -(Bf[c][0] * T[0][q] + Bf[c][1] * T[1][q] + Bf[c][2] * T[2][q]);
+        for (int q = 0; q < 3; q++) LE[3 * c + q] = -(Bf[c][0] * T[0][q] + Bf[c][1] * T[1][q] + Bf[c][2] * T[2][q]);
+    // record for the neighbours' part two
+    double* rc = pa.rec + (long long)i * kRec;
+    rc[P_X] = xi[0];
+    rc[P_X + 1] = xi[1];
+    rc[P_X + 2] = xi[2];
+    rc[P_H] = Hi;
+    rc[P_V] = Vi;
+    for (int f = 0; f < 5; f++) rc[P_PHI + f] = phi_i[f];
+    for (int k = 0; k < 9; k++) rc[P_LE + k] = LE[k];
+    for (int k = 0; k < 15; k++) rc[P_LS + k] = lS[k];
+    // i's side of every pair of its gather set
     double lH = 0.0, lV = 0.0;
     double lxi[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < cnum; k++) {
@@ -450,40 +532,22 @@ __global__ __launch_bounds__(256) void k_adj_gradients(PassArrays a, Phys ph, co
         double d[3];
         disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        double W, dWr, dWH;
-        kernel_wdw(r, Hi, W, dWr, dWH);
-        const double psi = W * Vi;
         const double rho_j = a.m[j] * a.nk[j];
-        const double phi_j[5] = {rho_j, a.vx[j], a.vy[j], a.vz[j], (ph.gamma - 1.0) * rho_j * a.u[j]};
-        double Ld[3], LTd[3];
-        for (int c = 0; c < 3; c++) {
-            Ld[c] = LE[c][0] * d[0] + LE[c][1] * d[1] + LE[c][2] * d[2];
-            LTd[c] = LE[0][c] * d[0] + LE[1][c] * d[1] + LE[2][c] * d[2];
-        }
-        double lpsi = d[0] * Ld[0] + d[1] * Ld[1] + d[2] * Ld[2];
-        double ld[3];
-        for (int c = 0; c < 3; c++) ld[c] = (Ld[c] + LTd[c]) * psi;
-        for (int f = 0; f < 5; f++) {
-            const double* ls = lS + 3 * f;
-            const double dl = d[0] * ls[0] + d[1] * ls[1] + d[2] * ls[2];
-            const double dphi = phi_j[f] - phi_i[f];
-            lpsi += dphi * dl;
-            for (int c = 0; c < 3; c++) ld[c] += dphi * psi * ls[c];
-            const double t = psi * dl;
-            atomicAdd(&aj.acc_phi[f * n + j], t);
-            lphi_i[f] -= t;
-        }
-        const double lW = lpsi * Vi;
+        const double dphi[5] = {rho_j - phi_i[0], a.vx[j] - phi_i[1], a.vy[j] - phi_i[2], a.vz[j] - phi_i[3],
+                                (ph.gamma - 1.0) * rho_j * a.u[j] - phi_i[4]};
+        double t[5], ld[3], lpsi, W, dWH;
+        grad_pair_terms(d, r, Hi, Vi, LE, lS, dphi, t, ld, lpsi, W, dWH);
         lV += lpsi * W;
-        lH += lW * dWH;
-        if (r > 0.0)
-            for (int c = 0; c < 3; c++) ld[c] += lW * dWr * d[c] / r;
+        lH += lpsi * Vi * dWH;
+        for (int f = 0; f < 5; f++) lphi_i[f] -= t[f];
+        for (int c = 0; c < 3; c++) lxi[c] -= ld[c];
         if (j == jr && r > 0.0)
-            for (int c = 0; c < 3; c++) ld[c] += 0.5 * lhalf * d[c] / r;
-        for (int c = 0; c < 3; c++) {
-            atomicAdd(&aj.acc_x[c * n + j], ld[c]);
-            lxi[c] -= ld[c];
-        }
+            for (int c = 0; c < 3; c++) {
+                // the farthest neighbour sets the limiter's length: its term goes by atomic
+                const double th = 0.5 * lhalf * d[c] / r;
+                atomicAdd(&aj.acc_x[c * n + j], th);
+                lxi[c] -= th;
+            }
     }
     for (int f = 0; f < 5; f++) {
         if (lmax[f] != 0.0) {
@@ -495,16 +559,54 @@ __global__ __launch_bounds__(256) void k_adj_gradients(PassArrays a, Phys ph, co
             else atomicAdd(&aj.acc_phi[f * n + jmin[f]], lmin[f]);
         }
     }
-    for (int f = 0; f < 5; f++) atomicAdd(&aj.acc_phi[f * n + i], lphi_i[f]);
-    for (int c = 0; c < 3; c++) atomicAdd(&aj.acc_x[c * n + i], lxi[c]);
+    for (int f = 0; f < 5; f++) pa.own[f * n + i] = lphi_i[f];
+    for (int c = 0; c < 3; c++) pa.own[(5 + c) * n + i] = lxi[c];
     aj.acc_H[i] += lH;
     aj.acc_V[i] += lV;
 }
 
+__global__ __launch_bounds__(256) void k_adj_grad_pull(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                        const int* __restrict__ list, AdjArrays aj, PullArrays pa) {
+    const int j = xcd_block_adj() * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const long long n = a.n;
+    const double xj[3] = {a.x[j], a.y[j], a.z[j]};
+    const double rho_j = a.m[j] * a.nk[j];
+    const double phi_j[5] = {rho_j, a.vx[j], a.vy[j], a.vz[j], (ph.gamma - 1.0) * rho_j * a.u[j]};
+    double lphi[5], lx[3];
+    for (int f = 0; f < 5; f++) lphi[f] = pa.own[f * n + j];
+    for (int c = 0; c < 3; c++) lx[c] = pa.own[(5 + c) * n + j];
+    const int cnum = counts[j];
+    for (int k = 0; k < cnum; k++) {
+        const int i = list[(long long)k * n + j];
+        const double* rc = pa.rec + (long long)i * kRec;
+        const double xi[3] = {rc[P_X], rc[P_X + 1], rc[P_X + 2]};
+        const double Hi = rc[P_H];
+        double d[3];
+        disp(ph, xi, xj[0], xj[1], xj[2], d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(r < Hi)) continue;   // j is not in i's gather set
+        double LE[9], lS[15], dphi[5];
+        for (int q = 0; q < 9; q++) LE[q] = rc[P_LE + q];
+        for (int q = 0; q < 15; q++) lS[q] = rc[P_LS + q];
+        for (int f = 0; f < 5; f++) dphi[f] = phi_j[f] - rc[P_PHI + f];
+        double t[5], ld[3], lpsi, W, dWH;
+        grad_pair_terms(d, r, Hi, rc[P_V], LE, lS, dphi, t, ld, lpsi, W, dWH);
+        for (int f = 0; f < 5; f++) lphi[f] += t[f];
+        for (int c = 0; c < 3; c++) lx[c] += ld[c];
+    }
+    for (int f = 0; f < 5; f++) aj.acc_phi[f * n + j] += lphi[f];
+    for (int c = 0; c < 3; c++) aj.acc_x[c * n + j] += lx[c];
+}
+
 // ---------------------------------------------- kernel-length reverse and outputs
-__global__ __launch_bounds__(256) void k_adj_length(PassArrays a, Phys ph, const int* __restrict__ gcount,
-                                                     const int* __restrict__ list, AdjArrays aj,
-                                                     double* __restrict__ out_v, double* __restrict__ out_u) {
+// Same split: part one (per i) finishes the outputs of i, the factor of its
+// radial terms and its own side; part two (per j) adds the terms of the pairs
+// whose gather set holds j.  Record: x, y, z, H, factor (in the first slots of
+// the gradient record).
+__global__ __launch_bounds__(256) void k_adj_length_own(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                                                         const int* __restrict__ list, AdjArrays aj, PullArrays pa,
+                                                         double* __restrict__ out_v, double* __restrict__ out_u) {
     const int i = xcd_block_adj() * 256 + threadIdx.x;
     if (i >= a.n) return;
     const long long n = a.n;
@@ -534,6 +636,14 @@ __global__ __launch_bounds__(256) void k_adj_length(PassArrays a, Phys ph, const
     const double c32 = 32.0 / 3.0;
     const double PhiH = -c32 * sqdw / Hi;
     const double kift = -lH / PhiH;   // dH = -dPhi / PhiH
+    // dn/dr = nrm w' / H ; dPhi/dr = (32/3) w' / H
+    const double fac = (ln * nrm + kift * c32) / Hi;
+    double* rc = pa.rec + (long long)i * kRec;
+    rc[P_X] = xi[0];
+    rc[P_X + 1] = xi[1];
+    rc[P_X + 2] = xi[2];
+    rc[P_H] = Hi;
+    rc[P_V] = fac;
     double lxi[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < cnum; k++) {
         const int j = list[(long long)k * n + i];
@@ -542,16 +652,35 @@ __global__ __launch_bounds__(256) void k_adj_length(PassArrays a, Phys ph, const
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         if (!(r > 0.0)) continue;
         const double q = r / Hi;
-        const double dw = spline_qdw(q) / q;   // w'(q)
-        // dn/dr = nrm w' / H ; dPhi/dr = (32/3) w' / H
-        const double lr = (ln * nrm + kift * c32) * dw / Hi;
-        for (int c = 0; c < 3; c++) {
-            const double t = lr * d[c] / r;
-            atomicAdd(&aj.acc_x[c * n + j], t);
-            lxi[c] -= t;
-        }
+        const double lr = fac * (spline_qdw(q) / q);   // w'(q)
+        for (int c = 0; c < 3; c++) lxi[c] -= lr * d[c] / r;
     }
-    for (int c = 0; c < 3; c++) atomicAdd(&aj.acc_x[c * n + i], lxi[c]);
+    for (int c = 0; c < 3; c++) pa.own[(5 + c) * n + i] = lxi[c];
+}
+
+__global__ __launch_bounds__(256) void k_adj_length_pull(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                          const int* __restrict__ list, AdjArrays aj, PullArrays pa) {
+    const int j = xcd_block_adj() * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const long long n = a.n;
+    const double xj[3] = {a.x[j], a.y[j], a.z[j]};
+    double lx[3];
+    for (int c = 0; c < 3; c++) lx[c] = pa.own[(5 + c) * n + j];
+    const int cnum = counts[j];
+    for (int k = 0; k < cnum; k++) {
+        const int i = list[(long long)k * n + j];
+        const double* rc = pa.rec + (long long)i * kRec;
+        const double xi[3] = {rc[P_X], rc[P_X + 1], rc[P_X + 2]};
+        const double Hi = rc[P_H];
+        double d[3];
+        disp(ph, xi, xj[0], xj[1], xj[2], d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(r < Hi) || !(r > 0.0)) continue;
+        const double q = r / Hi;
+        const double lr = rc[P_V] * (spline_qdw(q) / q);
+        for (int c = 0; c < 3; c++) lx[c] += lr * d[c] / r;
+    }
+    for (int c = 0; c < 3; c++) aj.acc_x[c * n + j] += lx[c];
 }
 
 void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts, const int* gcount,
@@ -565,10 +694,16 @@ void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts,
     aj.acc_V = scratch + 6 * n;
     aj.acc_B = scratch + 7 * n;
     aj.acc_g = scratch + 13 * n;
+    PullArrays pa;
+    pa.rec = scratch + kAdjPullOffset * n;
+    pa.own = pa.rec + kAdjRec * n;
     const int blocks = (int)((n + 255) / 256);
-    k_adj_pairs<<<blocks, 256, 0, s>>>(a, ph, counts, list, lam_dp, lam_dE, aj);
-    k_adj_gradients<<<blocks, 256, 0, s>>>(a, ph, gcount, list, aj);
-    k_adj_length<<<blocks, 256, 0, s>>>(a, ph, gcount, list, aj, out_v, out_u);
+    k_adj_side_pack<<<blocks, 256, 0, s>>>(a, lam_dp, lam_dE, pa.rec);
+    k_adj_pairs<<<blocks, 256, 0, s>>>(a, ph, counts, list, pa.rec, aj);
+    k_adj_grad_own<<<blocks, 256, 0, s>>>(a, ph, gcount, list, aj, pa);
+    k_adj_grad_pull<<<blocks, 256, 0, s>>>(a, ph, counts, list, aj, pa);
+    k_adj_length_own<<<blocks, 256, 0, s>>>(a, ph, gcount, list, aj, pa, out_v, out_u);
+    k_adj_length_pull<<<blocks, 256, 0, s>>>(a, ph, counts, list, aj, pa);
 }
 
 // ------------------------------------------------------------ step reverse

@@ -263,15 +263,7 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     return MFM_OK;
 }
 
-static Counters* counter_slot(mfm_ctx* c, int k) {
-    return (Counters*)((char*)c->cnt + (size_t)k * kCounterStride);
-}
-
-static void reset_counters(mfm_ctx* c, hipStream_t s) {
-    launch_fill_u64(kCounterCopies * kCounterStride / 8, (unsigned long long*)c->cnt, 0ull, s);
-    // first_bad starts at "none" in every copy
-    for (int k = 0; k < kCounterCopies; k++) launch_fill_u64(1, &counter_slot(c, k)->first_bad, ~0ull, s);
-}
+static void reset_counters(mfm_ctx* c, hipStream_t s) { launch_reset_counters(c->cnt, s); }
 
 static mfm_status check_particles(mfm_ctx* c, const mfm_particles* p) {
     if (!c) return MFM_E_INVALID;
@@ -596,7 +588,6 @@ mfm_status mfm_copy_flux_lists(mfm_ctx* c, int32_t* counts, int32_t* list, void*
 }  // extern "C"
 
 // ------------------------------------------------------------------ adjoints
-static const int kAdjSlots = 56;   // doubles per particle of adjoint scratch
 
 static mfm_status ensure_adj(mfm_ctx* c) {
     if (c->adj) return MFM_OK;
@@ -639,21 +630,29 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     hipStream_t s = (hipStream_t)stream;
     const long long n = ck->n;
     // 1. forward recompute of the step from the checkpoint, on the work set
-    auto cp = [&](double* dst, const double* src, long long len) {
-        hipMemcpyAsync(dst, src, sizeof(double) * len, hipMemcpyDeviceToDevice, s);
-    };
-    cp(w->x, ck->x, n);
-    cp(w->y, ck->y, n);
-    cp(w->z, ck->z, n);
-    cp(w->m, ck->m, n);
-    cp(w->vx, ck->vx, n);
-    cp(w->vy, ck->vy, n);
-    cp(w->vz, ck->vz, n);
-    cp(w->u, ck->u, n);
-    cp(w->H, ck->H, n);
-    cp(w->dp, ck->dp, 3 * n);
-    cp(w->dE, ck->dE, n);
-    if (w->id && ck->id) hipMemcpyAsync(w->id, ck->id, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s);
+    // (the checkpoint's arrays copied in one launch)
+    {
+        GatherBatch cb;
+        cb.count = 0;
+        auto cp = [&](void* dst, const void* src) {
+            cb.src[cb.count] = (const unsigned long long*)src;
+            cb.dst[cb.count] = (unsigned long long*)dst;
+            cb.count++;
+        };
+        cp(w->x, ck->x);
+        cp(w->y, ck->y);
+        cp(w->z, ck->z);
+        cp(w->m, ck->m);
+        cp(w->vx, ck->vx);
+        cp(w->vy, ck->vy);
+        cp(w->vz, ck->vz);
+        cp(w->u, ck->u);
+        cp(w->H, ck->H);
+        for (int k = 0; k < 3; k++) cp(w->dp + k * n, ck->dp + k * n);
+        cp(w->dE, ck->dE);
+        if (w->id && ck->id) cp(w->id, ck->id);
+        launch_copy_batch((int)n, cb, s);
+    }
     reset_counters(c, s);
     PassArrays a = arrays_of(w);
     launch_kick_drift(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, s);

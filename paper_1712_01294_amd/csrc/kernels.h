@@ -38,6 +38,10 @@ void launch_keys(int n, const double* x, const double* y, const double* z, const
                  unsigned long long* keys, int* idx, hipStream_t s);
 void launch_gather(int n, const GatherBatch& gb, const int* idx, hipStream_t s);
 void launch_fill_u64(long long m, unsigned long long* p, unsigned long long v, hipStream_t s);
+// all counter copies to their start values in one launch
+void launch_reset_counters(Counters* c, hipStream_t s);
+// dst[a][k] = src[a][k], k < n, for the arrays of the batch in one launch
+void launch_copy_batch(int n, const GatherBatch& gb, hipStream_t s);
 void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s);
 void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s);
 
@@ -61,6 +65,14 @@ void launch_dt_min(int n, const double* H, const double* vsig, double* partial, 
 int dt_min_parts(int n);
 
 // adjoint.hip
+// Adjoint scratch, doubles per particle: 0-27 pass accumulators, 28-55 step
+// reverse, then the per-particle records the pass reverse pulls through the
+// flux lists (kAdjRec) and its own-side terms (kAdjOwn).
+constexpr int kAdjRec = 36;
+constexpr int kAdjOwn = 8;
+constexpr int kAdjPullOffset = 56;
+constexpr int kAdjSlots = kAdjPullOffset + kAdjRec + kAdjOwn;
+
 void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts, const int* gcount,
                          const int* list, const double* lam_dp, const double* lam_dE, double* scratch,
                          double* out_x, double* out_v, double* out_u, hipStream_t s);

@@ -5,6 +5,8 @@
 // contiguous run of particles.  The build is: quantise positions -> keys,
 // stable LSD radix sort (8-bit digits, wave-ballot ranking), reorder the
 // particle arrays in place, fill (start, end) per occupied cell per level.
+#include <stddef.h>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -222,6 +224,21 @@ __global__ void k_fill_u64(long long m, unsigned long long* __restrict__ p, unsi
     for (; i < m; i += stride) p[i] = v;
 }
 
+// every counter word zero except first_bad of each copy, which starts at "none"
+__global__ void k_reset_counters(unsigned long long* __restrict__ p) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int per = kCounterStride / 8;
+    if (w >= kCounterCopies * per) return;
+    p[w] = (w % per) == (int)(offsetof(Counters, first_bad) / 8) ? ~0ull : 0ull;
+}
+
+// dst[a][k] = src[a][k] for every array of the batch (8-byte elements)
+__global__ void k_copy_batch(int n, GatherBatch gb) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    for (int a = 0; a < gb.count; a++) gb.dst[a][k] = gb.src[a][k];
+}
+
 // ----------------------------------------------------------- cell tables
 __global__ void k_tables(int n, const unsigned long long* __restrict__ keys, TreeDesc td,
                          int2* __restrict__ tab) {
@@ -254,6 +271,16 @@ void launch_keys(int n, const double* x, const double* y, const double* z, const
 
 void launch_gather(int n, const GatherBatch& gb, const int* idx, hipStream_t s) {
     k_gather_batch<<<(n + 255) / 256, 256, 0, s>>>(n, gb, idx);
+}
+
+void launch_reset_counters(Counters* c, hipStream_t s) {
+    constexpr int words = kCounterCopies * kCounterStride / 8;
+    k_reset_counters<<<(words + 255) / 256, 256, 0, s>>>((unsigned long long*)c);
+}
+
+void launch_copy_batch(int n, const GatherBatch& gb, hipStream_t s) {
+    if (n <= 0 || gb.count <= 0) return;
+    k_copy_batch<<<(n + 255) / 256, 256, 0, s>>>(n, gb);
 }
 
 void launch_fill_u64(long long m, unsigned long long* p, unsigned long long v, hipStream_t s) {
