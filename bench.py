@@ -61,7 +61,8 @@ def algorithmic(kernel, n, G, F, P):
     raise KeyError(kernel)
 
 
-KERNEL_NAMES = {"solve_h": "k_solve_h", "gradients": "k_gradients<false>", "hydro_fluxes": "k_fluxes_f64"}
+KERNEL_NAMES = {"solve_h": "k_solve_h + k_solve_h_wave + k_solve_h_fallback", "gradients": "k_gradients<false>",
+                "hydro_fluxes": "k_fluxes_f64"}
 KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/csrc/device.h",
                   "paper_1712_01294_amd/csrc/kernels.h")
 

@@ -111,7 +111,7 @@ typedef struct {
     int64_t first_bad;       /* lowest particle index flagged by any of the above   */
     double cond_max_seen;    /* largest ||E||_F ||B||_F                             */
     int64_t h_rounds_max;    /* most neighbour scans one kernel-length solve needed */
-    int64_t h_fallback;      /* particles solved one by one (very long gather sets) */
+    int64_t h_fallback;      /* particles solved one wave each after the group scan */
     int64_t h_rounds3;       /* particles whose solve needed three or more scans    */
     int64_t gather_entries;  /* gather-set entries of the last solve_h, self excluded */
 } mfm_counters;
@@ -221,10 +221,11 @@ int32_t mfm_max_ngb(const mfm_ctx *ctx);
 
 /*
  * Kernel timing, a measurement aid outside the method itself.  While enabled,
- * every launch of the three pass kernels (the kernel-length scan of
- * mfm_solve_h, the gradient kernel of mfm_gradients, the flux kernel of
- * mfm_hydro_fluxes) is bracketed by a pair of HIP events recorded on the
- * call's stream, so the elapsed time is that kernel's alone.
+ * every launch of the pass kernels is bracketed by a pair of HIP events
+ * recorded on the call's stream: the kernel-length kernels of mfm_solve_h
+ * (group scan, per-particle list solver and rescanning solver, which run back
+ * to back; the counter and list resets before them are outside), the
+ * gradient kernel of mfm_gradients, the flux kernel of mfm_hydro_fluxes.
  *  - mfm_set_kernel_timing(ctx, 1) enables timing and zeroes the totals;
  *    mfm_set_kernel_timing(ctx, 0) disables it.  Events are created by the
  *    library on first use and released by mfm_destroy.

@@ -37,6 +37,8 @@ struct mfm_ctx {
     int *counts = nullptr, *gcount = nullptr, *list = nullptr;
     int* fb_list = nullptr;               // particles handed to the per-particle kernel-length solve
     unsigned long long* fb_count = nullptr;
+    int* fb2_list = nullptr;              // particles the list solver hands to the rescanning one
+    unsigned long long* fb2_count = nullptr;
     void* rec = nullptr;                  // 32 x 8 B per particle
     double4* prim = nullptr;              // 128 B per particle: what gradients read of a neighbour
     double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
@@ -192,7 +194,7 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -246,6 +248,8 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->list, sizeof(int) * n * c->ph.max_ngb, "flux lists");
     alloc((void**)&c->fb_list, sizeof(int) * n, "fallback list");
     alloc((void**)&c->fb_count, sizeof(unsigned long long), "fallback count");
+    alloc((void**)&c->fb2_list, sizeof(int) * n, "second fallback list");
+    alloc((void**)&c->fb2_count, sizeof(unsigned long long), "second fallback count");
     alloc((void**)&c->rec, sizeof(double) * 32 * n, "records");
     alloc((void**)&c->prim, sizeof(double4) * 4 * n, "neighbour records");
     alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
@@ -356,7 +360,7 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     PassArrays a = arrays_of(p);
     const auto ev = clock_take(c, MFM_KERNEL_SOLVE_H);
     launch_solve_h(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
-                   c->fb_list, c->fb_count, ev.first, ev.second, s);
+                   c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, ev.first, ev.second, s);
     c->have_h = 1;
     c->have_grad = 0;
     c->last = s;

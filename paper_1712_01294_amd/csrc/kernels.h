@@ -48,8 +48,8 @@ void launch_pos4(int n, const double* x, const double* y, const double* z, doubl
 // pass.hip
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
-                    int* counts, int* fb_list, unsigned long long* fb_count, hipEvent_t t0, hipEvent_t t1,
-                    hipStream_t s);
+                    int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
+                    unsigned long long* fb2_count, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
                       double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,

@@ -68,9 +68,11 @@ __device__ __forceinline__ void displacement(const Phys& ph, const double xi[3],
 // lane whose R holds too few neighbours, or more than the list holds, adjusts R
 // and scans again.  Scans are wave-cooperative: each pass takes the lanes whose
 // trial radius is within a factor two of the largest one and lie close to the
-// first of them, and scans their union once.  Particles still without a
-// bracket go to the per-particle fallback.  After the root, the indices with
-// r < H (self excluded) are compacted in place: the gather part of the flux list.
+// first of them, and scans their union once.  Particles the first round leaves
+// without a bracket go to the per-particle list solver, one wave each, and the
+// few it cannot finish to the rescanning solver.  After the root, the indices
+// with r < H (self excluded) are compacted in place: the gather part of the
+// flux list.
 
 // Local density from the 3x3x3 block of cells around the particle's own cell,
 // on the finest level where the block holds at least kColdCount particles (so
@@ -150,6 +152,28 @@ __device__ double cold_guess(const TreeDesc& td, const int2* __restrict__ tab, c
 
 constexpr double kNewtonTail = 1e-9;   // last Newton step accepted without a check pass
 
+// One safeguarded Newton update from the residual f and slope fp at Hc, inside
+// the bracket (lo, hi]; true when Hc is final.  The sum is twice continuously
+// differentiable in H (so is the spline), so Newton converges quadratically:
+// after a step below kNewtonTail H the new iterate is within a small multiple
+// of kNewtonTail^2 H (a few 1e-18 relative) of the root and is returned without
+// another pass.  It is taken even at a bracket edge: an earlier iterate can
+// land on the root and become lo or hi.
+__device__ __forceinline__ bool newton_step(double f, double fp, double& lo, double& hi, double& Hc) {
+    if (f == 0.0) return true;
+    if (f < 0.0) lo = Hc;
+    else hi = Hc;
+    double Hn = Hc - f / fp;
+    if (fabs(Hn - Hc) <= kNewtonTail * Hc) {
+        Hc = fmin(hi, fmax(lo, Hn));
+        return true;
+    }
+    if (!(Hn > lo && Hn <= hi)) Hn = 0.5 * (lo + hi);
+    const double dH = fabs(Hn - Hc);
+    Hc = Hn;
+    return dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi);
+}
+
 // safeguarded Newton on the m radii rl[k * n + i]; returns converged
 __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int m, double n_ngb, int maxit,
                          double& lo, double& hi, double& Hc, unsigned long long& iters) {
@@ -164,41 +188,25 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
             s += spline_w(q);
             sq += spline_qdw(q);
         }
-        const double f = c32 * s - n_ngb;
-        if (f == 0.0) return true;
-        if (f < 0.0) lo = Hc;
-        else hi = Hc;
-        const double fp = -c32 * sq * iH;
-        double Hn = Hc - f / fp;
-        // The sum is twice continuously differentiable in H (so is the spline),
-        // so Newton converges quadratically: after a step below kNewtonTail H the
-        // new iterate is within a small multiple of kNewtonTail^2 H (a few 1e-18
-        // relative) of the root and is returned without another pass.  It is
-        // taken even at a bracket edge: an earlier iterate can land on the root
-        // and become lo or hi.
-        if (fabs(Hn - Hc) <= kNewtonTail * Hc) {
-            Hc = fmin(hi, fmax(lo, Hn));
-            return true;
-        }
-        if (!(Hn > lo && Hn <= hi)) Hn = 0.5 * (lo + hi);
-        const double dH = fabs(Hn - Hc);
-        Hc = Hn;
-        if (dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi)) return true;
+        if (newton_step(c32 * s - n_ngb, -c32 * sq * iH, lo, hi, Hc)) return true;
     }
     return false;
 }
 
-constexpr int kScanRounds = 12;   // scans per particle before the fallback takes it
+// Group scans per particle: particles the first round does not finish (no
+// bracket yet, or more radii than the list holds) go to the per-particle solver,
+// which is cheaper for them than further group passes over a sparse class.
+constexpr int kScanRounds = 1;
 #ifndef MFM_COLD_PAD
-#define MFM_COLD_PAD 1.1
+#define MFM_COLD_PAD 1.05
 #endif
 constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
 #ifndef MFM_WARM_PAD
-#define MFM_WARM_PAD 1.05
+#define MFM_WARM_PAD 1.03
 #endif
 constexpr double kWarmPad = MFM_WARM_PAD;   // first scan radius over the previous H
 #ifndef MFM_STORE_COLD
-#define MFM_STORE_COLD 1.1
+#define MFM_STORE_COLD 1.05
 #endif
 constexpr double kStoreCold = MFM_STORE_COLD;   // radii listed by a cold first scan, over the guess
 // a scan pass takes the lanes with R >= kClassRatio Rref within kClassWindow Rref
@@ -377,9 +385,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         gcount[i] = c;
         counts[i] = c;
     } else if (act) {
-        // hand over to the per-particle solver, which starts from this bracket
+        // hand over to the per-particle solver: the bracket and the next trial
+        // radius, in the particle's own (now unused) radius slots 0-2
         const unsigned long long slot = atomicAdd(fb_count, 1ull);
         if (slot < (unsigned long long)a.n) fb_list[slot] = i;
+        rl[i] = lo;
+        rl[n + i] = hi;
+        rl[2 * n + i] = R;
         a.H[i] = (hi < INFINITY) ? hi : (lo > 0.0 ? lo : guess);
     }
     const unsigned long long rr = (unsigned long long)rounds;
@@ -389,8 +401,194 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     count_add(&cnt->h_rounds3, rounds >= 3 ? 1ull : 0ull);
 }
 
-// Solve for the few particles the group scan handed over (no bracket within
-// the scan rounds, or more radii than the list holds): one wave per particle,
+// Particles the group scan hands over, one wave each.  The wave scans the cells
+// within a trial radius once and keeps every radius and index within it in
+// registers (entry e on lane e mod 64, slot e / 64, scan order), narrows the
+// bracket with the weighted count at that radius, and once the radius brackets
+// the root with every radius kept, runs Newton on them with wave-wide sums in
+// a fixed order.  Particles whose radii do not fit, or that find no bracket
+// within kWaveScans scans, go on to the rescanning solver below.
+constexpr int kWaveSlots = 3;   // entries per lane kept by the list solver (ra, rb, rc)
+constexpr int kWaveScans = 16;
+#ifndef MFM_WAVE_BLOCKS
+#define MFM_WAVE_BLOCKS 16384
+#endif
+constexpr int kWaveBlocks = MFM_WAVE_BLOCKS;   // waves of the list solver, striding over its particles
+
+__global__ __launch_bounds__(64) void k_solve_h_wave(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                      const double4* __restrict__ pos, Phys ph, Counters* cnt,
+                                                      const int* __restrict__ fb_list,
+                                                      const unsigned long long* __restrict__ fb_count,
+                                                      const double* __restrict__ hand, int* __restrict__ jl,
+                                                      int* __restrict__ gcount, int* __restrict__ counts,
+                                                      int* __restrict__ fb2_list,
+                                                      unsigned long long* __restrict__ fb2_count) {
+    cnt = counter_copy(cnt);
+    __shared__ ScanLds S;
+    const int lane = threadIdx.x;
+    const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
+    if (blockIdx.x == 0 && lane == 0) cnt->h_fallback = *fb_count;
+    const long long n = a.n;
+    constexpr int kKeep = kWaveSlots * kWave;
+    const double c32 = 32.0 / 3.0;
+    double half = INFINITY;
+    for (int d = 0; d < 3; d++)
+        if (ph.periodic[d]) half = fmin(half, 0.5 * ph.box[d]);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long iters = 0, iters_max = 0, over = 0, scans_max = 0, many = 0;
+    for (unsigned long long t = blockIdx.x; t < nfb; t += gridDim.x) {
+        const unsigned long long iters0 = iters;
+        const int i = __builtin_amdgcn_readfirstlane(fb_list[t]);
+        const double4 pi = pos[i];
+        const double xi[3] = {uniform_d(pi.x), uniform_d(pi.y), uniform_d(pi.z)};
+        double lo = uniform_d(hand[i]), hi = uniform_d(hand[n + i]), R = uniform_d(hand[2 * n + i]);
+        if (!(R > lo)) R = (hi < INFINITY) ? hi : 1.3 * lo;
+        // the kept entries of this lane: slots 0-2 (named, so they stay in registers)
+        double ra = INFINITY, rb = INFINITY, rc = INFINITY;
+        int ja = -1, jb = -1, jc = -1;
+        int m = 0, scans = 0;
+        double neff_hi = 0.0;
+        bool bracketed = false;
+        while (scans < kWaveScans) {
+            if (!(R < half)) R = half * (1.0 - 1e-12);
+            if (!(R > lo)) break;
+            scans++;
+            iters++;
+            const double R2 = R * R, iR = 1.0 / R;
+            double sw = 0.0;
+            m = 0;
+            ra = rb = rc = INFINITY;
+            ja = jb = jc = -1;
+            scan_cells(td, tab, pos, S, lane, xi, xi, R, [&](const double4& q, bool valid, int, int wrap) {
+                const double r2 = sq_disp(q, xi, wrap, td.box);
+                const bool in = valid && r2 < R2;
+                const double r = sqrt(r2);
+                if (in) sw += spline_w(r * iR);
+                // new entries m .. m + cin - 1 go to lanes (m + rank) mod 64; the
+                // other lanes send to the remaining lanes, so every lane gets one value
+                const unsigned long long b = __ballot(in);
+                const int cin = __popcll(b);
+                const int rank = in ? __popcll(b & below) : cin + __popcll(~b & below);
+                const int dest = (m + rank) & (kWave - 1);
+                const long long rbits = __double_as_longlong(r);
+                const int rlo = __builtin_amdgcn_ds_permute(dest * 4, (int)rbits);
+                const int rhi = __builtin_amdgcn_ds_permute(dest * 4, (int)(rbits >> 32));
+                const int jv = __builtin_amdgcn_ds_permute(dest * 4, (int)__double_as_longlong(q.w));
+                const int off = (lane - m) & (kWave - 1);
+                if (off < cin) {
+                    const int sl = (m + off) / kWave;
+                    const double rv = __longlong_as_double(((long long)rhi << 32) | (unsigned)rlo);
+                    ra = sl == 0 ? rv : ra;
+                    ja = sl == 0 ? jv : ja;
+                    rb = sl == 1 ? rv : rb;
+                    jb = sl == 1 ? jv : jb;
+                    rc = sl == 2 ? rv : rc;
+                    jc = sl == 2 ? jv : jc;
+                }
+                m += cin;
+            });
+            sw = uniform_d(wave_sum_d(sw));
+            const double neff = c32 * sw;
+            if (m > kKeep) {
+                // too many radii to keep; below n_ngb the root lies beyond them all
+                if (neff < ph.n_ngb) break;
+                hi = fmin(hi, R);
+                R = fmax(lo + 0.25 * (hi - lo), fmin(1.05 * R * cbrt(ph.n_ngb / neff), R * cbrt(0.8 * kKeep / m)));
+                if (!(R < hi)) R = 0.5 * (lo + hi);
+            } else if (neff < ph.n_ngb) {
+                lo = R;
+                if (hi < INFINITY) {
+                    R = hi;
+                } else {
+                    const double g = 1.1 * cbrt(ph.n_ngb / fmax(neff, 1e-300));
+                    R *= fmin(4.0, fmax(1.15, g));
+                }
+            } else {
+                hi = R;
+                neff_hi = neff;
+                bracketed = true;
+                break;
+            }
+        }
+        bool conv = false;
+        double Hc = hi;
+        if (bracketed) {
+            Hc = hi * cbrt(ph.n_ngb / neff_hi);
+            if (!(Hc > lo && Hc <= hi)) Hc = 0.5 * (lo + hi);
+            for (int it = 0; it < ph.h_maxit; it++) {
+                iters++;
+                const double iH = 1.0 / Hc;
+                double s = 0.0, sq = 0.0;
+                const double rs[kWaveSlots] = {ra, rb, rc};
+#pragma unroll
+                for (int sl = 0; sl < kWaveSlots; sl++)
+                    if (sl * kWave + lane < m) {
+                        const double q = rs[sl] * iH;
+                        s += spline_w(q);
+                        sq += spline_qdw(q);
+                    }
+                s = uniform_d(wave_sum_d(s));
+                sq = uniform_d(wave_sum_d(sq));
+                if (newton_step(c32 * s - ph.n_ngb, -c32 * sq * iH, lo, hi, Hc)) {
+                    conv = true;
+                    break;
+                }
+            }
+        }
+        if (!conv) {
+            // on to the rescanning solver, which grows a bracket from a.H
+            if (lane == 0) {
+                const unsigned long long slot = atomicAdd(fb2_count, 1ull);
+                if (slot < (unsigned long long)a.n) fb2_list[slot] = i;
+                a.H[i] = (hi < INFINITY) ? hi : R;
+            }
+            continue;
+        }
+        // gather list: every kept index with r < H but the particle itself, in scan order
+        const double iH = 1.0 / Hc;
+        double sum = 0.0;
+        int c = 0;
+        const double rs[kWaveSlots] = {ra, rb, rc};
+        const int js[kWaveSlots] = {ja, jb, jc};
+#pragma unroll
+        for (int sl = 0; sl < kWaveSlots; sl++) {
+            const bool have = sl * kWave + lane < m;
+            if (have) sum += spline_w(rs[sl] * iH);
+            const bool in = have && rs[sl] < Hc && js[sl] != i;
+            const unsigned long long b = __ballot(in);
+            const int slot = c + __popcll(b & below);
+            if (in && slot < ph.max_ngb) jl[(long long)slot * n + i] = js[sl];
+            c += __popcll(b);
+        }
+        sum = wave_sum_d(sum);
+        if (c > ph.max_ngb) {
+            c = ph.max_ngb;
+            over = 1;
+            if (lane == 0) flag_index(cnt, i);
+        }
+        if (lane == 0) {
+            const double nk = kernel_norm(Hc) * sum;
+            a.H[i] = Hc;
+            a.nk[i] = nk;
+            a.V[i] = 1.0 / nk;
+            gcount[i] = c;
+            counts[i] = c;
+        }
+        iters_max = max(iters_max, iters - iters0);
+        scans_max = max(scans_max, (unsigned long long)scans);
+        many += (1 + scans >= 3) ? 1ull : 0ull;
+    }
+    if (lane == 0) {
+        if (iters) atomicAdd(&cnt->h_iters, iters);
+        if (iters_max) atomicMax(&cnt->h_iters_max, iters_max);
+        if (scans_max) atomicMax(&cnt->h_rounds_max, 1 + scans_max);
+        if (many) atomicAdd(&cnt->h_rounds3, many);
+        if (over) atomicAdd(&cnt->overflow, over);
+    }
+}
+
+// Solve for the few particles the list solver handed on (no bracket within its
+// scans, or more radii than it keeps): one wave per particle,
 // every residual evaluation scans the cells within H again with the lanes
 // splitting the particles, so there is no limit on the number of neighbours.
 // The bracket grows from the handed-over H until it holds the root, then
@@ -405,7 +603,6 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
     __shared__ ScanLds S;
     const int lane = threadIdx.x;
     const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
-    if (blockIdx.x == 0 && lane == 0) cnt->h_fallback = *fb_count;
     const long long n = a.n;
     const double c32 = 32.0 / 3.0;
     double half = INFINITY;
@@ -458,22 +655,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
             for (int it = 0; it < ph.h_maxit; it++) {
                 iters++;
                 eval(Hc, f, fp, nk);
-                if (f == 0.0) {
-                    conv = true;
-                    break;
-                }
-                if (f < 0.0) lo = Hc;
-                else hi = Hc;
-                double Hn = Hc - f / fp;
-                if (fabs(Hn - Hc) <= kNewtonTail * Hc) {
-                    Hc = fmin(hi, fmax(lo, Hn));
-                    conv = true;
-                    break;
-                }
-                if (!(Hn > lo && Hn <= hi)) Hn = 0.5 * (lo + hi);
-                const double dH = fabs(Hn - Hc);
-                Hc = Hn;
-                if (dH <= 1e-14 * Hc || !(hi - lo > 4e-16 * hi)) {
+                if (newton_step(f, fp, lo, hi, Hc)) {
                     conv = true;
                     break;
                 }
@@ -1103,16 +1285,19 @@ constexpr int kFallbackWaves = 1024;
 
 void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
-                    int* counts, int* fb_list, unsigned long long* fb_count, hipEvent_t t0, hipEvent_t t1,
-                    hipStream_t s) {
+                    int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
+                    unsigned long long* fb2_count, hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
     launch_fill_u64(1, fb_count, 0ull, s);
+    launch_fill_u64(1, fb2_count, 0ull, s);
     if (t0) hipEventRecord(t0, s);
     k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
                                                   fb_list, fb_count);
-    if (t1) hipEventRecord(t1, s);
-    // one wave per handed-over particle, striding over the count the solve left on the device
-    k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, list, gcount,
+    // one wave per handed-over particle, striding over the count left on the device
+    k_solve_h_wave<<<kWaveBlocks, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, rl, list, gcount,
+                                              counts, fb2_list, fb2_count);
+    k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb2_list, fb2_count, list, gcount,
                                                      counts);
+    if (t1) hipEventRecord(t1, s);
 }
 
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
