@@ -37,6 +37,7 @@ struct mfm_ctx {
     int *counts = nullptr, *gcount = nullptr, *list = nullptr;
     int* fb_list = nullptr;               // particles handed to the per-particle kernel-length solve
     unsigned long long* fb_count = nullptr;
+    int* tails = nullptr;                 // per-particle tail buffers of the flux lists (kTailBuf slots)
     int* fb2_list = nullptr;              // particles the list solver hands to the rescanning one
     unsigned long long* fb2_count = nullptr;
     void* rec = nullptr;                  // 32 x 8 B per particle
@@ -194,7 +195,7 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -249,6 +250,7 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->fb_list, sizeof(int) * n, "fallback list");
     alloc((void**)&c->fb_count, sizeof(unsigned long long), "fallback count");
     alloc((void**)&c->fb2_list, sizeof(int) * n, "second fallback list");
+    alloc((void**)&c->tails, sizeof(int) * (size_t)kTailBuf * n, "tail buffers");
     alloc((void**)&c->fb2_count, sizeof(unsigned long long), "second fallback count");
     alloc((void**)&c->rec, sizeof(double) * 32 * n, "records");
     alloc((void**)&c->prim, sizeof(double4) * 4 * n, "neighbour records");
@@ -374,7 +376,7 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
     const auto ev = clock_take(c, MFM_KERNEL_GRADIENTS);
-    launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->rec_mixed, c->prim, c->rec, c->cnt, ev.first,
+    launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->tails, c->rec_mixed, c->prim, c->rec, c->cnt, ev.first,
                      ev.second, s);
     c->have_grad = 1;
     c->last = s;

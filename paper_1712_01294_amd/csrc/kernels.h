@@ -50,8 +50,11 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
                     const double4* pos, const Phys& ph, Counters* cnt, double* rl, int* list, int* gcount,
                     int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
                     unsigned long long* fb2_count, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
-void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
-                      double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s);
+// flux-list tail entries per particle held in its contiguous tail buffer
+constexpr int kTailBuf = 32;
+void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int* tails,
+                      int mixed, double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1,
+                      hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
                    int mixed, const void* rec, Counters* cnt, hipStream_t s);
 

@@ -711,7 +711,8 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
 // gather list anyway, appends each such j to i's list (atomic slot); then each
 // list sorts its appended tail by index so the list, and every sum over it, is
 // deterministic.
-constexpr int kTailNet = 32;   // tails up to this length are sorted in registers
+constexpr int kTailNet = kTailBuf;   // tails up to this length are buffered and sorted in registers
+static_assert(kTailNet % 4 == 0, "tail buffers are read as int4");
 
 // bitonic sorting network on N registers (indices fixed at compile time)
 template <int N>
@@ -732,18 +733,6 @@ __device__ __forceinline__ void bitonic_net(int* v) {
             }
 }
 
-// sort the first t entries of the calling thread's LDS column
-template <int N>
-__device__ __forceinline__ void sort_column(int (*col)[256], int t) {
-    int v[N];
-#pragma unroll
-    for (int k = 0; k < N; k++) v[k] = k < t ? col[k][threadIdx.x] : INT_MAX;
-    bitonic_net<N>(v);
-#pragma unroll
-    for (int k = 0; k < N; k++)
-        if (k < t) col[k][threadIdx.x] = v[k];
-}
-
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
@@ -756,16 +745,17 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 // The tail of particle i (entries gcount[i] .. counts[i]-1 of its flux list,
-// appended by other particles in no fixed order) is sorted by index, so every
-// later sum over the list runs in one order.  The list is interleaved
-// (list[k * n + i]) and tails start at different rows, so a wave walks the rows
-// its short tails span once, each access one coalesced row segment of the
-// wave's columns, into each lane's own LDS column; there a network sized to
-// the wave's longest tail sorts in registers.  Longer tails are ranked by the
-// whole wave in LDS.
+// appended by other particles in no fixed order: the first kTailNet in i's
+// contiguous tail buffer, the rest in the list) is sorted by index into the
+// list, so every later sum over the list runs in one order.  A short tail is
+// read from the buffer with vector loads, sorted in registers by a network
+// sized to the wave's longest tail, and written through per-lane LDS columns
+// a row at a time (the list is interleaved, list[k * n + i], and tails start
+// at different rows), each store one coalesced row segment of the wave's
+// columns.  Longer tails are ranked by the whole wave in LDS.
 __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* __restrict__ gcount,
                                                      int* __restrict__ counts, int* __restrict__ list,
-                                                     Counters* cnt) {
+                                                     const int* __restrict__ tails, Counters* cnt) {
     cnt = counter_copy(cnt);
     __shared__ int col[kTailNet][256];
     const int i = xcd_block() * 256 + threadIdx.x;
@@ -784,17 +774,31 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
         }
         t = e - g;
     }
-    const bool net = t > 1 && t <= kTailNet;
-    const int rlo = wave_min_i(net ? g : INT_MAX);
-    const int rhi = wave_max_i(net ? g + t : INT_MIN);
+    const bool net = t > 0 && t <= kTailNet;
     const int tmax = wave_max_i(net ? t : 0);
-    if (rlo < rhi) {
-        for (int r = rlo; r < rhi; r++)
-            if (net && r >= g && r < g + t) col[r - g][threadIdx.x] = list[(long long)r * n + i];
-        const int tn = net ? t : 0;
-        if (tmax <= 8) sort_column<8>(col, tn);
-        else if (tmax <= 16) sort_column<16>(col, tn);
-        else sort_column<kTailNet>(col, tn);
+    if (tmax > 0) {
+        int v[kTailNet];
+        if (net) {
+            const int4* tb = (const int4*)(tails + (long long)i * kTailNet);
+#pragma unroll
+            for (int q = 0; q < kTailNet / 4; q++) {
+                const int4 x = tb[q];
+                v[4 * q] = x.x;
+                v[4 * q + 1] = x.y;
+                v[4 * q + 2] = x.z;
+                v[4 * q + 3] = x.w;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTailNet; k++) v[k] = net && k < t ? v[k] : INT_MAX;
+        if (tmax <= 8) bitonic_net<8>(v);
+        else if (tmax <= 16) bitonic_net<16>(v);
+        else bitonic_net<kTailNet>(v);
+#pragma unroll
+        for (int k = 0; k < kTailNet; k++)
+            if (k < t && net) col[k][threadIdx.x] = v[k];
+        const int rlo = wave_min_i(net ? g : INT_MAX);
+        const int rhi = wave_max_i(net ? g + t : INT_MIN);
         for (int r = rlo; r < rhi; r++)
             if (net && r >= g && r < g + t) list[(long long)r * n + i] = col[r - g][threadIdx.x];
     }
@@ -809,7 +813,8 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
         const int src = __ffsll((long long)lm) - 1;
         lm &= lm - 1;
         const int gs = __shfl(g, src, kWave), ts = __shfl(t, src, kWave), is = __shfl(i, src, kWave);
-        for (int k = lane; k < ts; k += kWave) wb[k] = list[(long long)(gs + k) * n + is];
+        for (int k = lane; k < ts; k += kWave)
+            wb[k] = k < kTailNet ? tails[(long long)is * kTailNet + k] : list[(long long)(gs + k) * n + is];
         wave_lds_sync();
         for (int k = lane; k < ts; k += kWave) {
             const int v = wb[k];
@@ -823,6 +828,8 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
         wave_lds_sync();   // the next tail overwrites the region
     }
     if (t > kTailNet * kWave) {
+        // beyond what the wave's LDS region holds: move the buffer in, then sort in place
+        for (int k = 0; k < kTailNet; k++) list[(long long)(g + k) * n + i] = tails[(long long)i * kTailNet + k];
         for (int k = g + 1; k < g + t; k++) {
             const int v = list[(long long)k * n + i];
             int q = k - 1;
@@ -850,14 +857,14 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
 // What the gradient kernel reads of a neighbour, packed into one 128-byte line
-// per particle: (x, y, z, H), (rho, vx, vy, vz), (P, -, -, -), unused.
-__global__ void k_pack_prim(PassArrays a, Phys ph, double4* __restrict__ prim) {
+// per particle: (x, y, z, H), (rho, vx, vy, vz), (P, gather count, -, -), unused.
+__global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcount, double4* __restrict__ prim) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const double rho = a.m[i] * a.nk[i];
     prim[4 * (long long)i + 0] = make_double4(a.x[i], a.y[i], a.z[i], a.H[i]);
     prim[4 * (long long)i + 1] = make_double4(rho, a.vx[i], a.vy[i], a.vz[i]);
-    prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], 0.0, 0.0, 0.0);
+    prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], (double)gcount[i], 0.0, 0.0);
 }
 
 // Four waves per SIMD (128 VGPRs, no spills): the kernel waits on the gathers
@@ -868,7 +875,7 @@ __global__ void k_pack_prim(PassArrays a, Phys ph, double4* __restrict__ prim) {
 #endif
 template <bool MIXED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WAVES))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
-                                                    int* __restrict__ counts, int* __restrict__ list,
+                                                    int* __restrict__ counts, int* __restrict__ list, int* __restrict__ tails,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
                                                     Counters* cnt) {
     cnt = counter_copy(cnt);
@@ -898,15 +905,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
             const int j = list[(long long)k * n + i];
             const double4 pj = prim[4 * (long long)j + 0];
             const double4 qj = prim[4 * (long long)j + 1];
-            const double Pj = prim[4 * (long long)j + 2].x;
+            const double2 pg = *(const double2*)&prim[4 * (long long)j + 2];
+            const double Pj = pg.x;
             double d[3];
             displacement(ph, xi, pj.x, pj.y, pj.z, d);
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             if (!(r < pj.w)) {
                 // i is outside j's gather set: the pair enters j's flux list as a
-                // tail entry (slots past the gather part, sorted afterwards)
+                // tail entry (slots past the gather part, sorted afterwards); the
+                // first kTailNet go to j's contiguous tail buffer, so the appends to
+                // one particle share a cache line, the rest to the list itself
                 const int slot = atomicAdd(&counts[j], 1);
-                if (slot < cap) list[(long long)slot * n + j] = i;
+                const int st = slot - (int)pg.y;
+                if (st < kTailNet) tails[(long long)j * kTailNet + st] = i;
+                else if (slot < cap) list[(long long)slot * n + j] = i;
             }
             const double phi_j[5] = {qj.x, qj.y, qj.z, qj.w, Pj};
             if (!MIXED) {
@@ -1300,16 +1312,17 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
     if (t1) hipEventRecord(t1, s);
 }
 
-void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int mixed,
-                      double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
-    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, prim);
+void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int* tails,
+                      int mixed, double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1,
+                      hipStream_t s) {
+    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, prim);
     if (t0) hipEventRecord(t0, s);
     if (mixed)
-        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, prim, rec, cnt);
+        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt);
     else
-        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, prim, rec, cnt);
+        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt);
     if (t1) hipEventRecord(t1, s);
-    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, cnt);
+    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
 
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
