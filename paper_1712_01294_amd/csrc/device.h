@@ -203,9 +203,10 @@ __device__ __forceinline__ unsigned long long batch_mask(const ScanLds& S, int n
 
 // Cell enumeration and staging shared by the cooperative scans: the cells of
 // one table level within Rq of the box [bmin, bmax] (the finest level whose
-// cells are at least kScanScale Rq wide) are taken 64 at a time, one per lane
-// (key, table entry, periodic image), and their particles are handed out 64 at
-// a time, one per lane, with coalesced loads: chunk(q, valid, nb, wrap) runs on
+// cells are at least scale Rq wide, kScanScale by default) are taken 64 at a
+// time, one per lane (key, table entry, periodic image), and their particles
+// are handed out 64 at a time, one per lane, with coalesced loads: chunk(q,
+// valid, nb, wrap) runs on
 // every lane for each such chunk, q being the lane's particle moved to the
 // periodic image next to the box (index bits in q.w), valid whether the lane
 // holds one, nb how many lanes do.  `wrap` has bit d set when the scan spans
@@ -215,9 +216,10 @@ __device__ __forceinline__ unsigned long long batch_mask(const ScanLds& S, int n
 template <typename Chunk>
 __device__ __forceinline__ void scan_cells(const TreeDesc& td, const int2* __restrict__ tab,
                                            const double4* __restrict__ pos, ScanLds& S, int lane,
-                                           const double bmin[3], const double bmax[3], double Rq, Chunk&& chunk) {
+                                           const double bmin[3], const double bmax[3], double Rq, Chunk&& chunk,
+                                           double scale = kScanScale) {
     int L = td.bmax;
-    while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < kScanScale * Rq) L--;
+    while (L > 0 && fmin(td.cs[L][0], fmin(td.cs[L][1], td.cs[L][2])) < scale * Rq) L--;
     L = __builtin_amdgcn_readfirstlane(L);
     int a[3], cnt[3], nc[3];
     int wrap = 0;

@@ -414,6 +414,11 @@ constexpr int kWaveScans = 16;
 #define MFM_WAVE_BLOCKS 16384
 #endif
 constexpr int kWaveBlocks = MFM_WAVE_BLOCKS;   // waves of the list solver, striding over its particles
+// a single sphere's scan enumerates its cells at a coarser level than a group's
+#ifndef MFM_WAVE_SCAN_SCALE
+#define MFM_WAVE_SCAN_SCALE 0.5
+#endif
+constexpr double kWaveScanScale = MFM_WAVE_SCAN_SCALE;
 
 __global__ __launch_bounds__(64) void k_solve_h_wave(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                       const double4* __restrict__ pos, Phys ph, Counters* cnt,
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(64) void k_solve_h_wave(PassArrays a, TreeDesc td, 
                     jc = sl == 2 ? jv : jc;
                 }
                 m += cin;
-            });
+            }, kWaveScanScale);
             sw = uniform_d(wave_sum_d(sw));
             const double neff = c32 * sw;
             if (m > kKeep) {
