@@ -114,6 +114,7 @@ typedef struct {
     int64_t h_fallback;      /* particles solved one wave each after the group scan */
     int64_t h_rounds3;       /* particles whose solve needed three or more scans    */
     int64_t gather_entries;  /* gather-set entries of the last solve_h, self excluded */
+    int64_t h_rescan;        /* particles the rescanning kernel-length solver took   */
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:

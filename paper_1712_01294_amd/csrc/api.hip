@@ -518,8 +518,9 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
         h.h_fallback += o.h_fallback;
         h.h_rounds3 += o.h_rounds3;
         h.gather_entries += o.gather_entries;
+        h.h_rescan += o.h_rescan;
     }
-    static_assert(sizeof(Counters) == 18 * 8, "combine every counter field");
+    static_assert(sizeof(Counters) == 19 * 8, "combine every counter field");
     out->list_entries = (int64_t)h.list_entries;
     out->pairs = (int64_t)(h.list_entries / 2);
     out->list_max = (int64_t)h.list_max;
@@ -541,6 +542,7 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     out->h_fallback = (int64_t)h.h_fallback;
     out->h_rounds3 = (int64_t)h.h_rounds3;
     out->gather_entries = (int64_t)h.gather_entries;
+    out->h_rescan = (int64_t)h.h_rescan;
     return MFM_OK;
 }
 

@@ -63,6 +63,7 @@ struct Counters {
     unsigned long long h_fallback;   // particles solved by the per-particle kernel
     unsigned long long h_rounds3;    // particles that needed three or more scans
     unsigned long long gather_entries;  // sum of the gather-list lengths
+    unsigned long long h_rescan;     // particles the rescanning kernel-length solver took
 };
 constexpr int kCounterCopies = 32;
 constexpr int kCounterStride = 256;

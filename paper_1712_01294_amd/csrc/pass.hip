@@ -608,6 +608,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
     __shared__ ScanLds S;
     const int lane = threadIdx.x;
     const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
+    if (blockIdx.x == 0 && lane == 0) cnt->h_rescan = *fb_count;
     const long long n = a.n;
     const double c32 = 32.0 / 3.0;
     double half = INFINITY;

@@ -52,7 +52,7 @@ class Counters(C.Structure):
                                          "noconv", "minimage", "overflow", "illcond", "fallbacks",
                                          "clamps", "nonfinite", "floors", "first_bad")] + \
                [("cond_max_seen", C.c_double), ("h_rounds_max", C.c_int64), ("h_fallback", C.c_int64),
-                ("h_rounds3", C.c_int64), ("gather_entries", C.c_int64)]
+                ("h_rounds3", C.c_int64), ("gather_entries", C.c_int64), ("h_rescan", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -118,6 +118,32 @@ def test_lattices_ragged_and_perfect(n_side, jitter):
         assert ctx.counters()["pairs"] == 13 * w.n
 
 
+@pytest.mark.parametrize("n_ngb,path", [(150.0, "list"), (200.0, "rescan")])
+def test_high_neighbour_number_every_solve_path(n_ngb, path):
+    """16^3 jittered lattice at n_ngb = 150 and 200.  The group scan keeps at
+    most 160 radii per particle, so every particle goes on to the per-particle
+    list solver, which keeps up to 192; at 200 those overflow too and the
+    rescanning solver takes them.  Both against the oracle at the FP64 bar."""
+    import dataclasses
+    w = dataclasses.replace(W.jittered_sine(n_side=16, seed=W.SEED_BASE + 77), n_ngb=n_ngb)
+    ref = O.hydro_pass(O.Setup.of(w), w.arrays())
+    ctx, st = run_pass(w, max_ngb=512)
+    ctx.check()
+    c = ctx.counters()
+    print(f"n_ngb {n_ngb}: handed to the list solver {c['h_fallback']}, rescanned {c['h_rescan']}", flush=True)
+    assert c["h_fallback"] > w.n // 2
+    if path == "list":
+        assert c["h_rescan"] < c["h_fallback"] // 2
+    else:
+        assert c["h_rescan"] > w.n // 2
+    errs = compare_pass(st, ref)
+    _print(f"nngb{int(n_ngb)}", errs)
+    for k, e in errs.items():
+        assert e <= TOL_FP64, (k, e)
+    assert elem_rel(in_input_order(st, "H"), ref["H"]) <= TOL_FP64
+    assert c["pairs"] == ref["pairs"]
+
+
 def test_open_box_random_set():
     rng = np.random.default_rng(21)
     n = 3000
