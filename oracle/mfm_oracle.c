@@ -24,6 +24,9 @@
  *   R13 face frame moving with the mean particle velocity
  *   R14 HLLC star state with Davis wave speeds, R15 zero-mass-flux MFM flux
  *   R16 antisymmetric accumulation, each unordered pair in canonical order
+ *   MFV (the paper's other mesh-free finite-volume form, "various mesh-free
+ *   finite-volume Godunov methods"): faces move with the frame of R13 and the
+ *   full HLLC flux of mass, momentum and energy crosses them
  *
  * Everything is written as plain loops over an explicit neighbour search
  * (brute force, or a uniform bucket grid that the tests pin against brute
@@ -49,6 +52,7 @@ typedef struct {
     double beta;      /* limiter constant (R10) */
     double cond_max;  /* flag threshold on ||E||_F ||B||_F (R7) */
     double cell;      /* bucket grid cell size; <= 0 selects brute force */
+    int32_t scheme;   /* 0: meshless finite mass (R15), 1: meshless finite volume */
 } or_params;
 
 /* ------------------------------------------------------------------ */
@@ -488,10 +492,58 @@ static void load_side(side_t *s, int64_t i, int64_t n, const double *H, const do
         for (int a = 0; a < 3; a++) s->g[f][a] = grad[(3 * f + a) * n + i];
 }
 
-typedef struct { double Fp[3], FE, Pstar, Sstar; int fallback, clamp, skipped; } pairflux_t;
+typedef struct { double Fm, Fp[3], FE, Pstar, Sstar; int fallback, clamp, skipped; } pairflux_t;
+
+/*
+ * MFV: the HLLC flux through a face moving with w (R13), per unit area, in the
+ * face frame, then back in the lab frame.  With primes for face-frame
+ * velocities, U = (rho, rho v', E) with E = P/(gamma-1) + rho |v'|^2 / 2 and
+ * physical flux F = (rho u, rho v' u + P n, (E + P) u), u = v'.n.  The star
+ * state of side K keeps the tangential velocity and takes the normal speed S*:
+ *   U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, v'_K + (S* - u_K) n,
+ *          E_K/rho_K + (S* - u_K)(S* + P_K/(rho_K (S_K - u_K)))),
+ * and the flux is F_L (0 <= S_L), F_L + S_L (U*_L - U_L) (S_L < 0 <= S*),
+ * F_R + S_R (U*_R - U_R) (S* < 0 <= S_R), F_R (S_R < 0).  In the lab frame the
+ * mass flux is unchanged, the momentum flux gains w times it and the energy
+ * flux gains w.F_mom' + |w|^2/2 times the mass flux.
+ */
+static void mfv_face_flux(const double qL[5], const double qR[5], const double w[3],
+                          const double nh[3], double uL, double uR, double SL, double SR,
+                          double Ss, double gamma, double F[5])
+{
+    const double *q[2] = {qL, qR};
+    double Us[2][5], U[2][5], Fk[2][5];
+    double u[2] = {uL, uR}, S[2] = {SL, SR};
+    for (int k = 0; k < 2; k++) {
+        double rho = q[k][0], P = q[k][4];
+        double v[3] = {q[k][1] - w[0], q[k][2] - w[1], q[k][3] - w[2]};
+        double E = P / (gamma - 1.0) + 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        U[k][0] = rho;
+        for (int c = 0; c < 3; c++) U[k][1 + c] = rho * v[c];
+        U[k][4] = E;
+        Fk[k][0] = rho * u[k];
+        for (int c = 0; c < 3; c++) Fk[k][1 + c] = rho * v[c] * u[k] + P * nh[c];
+        Fk[k][4] = (E + P) * u[k];
+        double fac = rho * (S[k] - u[k]) / (S[k] - Ss);
+        Us[k][0] = fac;
+        for (int c = 0; c < 3; c++) Us[k][1 + c] = fac * (v[c] + (Ss - u[k]) * nh[c]);
+        Us[k][4] = fac * (E / rho + (Ss - u[k]) * (Ss + P / (rho * (S[k] - u[k]))));
+    }
+    double Ff[5];
+    for (int e = 0; e < 5; e++) {
+        if (SL >= 0.0) Ff[e] = Fk[0][e];
+        else if (Ss >= 0.0) Ff[e] = Fk[0][e] + SL * (Us[0][e] - U[0][e]);
+        else if (SR >= 0.0) Ff[e] = Fk[1][e] + SR * (Us[1][e] - U[1][e]);
+        else Ff[e] = Fk[1][e];
+    }
+    double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    F[0] = Ff[0];
+    for (int c = 0; c < 3; c++) F[1 + c] = Ff[1 + c] + w[c] * Ff[0];
+    F[4] = Ff[4] + w[0] * Ff[1] + w[1] * Ff[2] + w[2] * Ff[3] + 0.5 * ww * Ff[0];
+}
 
 static void pair_flux(const side_t *a, const side_t *b, const double d[3], double r,
-                      double gamma, pairflux_t *out)
+                      double gamma, int mfv, pairflux_t *out)
 {
     memset(out, 0, sizeof(*out));
     double Wa = or_kernel_W(r, a->H), Wb = or_kernel_W(r, b->H);
@@ -530,6 +582,16 @@ static void pair_flux(const side_t *a, const side_t *b, const double d[3], doubl
     double mL = rL * (SL - uL), mR = rR * (SR - uR);
     double Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
     double Ps = 0.5 * (pL + pR + mL * (Ss - uL) + mR * (Ss - uR));
+    if (mfv) {
+        double F[5];
+        mfv_face_flux(qL, qR, w, nh, uL, uR, SL, SR, Ss, gamma, F);
+        out->Fm = F[0] * Amag;
+        for (int c = 0; c < 3; c++) out->Fp[c] = F[1 + c] * Amag;
+        out->FE = F[4] * Amag;
+        out->Pstar = Ps;
+        out->Sstar = Ss;
+        return;
+    }
     if (Ps < 0.0) { Ps = 0.0; out->clamp = 1; }
 
     /* R15: zero mass flux; momentum P* A, energy P* (S* + w.n)|A| */
@@ -557,9 +619,32 @@ void or_hllc_star(double gamma, double rL, double uL, double pL, double rR, doub
     double w = 0.5 * (uL + uR);
     double d[3] = {1.0, 0.0, 0.0};
     pairflux_t o;
-    pair_flux(&a, &b, d, 1.0, gamma, &o);
+    pair_flux(&a, &b, d, 1.0, gamma, 0, &o);
     *Sstar = o.Sstar + w;
     *Pstar = o.Pstar;
+}
+
+/* Exported for the tests: the MFV flux (mass, momentum, energy per unit face
+ * area, lab frame) between two 1D states along +x, face velocity (uL + uR)/2. */
+void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, double uR, double pR,
+                 double F[3])
+{
+    side_t a, b;
+    memset(&a, 0, sizeof(a));
+    memset(&b, 0, sizeof(b));
+    /* identity B and V, equal H: A = W(1, 2) (1, 0, 0); the flux is divided by |A| */
+    a.H = b.H = 2.0;
+    a.V = b.V = 1.0;
+    for (int c = 0; c < 3; c++) a.B[c][c] = b.B[c][c] = 1.0;
+    a.phi[0] = rL; a.phi[1] = uL; a.phi[4] = pL;
+    b.phi[0] = rR; b.phi[1] = uR; b.phi[4] = pR;
+    double d[3] = {1.0, 0.0, 0.0};
+    pairflux_t o;
+    pair_flux(&a, &b, d, 1.0, gamma, 1, &o);
+    double Amag = 2.0 * or_kernel_W(1.0, 2.0);
+    F[0] = o.Fm / Amag;
+    F[1] = o.Fp[0] / Amag;
+    F[2] = o.FE / Amag;
 }
 
 /*
@@ -568,13 +653,14 @@ void or_hllc_star(double gamma, double rL, double uL, double pL, double rR, doub
  * index as the left state and s = +1 if i is that state, -1 otherwise.
  * vsig_i = max_j [c_i + c_j - min(0, (v_i - v_j).(x_i - x_j)/r_ij)] (R18).
  * hmax must bound H over all particles.  Counts: pair entries (directed),
- * first-order fallbacks and P* clamps (directed).
+ * first-order fallbacks and P* clamps (directed).  With scheme 1 (MFV) the
+ * pair flux is the full HLLC one and dm (nullable) receives -s F_m summed.
  */
 int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
               const double *z, const double *vx, const double *vy, const double *vz,
               const double *H, const double *V, const double *B, const double *rho,
               const double *P, const double *grad, const uint8_t *mask, double hmax,
-              double *dp, double *dE, double *vsig, int64_t *counts)
+              double *dp, double *dE, double *vsig, int64_t *counts, double *dm)
 {
     grid_t g;
     nbr_list L = {0};
@@ -585,7 +671,7 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
         double R = H[i] > hmax ? H[i] : hmax;
         rc = grid_find(&g, i, R, &L);
         if (rc) break;
-        double acc[4] = {0, 0, 0, 0};
+        double acc[4] = {0, 0, 0, 0}, accm = 0.0;
         double ci = sqrt(p->gamma * P[i] / rho[i]);
         double vs = 0.0;
         side_t si, sj;
@@ -600,17 +686,18 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
             pairflux_t o;
             double s;
             if (i < j) {
-                pair_flux(&si, &sj, L.a[k].d, r, p->gamma, &o);
+                pair_flux(&si, &sj, L.a[k].d, r, p->gamma, p->scheme == 1, &o);
                 s = 1.0;
             } else {
                 double dn[3] = {-L.a[k].d[0], -L.a[k].d[1], -L.a[k].d[2]};
-                pair_flux(&sj, &si, dn, r, p->gamma, &o);
+                pair_flux(&sj, &si, dn, r, p->gamma, p->scheme == 1, &o);
                 s = -1.0;
             }
             nfall += o.fallback;
             nclamp += o.clamp;
             for (int c = 0; c < 3; c++) acc[c] -= s * o.Fp[c];
             acc[3] -= s * o.FE;
+            accm -= s * o.Fm;
             double cj = sqrt(p->gamma * P[j] / rho[j]);
             const double *d = L.a[k].d; /* x_j - x_i */
             double proj = ((vx[i] - vx[j]) * (-d[0]) + (vy[i] - vy[j]) * (-d[1]) +
@@ -623,6 +710,7 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
         dp[2 * n + i] = acc[2];
         dE[i] = acc[3];
         vsig[i] = vs;
+        if (dm) dm[i] = accm;
     }
     if (counts) {
         counts[0] = npair;

@@ -32,7 +32,7 @@ _u8p = C.POINTER(C.c_uint8)
 class OrParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("n_ngb", C.c_double), ("box", C.c_double * 3),
                 ("periodic", C.c_int32 * 3), ("beta", C.c_double), ("cond_max", C.c_double),
-                ("cell", C.c_double)]
+                ("cell", C.c_double), ("scheme", C.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -64,6 +64,7 @@ def lib():
         L.or_fluxes.restype = C.c_int
         L.or_hllc_star.restype = None
         L.or_face.restype = None
+        L.or_mfv_flux.restype = None
         _lib = L
     return _lib
 
@@ -98,6 +99,7 @@ class Setup:
     beta: float = 1.0
     cond_max: float = 1.0e6
     cell: float = 0.0       # 0: brute-force neighbour search
+    scheme: str = "mfm"     # "mfm" (zero mass flux) or "mfv" (full HLLC flux, mass changes)
 
     @classmethod
     def of(cls, w, cell=None, **kw):
@@ -118,6 +120,7 @@ class Setup:
         p.beta = self.beta
         p.cond_max = self.cond_max
         p.cell = self.cell
+        p.scheme = {"mfm": 0, "mfv": 1}[self.scheme]
         return p
 
 
@@ -186,6 +189,7 @@ def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None):
     rho, P = _f64(g["rho"]), _f64(g["P"])
     dp = np.zeros(3 * n)
     dE = np.zeros(n)
+    dm = np.zeros(n)
     vsig = np.zeros(n)
     counts = np.zeros(3, dtype=np.int64)
     mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
@@ -195,8 +199,8 @@ def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None):
     _check(lib().or_fluxes(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
                            _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
                            _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
-                           _p(dE), _p(vsig), _p(counts)), "fluxes")
-    return dict(dp=dp.reshape(3, n), dE=dE, vsig=vsig, pair_entries=int(counts[0]),
+                           _p(dE), _p(vsig), _p(counts), _p(dm)), "fluxes")
+    return dict(dp=dp.reshape(3, n), dE=dE, dm=dm, vsig=vsig, pair_entries=int(counts[0]),
                 fallbacks=int(counts[1]), clamps=int(counts[2]))
 
 
@@ -219,6 +223,16 @@ def hllc_star(gamma, left, right):
                        C.c_double(left[2]), C.c_double(right[0]), C.c_double(right[1]),
                        C.c_double(right[2]), C.byref(Ss), C.byref(Ps))
     return Ss.value, Ps.value
+
+
+def mfv_flux(gamma, left, right):
+    """MFV flux (mass, momentum, energy per unit area, lab frame) between 1D
+    states (rho, u, P) along +x through a face moving with (u_L + u_R)/2."""
+    F = np.zeros(3)
+    lib().or_mfv_flux(C.c_double(gamma), C.c_double(left[0]), C.c_double(left[1]),
+                      C.c_double(left[2]), C.c_double(right[0]), C.c_double(right[1]),
+                      C.c_double(right[2]), _p(F))
+    return F
 
 
 def face(Ha, Va, Ba6, Hb, Vb, Bb6, d):

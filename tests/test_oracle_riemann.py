@@ -115,3 +115,86 @@ def test_tube_tracks_exact_solution(small_tube):
     cross = xs[np.flatnonzero(rho_s < mid)[0]]
     dx = 2 * w.extra["spacing_right"]
     assert abs(cross - (1.0 + S * t)) < dx
+
+
+# ---------------------------------------------------------------- MFV flux
+# The meshless finite-volume form: the full HLLC flux through a face moving
+# with the mean particle velocity.  Pins: isolated contacts (HLLC resolves them
+# exactly), Galilean covariance of the lab-frame flux, agreement with the MFM
+# flux when the contact sits on the face, and the exact Godunov flux for weak
+# waves.
+def _godunov_flux_through_moving_face(left, right, gamma):
+    """Exact solution sampled on the face (speed w = (u_L + u_R)/2), flux per area."""
+    w = 0.5 * (left[1] + right[1])
+    rho, u, p = (float(np.asarray(v).ravel()[0]) for v in R.sample(left, right, gamma, np.array([w])))
+    E = p / (gamma - 1.0) + 0.5 * rho * u * u
+    return np.array([rho * (u - w), rho * u * (u - w) + p, E * (u - w) + p * u])
+
+
+@pytest.mark.parametrize("rl,rr,u0,p", [(1.0, 0.125, 0.0, 1.0), (0.3, 2.0, 0.7, 0.4), (5.0, 1.0, -1.3, 2.5)])
+def test_mfv_flux_isolated_contact(rl, rr, u0, p):
+    """A contact moving with the face carries no mass; the face feels p and does work p u0."""
+    F = O.mfv_flux(5.0 / 3.0, (rl, u0, p), (rr, u0, p))
+    assert abs(F[0]) <= 1e-15 * rl * (abs(u0) + 1)
+    assert F[1] == pytest.approx(p, rel=1e-14)
+    assert F[2] == pytest.approx(p * u0, rel=1e-14, abs=1e-15)
+
+
+def test_mfv_flux_galilean_covariance():
+    """Shifting every velocity (and so the face) by V leaves the mass flux and
+    adds V F_m to the momentum flux and V F_mom + V^2/2 F_m to the energy flux."""
+    rng = np.random.default_rng(5)
+    g = 5.0 / 3.0
+    for _ in range(50):
+        L = (rng.uniform(0.2, 3), rng.normal(0, 1), rng.uniform(0.2, 3))
+        Rt = (rng.uniform(0.2, 3), rng.normal(0, 1), rng.uniform(0.2, 3))
+        V = rng.normal(0, 2)
+        F0 = O.mfv_flux(g, L, Rt)
+        F1 = O.mfv_flux(g, (L[0], L[1] + V, L[2]), (Rt[0], Rt[1] + V, Rt[2]))
+        scale = np.abs(F0).max() + abs(V) * (np.abs(F0).max() + abs(V) * abs(F0[0]))
+        assert abs(F1[0] - F0[0]) <= 1e-12 * scale
+        assert abs(F1[1] - (F0[1] + V * F0[0])) <= 1e-12 * scale
+        assert abs(F1[2] - (F0[2] + V * F0[1] + 0.5 * V * V * F0[0])) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("rho,u,p", [(1.0, 0.3, 1.0), (0.5, -0.8, 2.0), (2.0, 1.5, 0.3)])
+def test_mfv_equals_mfm_when_the_contact_sits_on_the_face(rho, u, p):
+    """Mirror-symmetric states (u_L = -u_R): S* = 0 in the face frame, so the
+    full HLLC flux has no mass or energy part and its momentum part is the MFM
+    star pressure."""
+    g = 1.4
+    F = O.mfv_flux(g, (rho, u, p), (rho, -u, p))
+    _, Ps = O.hllc_star(g, (rho, u, p), (rho, -u, p))
+    assert abs(F[0]) <= 1e-14 * rho * abs(u)
+    assert F[1] == pytest.approx(Ps, rel=1e-13)
+    assert abs(F[2]) <= 1e-13 * Ps * abs(u) + 1e-16
+
+
+@pytest.mark.parametrize("L,Rt", [((1.0, 0.2, 1.0), (0.9, 0.1, 0.85)), ((1.0, 0.0, 1.0), (0.95, 0.05, 0.9)),
+                                  ((0.8, -0.1, 0.7), (0.85, -0.12, 0.75))])
+def test_mfv_flux_near_exact_godunov_for_weak_waves(L, Rt):
+    """HLLC is approximate for acoustic waves; for jumps of ~10% it stays within
+    1% of the exact Godunov flux through the moving face."""
+    g = 5.0 / 3.0
+    F = O.mfv_flux(g, L, Rt)
+    ex = _godunov_flux_through_moving_face(L, Rt, g)
+    assert np.abs(F - ex).max() <= 1e-2 * np.abs(ex).max()
+
+
+def test_mfv_pass_conserves_mass_momentum_energy():
+    """Whole oracle pass in MFV form: every pair flux is applied with opposite
+    signs, so total mass, momentum and energy rates vanish to round-off."""
+    import dataclasses
+    w = W.jittered_sine(n_side=8, seed=W.SEED_BASE + 91)
+    s = dataclasses.replace(O.Setup.of(w), scheme="mfv")
+    out = O.hydro_pass(s, w.arrays())
+    assert np.abs(out["dm"]).max() > 0
+    eps = np.finfo(np.float64).eps
+    assert abs(out["dm"].sum()) <= 10 * eps * np.abs(out["dm"]).sum()
+    for c in range(3):
+        assert abs(out["dp"][c].sum()) <= 10 * eps * np.abs(out["dp"][c]).sum()
+    assert abs(out["dE"].sum()) <= 10 * eps * np.abs(out["dE"]).sum()
+    # the MFM pass of the same state has no mass flux and the same kernel lengths
+    mfm = O.hydro_pass(O.Setup.of(w), w.arrays())
+    assert np.array_equal(mfm["H"], out["H"])
+    assert np.all(mfm["dm"] == 0.0)
