@@ -24,8 +24,8 @@
  *   R13 face frame moving with the mean particle velocity
  *   R14 HLLC star state with Davis wave speeds, R15 zero-mass-flux MFM flux
  *   R16 antisymmetric accumulation, each unordered pair in canonical order
- *   MFV (the paper's other mesh-free finite-volume form, "various mesh-free
- *   finite-volume Godunov methods"): faces move with the frame of R13 and the
+ *   MFV (the other mesh-free Godunov form that section 2 lists, with the
+ *   moving faces of section 4): faces move with the frame of R13 and the
  *   full HLLC flux of mass, momentum and energy crosses them
  *
  * Everything is written as plain loops over an explicit neighbour search
@@ -625,9 +625,13 @@ void or_hllc_star(double gamma, double rL, double uL, double pL, double rR, doub
 }
 
 /* Exported for the tests: the MFV flux (mass, momentum, energy per unit face
- * area, lab frame) between two 1D states along +x, face velocity (uL + uR)/2. */
-void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, double uR, double pR,
-                 double F[3])
+ * area, lab frame) between two 1D face states (rho, u, P) along +x, when the
+ * particles themselves move with vL and vR, so that the face moves with
+ * (vL + vR)/2.  The face states are made by the reconstruction of R12: each
+ * side's velocity gradient along x is set so that its midpoint value is the
+ * given face velocity (d = 1, so half a unit of gradient per unit offset). */
+void or_mfv_flux_moving(double gamma, double vL, double vR, double rL, double uL, double pL,
+                        double rR, double uR, double pR, double F[3])
 {
     side_t a, b;
     memset(&a, 0, sizeof(a));
@@ -636,8 +640,10 @@ void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, doubl
     a.H = b.H = 2.0;
     a.V = b.V = 1.0;
     for (int c = 0; c < 3; c++) a.B[c][c] = b.B[c][c] = 1.0;
-    a.phi[0] = rL; a.phi[1] = uL; a.phi[4] = pL;
-    b.phi[0] = rR; b.phi[1] = uR; b.phi[4] = pR;
+    a.phi[0] = rL; a.phi[1] = vL; a.phi[4] = pL;
+    b.phi[0] = rR; b.phi[1] = vR; b.phi[4] = pR;
+    a.g[1][0] = 2.0 * (uL - vL);     /* qL = vL + g/2 = uL */
+    b.g[1][0] = 2.0 * (vR - uR);     /* qR = vR - g/2 = uR */
     double d[3] = {1.0, 0.0, 0.0};
     pairflux_t o;
     pair_flux(&a, &b, d, 1.0, gamma, 1, &o);
@@ -645,6 +651,14 @@ void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, doubl
     F[0] = o.Fm / Amag;
     F[1] = o.Fp[0] / Amag;
     F[2] = o.FE / Amag;
+}
+
+/* The same with the particles moving at the face states' own velocities, so
+ * that the face moves with (uL + uR)/2. */
+void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, double uR, double pR,
+                 double F[3])
+{
+    or_mfv_flux_moving(gamma, uL, uR, rL, uL, pL, rR, uR, pR, F);
 }
 
 /*

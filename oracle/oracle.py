@@ -65,6 +65,7 @@ def lib():
         L.or_hllc_star.restype = None
         L.or_face.restype = None
         L.or_mfv_flux.restype = None
+        L.or_mfv_flux_moving.restype = None
         _lib = L
     return _lib
 
@@ -232,6 +233,17 @@ def mfv_flux(gamma, left, right):
     lib().or_mfv_flux(C.c_double(gamma), C.c_double(left[0]), C.c_double(left[1]),
                       C.c_double(left[2]), C.c_double(right[0]), C.c_double(right[1]),
                       C.c_double(right[2]), _p(F))
+    return F
+
+
+def mfv_flux_moving(gamma, v_particles, left, right):
+    """MFV flux between 1D face states (rho, u, P) along +x when the two
+    particles move with v_particles = (vL, vR), so the face moves with their
+    mean; the face states come from the reconstruction."""
+    F = np.zeros(3)
+    lib().or_mfv_flux_moving(C.c_double(gamma), C.c_double(v_particles[0]), C.c_double(v_particles[1]),
+                             C.c_double(left[0]), C.c_double(left[1]), C.c_double(left[2]),
+                             C.c_double(right[0]), C.c_double(right[1]), C.c_double(right[2]), _p(F))
     return F
 
 

@@ -123,9 +123,9 @@ def test_tube_tracks_exact_solution(small_tube):
 # exactly), Galilean covariance of the lab-frame flux, agreement with the MFM
 # flux when the contact sits on the face, and the exact Godunov flux for weak
 # waves.
-def _godunov_flux_through_moving_face(left, right, gamma):
-    """Exact solution sampled on the face (speed w = (u_L + u_R)/2), flux per area."""
-    w = 0.5 * (left[1] + right[1])
+def _godunov_flux_through_moving_face(left, right, gamma, w=None):
+    """Exact solution sampled on the face (speed w, by default (u_L + u_R)/2), flux per area."""
+    w = 0.5 * (left[1] + right[1]) if w is None else w
     rho, u, p = (float(np.asarray(v).ravel()[0]) for v in R.sample(left, right, gamma, np.array([w])))
     E = p / (gamma - 1.0) + 0.5 * rho * u * u
     return np.array([rho * (u - w), rho * u * (u - w) + p, E * (u - w) + p * u])
@@ -198,3 +198,44 @@ def test_mfv_pass_conserves_mass_momentum_energy():
     mfm = O.hydro_pass(O.Setup.of(w), w.arrays())
     assert np.array_equal(mfm["H"], out["H"])
     assert np.all(mfm["dm"] == 0.0)
+
+
+@pytest.mark.parametrize("mach", [3.0, 0.3, -0.3, -3.0])
+def test_mfv_flux_contact_crossing_a_moving_face(mach):
+    """A contact (equal u0 and P, unequal densities) seen from a face that moves
+    with W != u0.  The exact solution at the face is the upwind state, so the
+    flux is that state's flux through the moving face.  The face-frame speed
+    u0 - W = mach * c_max selects each branch in turn: the one-sided F_L
+    (mach 3) and F_R (mach -3), and the star states of the left (0.3) and right
+    (-0.3) side, which for a contact equal the side states."""
+    g = 5.0 / 3.0
+    for rl, rr, p, W in [(1.0, 0.125, 1.0, 0.2), (0.3, 2.0, 0.4, -0.7), (5.0, 1.0, 2.5, 1.3)]:
+        cmax = np.sqrt(g * p / min(rl, rr))
+        u0 = W + mach * cmax
+        F = O.mfv_flux_moving(g, (W, W), (rl, u0, p), (rr, u0, p))
+        up = rl if mach > 0 else rr
+        E = p / (g - 1.0) + 0.5 * up * u0 * u0
+        ex = np.array([up * (u0 - W), up * u0 * (u0 - W) + p, E * (u0 - W) + p * u0])
+        assert np.abs(F - ex).max() <= 1e-13 * np.abs(ex).max(), (F, ex)
+
+
+def test_mfv_flux_continuous_as_the_face_crosses_the_contact():
+    """The lab-frame contact speed S* does not depend on the face speed W.  As
+    W crosses it the selection switches from the right star state to the left
+    one; both star states satisfy the jump condition across the contact, so
+    the flux through the face changes by O(dW) only.  A wrong term in either
+    star state leaves an O(1) jump."""
+    g = 1.4
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        L = (rng.uniform(0.2, 3), rng.normal(0, 1), rng.uniform(0.2, 3))
+        Rt = (rng.uniform(0.2, 3), rng.normal(0, 1), rng.uniform(0.2, 3))
+        Ss, _ = O.hllc_star(g, L, Rt)
+        dW = 1e-7
+        lo = O.mfv_flux_moving(g, (Ss - dW, Ss - dW), L, Rt)
+        hi = O.mfv_flux_moving(g, (Ss + dW, Ss + dW), L, Rt)
+        scale = np.abs(lo).max() + np.abs(hi).max()
+        assert np.abs(hi - lo).max() <= 1e-5 * scale, (L, Rt, lo, hi)
+        # and well away from S* the two selections differ (the check has teeth)
+        far = O.mfv_flux_moving(g, (Ss + 0.5, Ss + 0.5), L, Rt)
+        assert np.abs(far - lo).max() > 1e-3 * scale
