@@ -5,8 +5,9 @@
 
 Metric: unordered particle-pair interactions per second per hydro pass (kernel
 length + gradients + fluxes on particles already in the library's spatial
-order), FP64, with the mixed form and its per-field error beside it, and the
-forward + adjoint time of 10 fixed-dt steps on the 64^3 jittered box.
+order), FP64, with the mixed form and its per-field error beside it, the
+finite-volume (MFV) form of the same pass, and the forward + adjoint time of
+10 fixed-dt steps on the 64^3 jittered box.
 
 Inputs are seeded synthetic particle sets resident in HBM before timing starts.
 Every timed pass starts the kernel-length solve cold (H = 0), so each step
@@ -51,6 +52,9 @@ PEAK_FP32_VALU = 157.3e12  # flop/s, FP32 vector (packed)
 #              weights 20, faces 52, reconstruction 70, frame 22, HLLC 31, flux
 #              6, distance 9, accumulation and signal speed 26), add/mul/div/sqrt
 #              counted as one and fma as two.
+#   fluxes, finite-volume form: dm (8 B) more out; the full HLLC flux of the
+#              selected side (state, physical flux, star correction) and the
+#              lab-frame boost replace the P* flux: about 310 flops per pair.
 def algorithmic(kernel, n, G, F, P):
     if kernel == "solve_h":
         return 64.0 * n + 4.0 * G, 33.0 * G
@@ -58,6 +62,8 @@ def algorithmic(kernel, n, G, F, P):
         return 272.0 * n + 4.0 * F, 75.0 * G + 200.0 * n
     if kernel == "hydro_fluxes":
         return 288.0 * n + 4.0 * F, 236.0 * P
+    if kernel == "hydro_fluxes_mfv":
+        return 296.0 * n + 4.0 * F, 310.0 * P
     raise KeyError(kernel)
 
 
@@ -71,9 +77,10 @@ KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/cs
 # known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
 # only for the kernel sources whose fingerprint is recorded with it.
 TRAFFIC = {
-    ("clustered", "solve_h"): {"bytes_per_launch": 141.93e9, "fingerprint": "9389072a332e9617"},
-    ("clustered", "gradients"): {"bytes_per_launch": 30.44e9, "fingerprint": "9389072a332e9617"},
-    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 30.68e9, "fingerprint": "9389072a332e9617"},
+    ("clustered", "solve_h"): {"bytes_per_launch": 140.75e9, "fingerprint": "fc80fc90130fbf79"},
+    ("clustered", "gradients"): {"bytes_per_launch": 30.43e9, "fingerprint": "fc80fc90130fbf79"},
+    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 30.67e9, "fingerprint": "fc80fc90130fbf79"},
+    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 40.19e9, "fingerprint": "fc80fc90130fbf79"},
 }
 
 
@@ -100,6 +107,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mfv", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
@@ -227,9 +235,9 @@ def adjoint_timing(reps=3):
             "note": "wall clock with the stream synchronised at both ends; forward keeps one checkpoint per step"}
 
 
-def run_precision(mfm, w, prec, kw, args, stream):
-    ctx = mfm.Context(mfm.config_of(w, precision=prec, **kw), w.n)
-    st = mfm.State.from_arrays(w.arrays(), ids=True)
+def run_precision(mfm, w, prec, kw, args, stream, scheme=0):
+    ctx = mfm.Context(mfm.config_of(w, precision=prec, scheme=scheme, **kw), w.n)
+    st = mfm.State.from_arrays(w.arrays(), ids=True, dm=scheme == mfm.SCHEME_MFV)
     ctx.build_neighbours(st)
     ctx.hydro_pass(st)
     ctx.check(allow_illcond=True)
@@ -338,6 +346,31 @@ def main():
         del stmx
     del st64
     torch.cuda.empty_cache()
+
+    if not args.no_mfv:
+        ctx, stv, tv, kv, cv = run_precision(mfm, w, mfm.FP64, kw, args, stream, scheme=mfm.SCHEME_MFV)
+        del ctx
+        v_ms = tv["solve_h"] + tv["gradients"] + tv["fluxes"]
+        fk = kv["hydro_fluxes"]
+        b, f = algorithmic("hydro_fluxes_mfv", n, cv["gather_entries"], cv["list_entries"], cv["pairs"])
+        s = fk["ms_avg"] * 1e-3
+        dm = stv.dm
+        out["mfv"] = {"value": cv["pairs"] / (v_ms * 1e-3), "unit": "pairs/s", "dtype": "f64",
+                      "ms_per_step": v_ms, "stage_ms": tv,
+                      "flux_kernel": {"kernel": "k_fluxes_mfv", "ms_avg": fk["ms_avg"], "launches": fk["launches"],
+                                      "algorithmic_bytes": b, "GBps": b / s / 1e9, "frac_hbm": b / s / PEAK_HBM,
+                                      "algorithmic_flops": f, "GFLOPps": f / s / 1e9,
+                                      "frac_fp64": f / s / PEAK_FP64_VALU},
+                      "mass_rate_sum_rel": float(dm.sum().abs() / dm.abs().sum()),
+                      "flux_kernel_traffic": (TRAFFIC[(w.name, "hydro_fluxes_mfv")]["bytes_per_launch"]
+                                              if (w.name, "hydro_fluxes_mfv") in TRAFFIC
+                                              and TRAFFIC[(w.name, "hydro_fluxes_mfv")]["fingerprint"] == fp
+                                              else None),
+                      "fallbacks": cv["fallbacks"]}
+        log(f"mfv: " + " ".join(f"{k}={v:.3f}ms" for k, v in tv.items())
+            + f" flux kernel {fk['ms_avg']:.3f} ms")
+        del stv
+        torch.cuda.empty_cache()
 
     if not args.no_adjoint:
         log("adjoint ...")

@@ -53,6 +53,14 @@ typedef enum {
 
 typedef enum { MFM_FP64 = 0, MFM_MIXED = 1 } mfm_precision;
 
+/* MFM: faces carry no mass (the Lagrangian form the rest of this header
+ * describes).  MFV (the other mesh-free Godunov form that section 2 lists;
+ * section 4 on meshes that move): the same pass, but the full HLLC flux of
+ * mass, momentum and energy crosses each face, which moves with the mean
+ * particle velocity, so masses change at the rate dm.  MFV runs in MFM_FP64 only, and mfm_step and the adjoints accept
+ * only MFM. */
+typedef enum { MFM_SCHEME_MFM = 0, MFM_SCHEME_MFV = 1 } mfm_scheme;
+
 typedef struct {
     double gamma;          /* adiabatic index, > 1                                     */
     double n_ngb;          /* effective neighbour number, > 32/3                       */
@@ -66,7 +74,7 @@ typedef struct {
     int32_t h_maxit;       /* cap on kernel-length iterations (<= 0: 64)               */
     int32_t max_ngb;       /* flux-list slots per particle (<= 0: 256)                 */
     int32_t tree_levels;   /* cell-table depth (<= 0: from n)                          */
-    int32_t reserved;
+    int32_t scheme;        /* mfm_scheme                                               */
 } mfm_params;
 
 /*
@@ -92,6 +100,7 @@ typedef struct {
     double *dE;              /* total-energy rate dE/dt             [hydro_fluxes]   */
     double *vsig;            /* signal speed                        [hydro_fluxes]   */
     int64_t *id;             /* nullable: carried along every reordering            */
+    double *dm;              /* mass rate dm/dt, MFV only (nullable for MFM) [hydro_fluxes] */
 } mfm_particles;
 
 typedef struct {
@@ -118,7 +127,8 @@ typedef struct {
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:
- * gamma > 1, n_ngb > 32/3, box > 0, beta > 0.  Allocates scratch on the
+ * gamma > 1, n_ngb > 32/3, box > 0, beta > 0, scheme MFM, or MFV with
+ * precision MFM_FP64.  Allocates scratch on the
  * current HIP device.  *out is NULL on failure. */
 mfm_status mfm_create(const mfm_params *params, int64_t capacity, mfm_ctx **out);
 
@@ -129,7 +139,7 @@ void mfm_destroy(mfm_ctx *ctx);
  * r < max(H_i, H_j); the search is the library's own choice).
  * Quantises positions to a per-axis Morton key, sorts particles by key
  * (stable LSD radix sort), REORDERS IN PLACE every non-NULL array among
- * x, y, z, m, vx, vy, vz, u, H, dp, dE, vsig, id into that order, and
+ * x, y, z, m, vx, vy, vz, u, H, dp, dE, vsig, dm, id into that order, and
  * builds the per-level cell tables of the implicit octree.  Other output
  * arrays are left stale and are rewritten by the next pass. */
 mfm_status mfm_build_neighbours(mfm_ctx *ctx, mfm_particles *p, void *stream);
@@ -161,7 +171,11 @@ mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * opposite signs to both particles.  vsig_i = max_j [c_i + c_j
  * - min(0, (v_i - v_j).(x_i - x_j)/r)].  Requires mfm_gradients.
  * MFM_MIXED: displacements from FP64 positions, then kernel weights, faces,
- * reconstruction and HLLC in FP32; the per-particle sums of dp and dE in FP64. */
+ * reconstruction and HLLC in FP32; the per-particle sums of dp and dE in FP64.
+ * MFM_SCHEME_MFV: the same faces, reconstruction, face frame and wave speeds,
+ * then the full HLLC flux (F_L, F_L + S_L (U*_L - U_L), F_R + S_R (U*_R - U_R)
+ * or F_R by the signs of S_L, S*, S_R) in the face frame, taken back to the lab
+ * frame; dm (required) receives the mass rate; no P* clamp applies. */
 mfm_status mfm_hydro_fluxes(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* solve_h + gradients + hydro_fluxes on already-ordered particles. */

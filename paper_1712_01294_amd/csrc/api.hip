@@ -210,6 +210,8 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     for (int d = 0; d < 3; d++)
         if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return MFM_E_INVALID;
     if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return MFM_E_INVALID;
+    if (p.scheme != MFM_SCHEME_MFM && p.scheme != MFM_SCHEME_MFV) return MFM_E_INVALID;
+    if (p.scheme == MFM_SCHEME_MFV && p.precision != MFM_FP64) return MFM_E_INVALID;
     if (capacity < 1 || capacity > (1ll << 30)) return MFM_E_INVALID;
     mfm_ctx* c = new mfm_ctx();
     c->p = p;
@@ -303,6 +305,7 @@ static PassArrays arrays_of(const mfm_particles* p) {
     a.dp = p->dp;
     a.dE = p->dE;
     a.vsig = p->vsig;
+    a.dm = p->dm;
     return a;
 }
 
@@ -338,6 +341,7 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     }
     add(p->dE);
     add(p->vsig);
+    add(p->dm);
     add(p->id);
     for (int k = 0; k < nextra; k++) add(extra[k]);
     launch_gather(n, gb, c->idx, s);
@@ -385,11 +389,13 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
 
 static mfm_status do_fluxes(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!p->dp || !p->dE || !p->vsig) return fail(c, MFM_E_INVALID, "dp, dE and vsig are required");
+    const int mfv = c->p.scheme == MFM_SCHEME_MFV;
+    if (mfv && !p->dm) return fail(c, MFM_E_INVALID, "the finite-volume scheme needs dm");
     if (!c->have_grad || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_gradients must run first");
     PassArrays a = arrays_of(p);
     const auto ev = clock_take(c, MFM_KERNEL_FLUXES);
     if (ev.first) hipEventRecord(ev.first, s);
-    launch_fluxes(a, c->ph, c->counts, c->list, c->rec_mixed, c->rec, c->cnt, s);
+    launch_fluxes(a, c->ph, c->counts, c->list, c->rec_mixed, mfv, c->rec, c->cnt, s);
     if (ev.second) hipEventRecord(ev.second, s);
     c->have_flux = 1;
     c->last = s;
@@ -423,6 +429,7 @@ mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
     if (st) return st;
     hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
+    if (c->p.scheme == MFM_SCHEME_MFV && !p->dm) return fail(c, MFM_E_INVALID, "the finite-volume scheme needs dm");
     reset_counters(c, s);
     if ((st = do_solve_h(c, p, s))) return st;
     if ((st = do_gradients(c, p, s))) return st;
@@ -432,6 +439,7 @@ mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
 mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
+    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "mfm_step integrates the MFM scheme only");
     if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
         return fail(c, MFM_E_INVALID, "mfm_step needs every pass output array");
     if (!c->have_flux || c->n_tree != p->n)
@@ -607,6 +615,7 @@ extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p,
                                              void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
+    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme only");
     if (!adj_dp || !adj_dE || !adj_x || !adj_v || !adj_u) return fail(c, MFM_E_INVALID, "null adjoint array");
     if (!p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
         return fail(c, MFM_E_INVALID, "the pass adjoint needs the forward outputs nk, V, B, rho, P, grad");
@@ -626,6 +635,7 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
                                        void* stream) {
     mfm_status st = check_particles(c, ck);
     if (st) return st;
+    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme only");
     if ((st = check_particles(c, w))) return st;
     if (w->n != ck->n) return fail(c, MFM_E_INVALID, "checkpoint and work sets differ in size");
     if (!(dt > 0.0)) return fail(c, MFM_E_INVALID, "the step adjoint needs a fixed dt > 0");

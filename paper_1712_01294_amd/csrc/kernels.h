@@ -27,6 +27,7 @@ struct PassArrays {
     double *H, *nk, *V;
     double *B, *rho, *P, *grad, *alpha;
     double *dp, *dE, *vsig;
+    double *dm;   // finite-volume form only
 };
 
 // tree.hip
@@ -56,7 +57,7 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
                       int mixed, double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1,
                       hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
-                   int mixed, const void* rec, Counters* cnt, hipStream_t s);
+                   int mixed, int mfv, const void* rec, Counters* cnt, hipStream_t s);
 
 // step.hip
 void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor,

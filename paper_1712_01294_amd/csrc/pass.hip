@@ -1085,6 +1085,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
 // ------------------------------------------------------------------- fluxes
 template <typename T>
 struct PairOut {
+    T Fm;
     T Fp[3];
     T FE;
     int fallback, clamp;
@@ -1118,11 +1119,54 @@ __device__ __forceinline__ T add_rn(T x, T y) {
 // for that side (left: +1/2, right: -1/2 along d), and the sum of the two
 // face halves is commutative and unfused, so both owners produce the same
 // bits; only the reconstructed face states are put in left/right order.
+// MFV (the finite-volume form): the full HLLC flux through the face, which
+// moves with w.  Only the side that the star-state selection picks is built:
+// K is the left side when S* >= 0 (or S_L >= 0), else the right side, and the
+// star correction S_K (U*_K - U_K) is added unless that side's outer wave has
+// already passed the face.  In the face frame (primes) the side state is
+// rho, v' = v - w, E = P/(gamma-1) + rho |v'|^2/2, with physical flux
+// (rho u, rho u v' + P n, (E + P) u), u = v'.n; its star state scales by
+// f = rho (S_K - u)/(S_K - S*) and takes the normal speed S*.  The lab-frame
+// flux adds w times the mass flux to the momentum flux and
+// w.F_mom' + |w|^2/2 F_mass to the energy flux.
 template <typename T>
+__device__ __forceinline__ void mfv_flux(const T qL[5], const T qR[5], const T w[3], const T nh[3], T uL, T uR,
+                                         T SL, T SR, T Ss, T gamma, T Amag, PairOut<T>& out) {
+    const bool left = (SL >= T(0)) || (Ss >= T(0));
+    const bool star = left ? !(SL >= T(0)) : (SR >= T(0));
+    T q[5];
+#pragma unroll
+    for (int f = 0; f < 5; f++) q[f] = left ? qL[f] : qR[f];
+    const T u = left ? uL : uR;
+    const T S = left ? SL : SR;
+    const T rho = q[0], P = q[4];
+    const T vp[3] = {q[1] - w[0], q[2] - w[1], q[3] - w[2]};
+    const T E = P / (gamma - T(1)) + T(0.5) * rho * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]);
+    T F[5];
+    F[0] = rho * u;
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[1 + c] = rho * vp[c] * u + P * nh[c];
+    F[4] = (E + P) * u;
+    if (star) {
+        const T f = rho * (S - u) / (S - Ss);
+        const T du = Ss - u;
+        F[0] += S * (f - rho);
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[1 + c] += S * (f * (vp[c] + du * nh[c]) - rho * vp[c]);
+        F[4] += S * (f * (E / rho + du * (Ss + P / (rho * (S - u)))) - E);
+    }
+    const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    out.Fm = F[0] * Amag;
+#pragma unroll
+    for (int c = 0; c < 3; c++) out.Fp[c] = (F[1 + c] + w[c] * F[0]) * Amag;
+    out.FE = (F[4] + w[0] * F[1] + w[1] * F[2] + w[2] * F[3] + T(0.5) * ww * F[0]) * Amag;
+}
+
+template <typename T, bool MFV>
 __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T* __restrict__ o, bool mL,
                                                 const T d[3], T r, T gamma) {
     PairOut<T> out;
-    out.Fp[0] = out.Fp[1] = out.Fp[2] = out.FE = T(0);
+    out.Fm = out.Fp[0] = out.Fp[1] = out.Fp[2] = out.FE = T(0);
     out.fallback = out.clamp = 0;
     // face A = V_m^2 W_m B_m d + V_o^2 W_o B_o d (the kernel factor K = V^2 8/(pi H^3))
     const T km = m[R_K] * spline_w(r * m[R_IH]);
@@ -1173,6 +1217,10 @@ __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T
     const T SR = (uL + cL > uR + cR) ? uL + cL : uR + cR;
     const T mLf = rL * (SL - uL), mRf = rR * (SR - uR);
     const T Ss = (pR - pL + mLf * uL - mRf * uR) / (mLf - mRf);
+    if (MFV) {
+        mfv_flux<T>(qL, qR, w, nh, uL, uR, SL, SR, Ss, gamma, Amag, out);
+        return out;
+    }
     T Ps = T(0.5) * (pL + pR + mLf * (Ss - uL) + mRf * (Ss - uR));
     if (Ps < T(0)) {
         Ps = T(0);
@@ -1210,7 +1258,7 @@ __device__ __forceinline__ void load_rec<float>(const float* __restrict__ rec, l
     }
 }
 
-template <typename T>
+template <typename T, bool MFV>
 __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
                                             const int* __restrict__ list, const T* __restrict__ rec,
                                             Counters* cnt) {
@@ -1226,6 +1274,7 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         const double vi[3] = {(double)ri[R_V0], (double)ri[R_V0 + 1], (double)ri[R_V0 + 2]};
         const double ci = (double)ri[R_C];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double accm = 0.0;
         double vs = 0.0;
         const T gam = (T)ph.gamma;
         const int cnum = counts[i];
@@ -1251,8 +1300,9 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             // negation exactly, so both owners of the pair hold the same bits
             const double sg = iL ? 1.0 : -1.0;
             const T dT[3] = {(T)(sg * dij[0]), (T)(sg * dij[1]), (T)(sg * dij[2])};
-            PairOut<T> o = pair_flux<T>(ri, rj, iL, dT, (T)r, gam);
+            PairOut<T> o = pair_flux<T, MFV>(ri, rj, iL, dT, (T)r, gam);
             const double s = iL ? 1.0 : -1.0;
+            if (MFV) accm -= s * (double)o.Fm;
             acc[0] -= s * (double)o.Fp[0];
             acc[1] -= s * (double)o.Fp[1];
             acc[2] -= s * (double)o.Fp[2];
@@ -1269,7 +1319,8 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         a.dp[2 * n + i] = acc[2];
         a.dE[i] = acc[3];
         a.vsig[i] = vs;
-        if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(acc[3])) {
+        if (MFV) a.dm[i] = accm;
+        if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(acc[3]) || !isfinite(accm)) {
             nonfin = 1;
             flag_index(cnt, i);
         }
@@ -1288,13 +1339,20 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
-    fluxes_body<double>(a, ph, counts, list, rec, cnt);
+    fluxes_body<double, false>(a, ph, counts, list, rec, cnt);
+}
+
+// The finite-volume form, FP64 records only.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_mfv(PassArrays a, Phys ph, const int* __restrict__ counts,
+                                                    const int* __restrict__ list, const double* __restrict__ rec,
+                                                    Counters* cnt) {
+    fluxes_body<double, true>(a, ph, counts, list, rec, cnt);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
 void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
                   const float* __restrict__ rec, Counters* cnt) {
-    fluxes_body<float>(a, ph, counts, list, rec, cnt);
+    fluxes_body<float, false>(a, ph, counts, list, rec, cnt);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1331,9 +1389,11 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
 
-void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
+void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed, int mfv,
                    const void* rec, Counters* cnt, hipStream_t s) {
-    if (mixed)
+    if (mfv)
+        k_fluxes_mfv<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+    else if (mixed)
         k_fluxes_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
     else
         k_fluxes_f64<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);

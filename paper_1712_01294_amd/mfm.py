@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfm.so")
 
 FP64, MIXED = 0, 1
+SCHEME_MFM, SCHEME_MFV = 0, 1   # mfm_scheme
 
 STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV", -4: "MFM_E_ILLCOND",
           -5: "MFM_E_MINIMAGE", -6: "MFM_E_CAPACITY", -7: "MFM_E_NONFINITE", -8: "MFM_E_STATE"}
@@ -34,7 +35,7 @@ class Params(C.Structure):
                 ("box", C.c_double * 3), ("periodic", C.c_int32 * 3), ("precision", C.c_int32),
                 ("beta", C.c_double), ("cond_max", C.c_double), ("u_floor", C.c_double),
                 ("h_maxit", C.c_int32), ("max_ngb", C.c_int32), ("tree_levels", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("scheme", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -44,7 +45,7 @@ class Particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", _dp), ("y", _dp), ("z", _dp), ("m", _dp), ("vx", _dp),
                 ("vy", _dp), ("vz", _dp), ("u", _dp), ("H", _dp), ("nk", _dp), ("V", _dp),
                 ("B", _dp), ("rho", _dp), ("P", _dp), ("grad", _dp), ("alpha", _dp), ("dp", _dp),
-                ("dE", _dp), ("vsig", _dp), ("id", C.POINTER(C.c_int64))]
+                ("dE", _dp), ("vsig", _dp), ("id", C.POINTER(C.c_int64)), ("dm", _dp)]
 
 
 class Counters(C.Structure):
@@ -129,6 +130,7 @@ class Config:
     h_maxit: int = 64
     max_ngb: int = 256
     tree_levels: int = 0
+    scheme: int = SCHEME_MFM
 
     def c(self) -> Params:
         p = Params()
@@ -145,6 +147,7 @@ class Config:
         p.h_maxit = self.h_maxit
         p.max_ngb = self.max_ngb
         p.tree_levels = self.tree_levels
+        p.scheme = int(self.scheme)
         return p
 
 
@@ -153,7 +156,7 @@ class State:
 
     INPUTS = ("x", "y", "z", "m", "vx", "vy", "vz", "u")
 
-    def __init__(self, n: int, device="cuda", alpha: bool = False, ids: bool = True):
+    def __init__(self, n: int, device="cuda", alpha: bool = False, ids: bool = True, dm: bool = False):
         f = dict(dtype=torch.float64, device=device)
         self.n = n
         for k in self.INPUTS + ("H", "nk", "V", "rho", "P", "dE", "vsig"):
@@ -163,6 +166,7 @@ class State:
         self.dp = torch.zeros(3, n, **f)
         self.alpha = torch.zeros(5, n, **f) if alpha else None
         self.id = torch.arange(n, dtype=torch.int64, device=device) if ids else None
+        self.dm = torch.zeros(n, **f) if dm else None
 
     @classmethod
     def from_arrays(cls, arrays: dict, device="cuda", **kw) -> "State":
@@ -176,7 +180,7 @@ class State:
         p = Particles()
         p.n = self.n
         for k in ("x", "y", "z", "m", "vx", "vy", "vz", "u", "H", "nk", "V", "B", "rho", "P", "grad",
-                  "alpha", "dp", "dE", "vsig"):
+                  "alpha", "dp", "dE", "vsig", "dm"):
             setattr(p, k, _ptr(getattr(self, k)))
         p.id = C.cast(C.c_void_p(self.id.data_ptr()), C.POINTER(C.c_int64)) if self.id is not None else None
         return p

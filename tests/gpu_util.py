@@ -9,7 +9,7 @@ def run_pass(w, precision=0, alpha=True, **cfg_kw):
     from paper_1712_01294_amd import mfm
     cfg = mfm.config_of(w, precision=precision, **cfg_kw)
     ctx = mfm.Context(cfg, w.n)
-    st = mfm.State.from_arrays(w.arrays(), alpha=alpha)
+    st = mfm.State.from_arrays(w.arrays(), alpha=alpha, dm=cfg.scheme == mfm.SCHEME_MFV)
     ctx.build_neighbours(st)
     ctx.hydro_pass(st)
     torch.cuda.synchronize()

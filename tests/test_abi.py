@@ -55,9 +55,36 @@ def test_create_rejects_bad_parameters_before_touching_the_device(lib):
     good = mfm.Config(gamma=5 / 3, box=(1, 1, 1))
     h = C.c_void_p()
     for bad in (dict(gamma=1.0), dict(n_ngb=10.0), dict(box=(1, 0, 1)), dict(beta=0.0),
-                dict(precision=7)):
+                dict(precision=7), dict(scheme=7), dict(scheme=mfm.SCHEME_MFV, precision=mfm.MIXED)):
         cfg = mfm.Config(**{**good.__dict__, **bad})
         assert lib.mfm_create(C.byref(cfg.c()), 1000, C.byref(h)) == -1
         assert not h.value
     assert lib.mfm_create(C.byref(good.c()), 0, C.byref(h)) == -1
     assert lib.mfm_create(None, 10, C.byref(h)) == -1
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """sizeof and every field offset of the three structs, from a C compile of the header."""
+    import shutil
+    import subprocess
+    from paper_1712_01294_amd import mfm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mfm_params": mfm.Params, "mfm_particles": mfm.Particles, "mfm_counters": mfm.Counters}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mfm.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
