@@ -293,10 +293,13 @@ def sampled_pass(s: Setup, st: dict, targets, h_bound: float):
 # R17/R18: kick-drift-kick step with a predicted state, one pass per step.
 # --------------------------------------------------------------------------
 class Stepper:
-    """Plain FP64 time integration of the MFM gas (global time step)."""
+    """Plain FP64 time integration of the gas (global time step).  scheme "mfm"
+    keeps every mass; scheme "mfv" (R21/R22) kicks mass, momentum and total
+    energy as conserved quantities with the mass flux of the finite-volume form."""
 
-    def __init__(self, w, cell=None, u_floor=None):
+    def __init__(self, w, cell=None, u_floor=None, scheme="mfm"):
         self.s = Setup.of(w, cell=cell)
+        self.s.scheme = scheme
         self.cfl = w.cfl
         self.st = {k: _f64(getattr(w, k)).copy() for k in ("x", "y", "z", "m", "vx", "vy", "vz", "u")}
         self.u_floor = 1e-10 * float(np.mean(self.st["u"])) if u_floor is None else u_floor
@@ -304,8 +307,8 @@ class Stepper:
         self.last = None
         self.floors = 0
 
-    def _pass(self, x, y, z, vx, vy, vz, u):
-        st = dict(x=x, y=y, z=z, m=self.st["m"], vx=vx, vy=vy, vz=vz, u=u)
+    def _pass(self, x, y, z, vx, vy, vz, u, m=None):
+        st = dict(x=x, y=y, z=z, m=self.st["m"] if m is None else m, vx=vx, vy=vy, vz=vz, u=u)
         out = hydro_pass(self.s, st, self.H)
         self.H = out["H"]
         return out
@@ -324,6 +327,9 @@ class Stepper:
         st, s, last = self.st, self.s, self.last
         if dt is None or dt <= 0:
             dt = self.cfl_dt(last)
+        if self.s.scheme == "mfv":
+            self._step_mfv(dt)
+            return dt
         m = st["m"]
         # first half kick of momentum and total energy
         E = m * (st["u"] + 0.5 * (st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2))
@@ -354,3 +360,48 @@ class Stepper:
         st.update(x=x[0], y=x[1], z=x[2], vx=v[0], vy=v[1], vz=v[2], u=u)
         self.last = out
         return dt
+
+    def _drift(self, v, dt):
+        st, s = self.st, self.s
+        x = []
+        for c, k in enumerate(("x", "y", "z")):
+            xc = st[k] + dt * v[c]
+            if s.periodic[c]:
+                L = s.box[c]
+                xc = xc - L * np.floor(xc / L)
+                xc[xc >= L] = 0.0
+            x.append(xc)
+        return x
+
+    def _step_mfv(self, dt):
+        """R22: kick-drift-kick of the conserved mass Q_m = m, momentum Q_p = m v
+        and total energy Q_E = m (u + |v|^2/2) with the rates (dm, dp, dE) of
+        the finite-volume pass; velocities and u are recovered as Q_p/Q_m and
+        Q_E/Q_m - |v|^2/2 after each kick."""
+        st, last = self.st, self.last
+        m = st["m"]
+        v = [st[k] for k in ("vx", "vy", "vz")]
+        # first half kick of the conserved quantities
+        Qm = m + 0.5 * dt * last["dm"]
+        Qp = [m * v[c] + 0.5 * dt * last["dp"][c] for c in range(3)]
+        QE = m * (st["u"] + 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)) + 0.5 * dt * last["dE"]
+        vh = [Qp[c] / Qm for c in range(3)]
+        # drift with the half-step velocity, wrapped into the box
+        x = self._drift(vh, dt)
+        # predicted state for the flux pass, its masses included
+        mp = Qm + 0.5 * dt * last["dm"]
+        vp = [(Qp[c] + 0.5 * dt * last["dp"][c]) / mp for c in range(3)]
+        up = (QE + 0.5 * dt * last["dE"]) / mp - 0.5 * (vp[0] ** 2 + vp[1] ** 2 + vp[2] ** 2)
+        up = np.maximum(up, self.u_floor)
+        out = self._pass(x[0], x[1], x[2], vp[0], vp[1], vp[2], up, m=mp)
+        # second half kick and recovery of v and u
+        Qm = Qm + 0.5 * dt * out["dm"]
+        Qp = [Qp[c] + 0.5 * dt * out["dp"][c] for c in range(3)]
+        QE = QE + 0.5 * dt * out["dE"]
+        v = [Qp[c] / Qm for c in range(3)]
+        u = QE / Qm - 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+        low = u < self.u_floor
+        self.floors += int(np.count_nonzero(low))
+        u = np.where(low, self.u_floor, u)
+        st.update(x=x[0], y=x[1], z=x[2], m=Qm, vx=v[0], vy=v[1], vz=v[2], u=u)
+        self.last = out
