@@ -57,8 +57,8 @@ typedef enum { MFM_FP64 = 0, MFM_MIXED = 1 } mfm_precision;
  * describes).  MFV (the other mesh-free Godunov form that section 2 lists;
  * section 4 on meshes that move): the same pass, but the full HLLC flux of
  * mass, momentum and energy crosses each face, which moves with the mean
- * particle velocity, so masses change at the rate dm.  MFV runs in MFM_FP64 only, and mfm_step and the adjoints accept
- * only MFM. */
+ * particle velocity, so masses change at the rate dm.  MFV runs in MFM_FP64
+ * only; mfm_step integrates both forms and the adjoints accept only MFM. */
 typedef enum { MFM_SCHEME_MFM = 0, MFM_SCHEME_MFV = 1 } mfm_scheme;
 
 typedef struct {
@@ -190,7 +190,11 @@ mfm_status mfm_hydro_pass(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * pass of the current state (mfm_hydro_pass or a previous mfm_step), and
  * hold the new state's pass on return.  dt > 0: fixed step; dt <= 0: CFL
  * step cfl * min_i H_i / vsig_i from the current vsig (reading R18), which
- * synchronises the stream.  *dt_used (nullable, host) receives the step. */
+ * synchronises the stream.  *dt_used (nullable, host) receives the step.
+ * MFM_SCHEME_MFV (reading R22): mass, momentum m v and total energy are the
+ * kicked quantities, with dm, dp, dE (dm required); the half kick sets m and
+ * v = (m v)/m; the pass runs on the predicted masses too; the second half
+ * kick updates m, v and u in place. */
 mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, void *stream);
 
 /* Adjoint of the pass (reading R20): given the adjoints adj_dp (3 x n) and

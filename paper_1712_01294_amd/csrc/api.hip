@@ -43,6 +43,7 @@ struct mfm_ctx {
     void* rec = nullptr;                  // 32 x 8 B per particle
     double4* prim = nullptr;              // 128 B per particle: what gradients read of a neighbour
     double *vp = nullptr, *up = nullptr, *Ehalf = nullptr;
+    double* mp = nullptr;                 // predicted masses of the finite-volume step
     double *dt_part = nullptr, *dt_out = nullptr;
     Counters* cnt = nullptr;
     double* adj = nullptr;                // adjoint scratch, kAdjSlots x cap, allocated on first use
@@ -195,7 +196,7 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->dt_part, c->dt_out, c->cnt, c->adj};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -259,6 +260,7 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
     alloc((void**)&c->up, sizeof(double) * n, "predicted u");
     alloc((void**)&c->Ehalf, sizeof(double) * n, "half-step energy");
+    if (p.scheme == MFM_SCHEME_MFV) alloc((void**)&c->mp, sizeof(double) * n, "predicted masses");
     alloc((void**)&c->dt_part, sizeof(double) * 1024, "dt partials");
     alloc((void**)&c->dt_out, sizeof(double) * 2, "dt");
     alloc((void**)&c->cnt, (size_t)kCounterCopies * kCounterStride, "counters");
@@ -319,6 +321,10 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     gb.count = 0;
     auto add = [&](void* ptr) {
         if (!ptr) return;
+        if (gb.count == kGatherMax) {   // staging full: reorder this batch, then reuse the staging
+            launch_gather(n, gb, c->idx, s);
+            gb.count = 0;
+        }
         unsigned long long* stage = c->gtmp + (long long)gb.count * n;
         hipMemcpyAsync(stage, ptr, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
         gb.src[gb.count] = stage;
@@ -439,8 +445,8 @@ mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
 mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "mfm_step integrates the MFM scheme only");
-    if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
+    const int mfv = c->p.scheme == MFM_SCHEME_MFV;
+    if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad || (mfv && !p->dm))
         return fail(c, MFM_E_INVALID, "mfm_step needs every pass output array");
     if (!c->have_flux || c->n_tree != p->n)
         return fail(c, MFM_E_STATE, "mfm_step needs a pass on the current state (mfm_hydro_pass)");
@@ -460,20 +466,27 @@ mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, vo
     if (dt_used) *dt_used = dt;
     reset_counters(c, s);
     PassArrays a = arrays_of(p);
-    launch_kick_drift(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, s);
-    double* extra[5] = {c->vp, c->vp + n, c->vp + 2 * (long long)n, c->up, c->Ehalf};
-    if ((st = build(c, p, s, extra, 5))) return st;
-    // pass on the predicted state
+    if (mfv)
+        launch_kick_drift_mfv(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, c->mp, s);
+    else
+        launch_kick_drift(a, c->ph, dt, c->p.u_floor, c->vp, c->up, c->Ehalf, s);
+    double* extra[6] = {c->vp, c->vp + n, c->vp + 2 * (long long)n, c->up, c->Ehalf, c->mp};
+    if ((st = build(c, p, s, extra, mfv ? 6 : 5))) return st;
+    // pass on the predicted state (with the predicted masses in the finite-volume form)
     mfm_particles q = *p;
     q.vx = c->vp;
     q.vy = c->vp + n;
     q.vz = c->vp + 2 * (long long)n;
     q.u = c->up;
+    if (mfv) q.m = c->mp;
     if ((st = do_solve_h(c, &q, s))) return st;
     if ((st = do_gradients(c, &q, s))) return st;
     if ((st = do_fluxes(c, &q, s))) return st;
     a = arrays_of(p);
-    launch_kick2(a, dt, c->p.u_floor, c->Ehalf, p->u, c->cnt, s);
+    if (mfv)
+        launch_kick2_mfv(a, dt, c->p.u_floor, c->Ehalf, p->u, c->cnt, s);
+    else
+        launch_kick2(a, dt, c->p.u_floor, c->Ehalf, p->u, c->cnt, s);
     c->last = s;
     return launched(c, "step");
 }

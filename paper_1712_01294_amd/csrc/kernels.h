@@ -64,6 +64,10 @@ void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_
                        double* vp, double* up, double* Ehalf, hipStream_t s);
 void launch_kick2(const PassArrays& a, double dt, double u_floor, const double* Ehalf,
                   double* u, Counters* cnt, hipStream_t s);
+void launch_kick_drift_mfv(const PassArrays& a, const Phys& ph, double dt, double u_floor,
+                           double* vp, double* up, double* Ehalf, double* mp, hipStream_t s);
+void launch_kick2_mfv(const PassArrays& a, double dt, double u_floor, const double* Ehalf,
+                      double* u, Counters* cnt, hipStream_t s);
 void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts,
                    double* out, hipStream_t s);
 int dt_min_parts(int n);

@@ -1,4 +1,4 @@
-// Kick-drift-kick update of the MFM gas and the Courant time-step reduction.
+// Kick-drift-kick update of the gas (MFM and MFV forms) and the Courant time-step reduction.
 #include <math.h>
 
 #include "device.h"
@@ -70,6 +70,85 @@ __global__ void k_kick2(PassArrays a, double dt, double u_floor, const double* _
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt->floors, s);
 }
 
+// Finite-volume form: mass, momentum m v and total energy are kicked as
+// conserved quantities with (dm, dp, dE), and v and u are recovered from them.
+// First half kick, drift with the half-step velocity and wrap, and the
+// predicted mass, velocity and u for the flux pass.  The half-step mass and
+// velocity replace m and v; the half-step energy goes to Ehalf.
+__global__ void k_kick_drift_mfv(PassArrays a, Phys ph, double dt, double u_floor, double* __restrict__ vp,
+                                 double* __restrict__ up, double* __restrict__ Ehalf, double* __restrict__ mp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const long long n = a.n;
+    const double m = a.m[i];
+    const double v0[3] = {a.vx[i], a.vy[i], a.vz[i]};
+    const double hdt = 0.5 * dt;
+    const double mh = m + hdt * a.dm[i];
+    double Qp[3], vh[3];
+    for (int c = 0; c < 3; c++) {
+        Qp[c] = m * v0[c] + hdt * a.dp[c * n + i];
+        vh[c] = Qp[c] / mh;
+    }
+    const double Eh = m * (a.u[i] + 0.5 * (v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2])) + hdt * a.dE[i];
+    double* xs[3] = {(double*)a.x, (double*)a.y, (double*)a.z};
+    for (int c = 0; c < 3; c++) {
+        double xc = xs[c][i] + dt * vh[c];
+        if (ph.periodic[c]) {
+            const double L = ph.box[c];
+            xc = xc - L * floor(xc / L);
+            if (xc >= L) xc = 0.0;
+        }
+        xs[c][i] = xc;
+    }
+    const double mq = mh + hdt * a.dm[i];
+    double q[3];
+    for (int c = 0; c < 3; c++) q[c] = (Qp[c] + hdt * a.dp[c * n + i]) / mq;
+    double uu = (Eh + hdt * a.dE[i]) / mq - 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    uu = fmax(uu, u_floor);
+    ((double*)a.m)[i] = mh;
+    ((double*)a.vx)[i] = vh[0];
+    ((double*)a.vy)[i] = vh[1];
+    ((double*)a.vz)[i] = vh[2];
+    vp[i] = q[0];
+    vp[n + i] = q[1];
+    vp[2 * n + i] = q[2];
+    up[i] = uu;
+    Ehalf[i] = Eh;
+    mp[i] = mq;
+}
+
+// second half kick of the conserved quantities, then v = (m v)/m and
+// u = E/m - |v|^2/2, floored
+__global__ void k_kick2_mfv(PassArrays a, double dt, double u_floor, const double* __restrict__ Ehalf,
+                            double* __restrict__ u, Counters* cnt) {
+    cnt = counter_copy(cnt);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long fl = 0;
+    if (i < a.n) {
+        const long long n = a.n;
+        const double hdt = 0.5 * dt;
+        const double mh = a.m[i];
+        const double vh[3] = {a.vx[i], a.vy[i], a.vz[i]};
+        const double m1 = mh + hdt * a.dm[i];
+        double v[3];
+        for (int c = 0; c < 3; c++) v[c] = (mh * vh[c] + hdt * a.dp[c * n + i]) / m1;
+        const double E = Ehalf[i] + hdt * a.dE[i];
+        double uu = E / m1 - 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (uu < u_floor) {
+            uu = u_floor;
+            fl = 1;
+        }
+        ((double*)a.m)[i] = m1;
+        ((double*)a.vx)[i] = v[0];
+        ((double*)a.vy)[i] = v[1];
+        ((double*)a.vz)[i] = v[2];
+        u[i] = uu;
+    }
+    unsigned long long s = fl;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt->floors, s);
+}
+
 // min_i H_i / vsig_i: per-block partial minima, then one block over the partials
 __global__ __launch_bounds__(256) void k_dt_partial(int n, const double* __restrict__ H,
                                                      const double* __restrict__ vsig, double* __restrict__ part) {
@@ -114,6 +193,16 @@ void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_
 void launch_kick2(const PassArrays& a, double dt, double u_floor, const double* Ehalf, double* u, Counters* cnt,
                   hipStream_t s) {
     k_kick2<<<(a.n + 255) / 256, 256, 0, s>>>(a, dt, u_floor, Ehalf, u, cnt);
+}
+
+void launch_kick_drift_mfv(const PassArrays& a, const Phys& ph, double dt, double u_floor, double* vp, double* up,
+                           double* Ehalf, double* mp, hipStream_t s) {
+    k_kick_drift_mfv<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt, u_floor, vp, up, Ehalf, mp);
+}
+
+void launch_kick2_mfv(const PassArrays& a, double dt, double u_floor, const double* Ehalf, double* u,
+                      Counters* cnt, hipStream_t s) {
+    k_kick2_mfv<<<(a.n + 255) / 256, 256, 0, s>>>(a, dt, u_floor, Ehalf, u, cnt);
 }
 
 void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts, double* out,
