@@ -907,8 +907,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
         const float normf = (float)norm, iHf = (float)iH;
         const int cnum = gcount[i];
         const int cap = ph.max_ngb;
+        // the next list entry is loaded one neighbour ahead, so the record
+        // loads do not wait for their index
+        int jn = cnum > 0 ? list[i] : 0;
         for (int k = 0; k < cnum; k++) {
-            const int j = list[(long long)k * n + i];
+            const int j = jn;
+            if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
             const double4 pj = prim[4 * (long long)j + 0];
             const double4 qj = prim[4 * (long long)j + 1];
             const double2 pg = *(const double2*)&prim[4 * (long long)j + 2];
@@ -1278,8 +1282,12 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         double vs = 0.0;
         const T gam = (T)ph.gamma;
         const int cnum = counts[i];
+        // the next list entry is loaded one pair ahead, so the record loads of
+        // a pair do not wait for its index
+        int jn = cnum > 0 ? list[i] : 0;
         for (int k = 0; k < cnum; k++) {
-            const int j = list[(long long)k * n + i];
+            const int j = jn;
+            if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
             T rj[32];
             load_rec<T>(rec, j, rj);
             double xj[3];
@@ -1330,11 +1338,13 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
     count_add(&cnt->nonfinite, nonfin);
 }
 
-// One kernel per record precision: each pair holds both records in registers,
-// and the FP32 form fits four waves per SIMD where the FP64 form fits three
-// (with a few spilled loop invariants, cheaper than the third wave is worth).
+// One kernel per record precision: each pair holds both records in registers.
+// The FP32 form runs at four waves per SIMD.  The FP64 form runs at two: with
+// the list index loaded a pair ahead, a third wave (a few spilled loop
+// invariants, and twice the HBM traffic as more records compete for L2) no
+// longer pays.
 #ifndef MFM_FLUX64_WAVES
-#define MFM_FLUX64_WAVES 3
+#define MFM_FLUX64_WAVES 2
 #endif
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
@@ -1342,11 +1352,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_
     fluxes_body<double, false>(a, ph, counts, list, rec, cnt);
 }
 
-// The finite-volume form, FP64 records only.  At three waves per SIMD its
-// extra live values spill (eight registers, 9 GB of scratch traffic on the
-// clustered set); at two it fits in 192 registers and runs 3% faster.
+// The finite-volume form, FP64 records only, at two waves per SIMD like the
+// FP64 form (at three its extra live values spill).
 #ifndef MFM_FLUXMFV_WAVES
-#define MFM_FLUXMFV_WAVES 2
+#define MFM_FLUXMFV_WAVES MFM_FLUX64_WAVES
 #endif
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUXMFV_WAVES))) void k_fluxes_mfv(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
