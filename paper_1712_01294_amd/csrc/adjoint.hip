@@ -301,8 +301,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_ADJ_PAI
     zero_adj(own);
     double lx[3] = {0.0, 0.0, 0.0};
     const int cnum = counts[i];
+    int jn = cnum > 0 ? list[i] : 0;   // the next list entry, loaded one neighbour ahead
     for (int k = 0; k < cnum; k++) {
-        const int j = list[(long long)k * n + i];
+        const int j = jn;
+        if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
         const bool iL = i < j;
         const double* rL = rec + (long long)(iL ? i : j) * kAdjRec;
         const double* rR = rec + (long long)(iL ? j : i) * kAdjRec;
@@ -404,8 +406,10 @@ __global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, con
     }
     double rmax = 0.0;
     int jr = i;
+    int jn = cnum > 0 ? list[i] : 0;   // the next list entry, loaded one neighbour ahead
     for (int k = 0; k < cnum; k++) {
-        const int j = list[(long long)k * n + i];
+        const int j = jn;
+        if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
         double d[3];
         disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -527,8 +531,10 @@ __global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, con
     // i's side of every pair of its gather set
     double lH = 0.0, lV = 0.0;
     double lxi[3] = {0.0, 0.0, 0.0};
+    jn = cnum > 0 ? list[i] : 0;   // the next list entry, loaded one neighbour ahead
     for (int k = 0; k < cnum; k++) {
-        const int j = list[(long long)k * n + i];
+        const int j = jn;
+        if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
         double d[3];
         disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -621,8 +627,10 @@ __global__ __launch_bounds__(256) void k_adj_length_own(PassArrays a, Phys ph, c
     const int cnum = gcount[i];
     // sums over the gather set (self term: r = 0, w(0) = 1, q w'(q) = 0)
     double sqdw = 0.0;
+    int jn = cnum > 0 ? list[i] : 0;   // the next list entry, loaded one neighbour ahead
     for (int k = 0; k < cnum; k++) {
-        const int j = list[(long long)k * n + i];
+        const int j = jn;
+        if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
         double d[3];
         disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -645,8 +653,10 @@ __global__ __launch_bounds__(256) void k_adj_length_own(PassArrays a, Phys ph, c
     rc[P_H] = Hi;
     rc[P_V] = fac;
     double lxi[3] = {0.0, 0.0, 0.0};
+    jn = cnum > 0 ? list[i] : 0;   // the next list entry, loaded one neighbour ahead
     for (int k = 0; k < cnum; k++) {
-        const int j = list[(long long)k * n + i];
+        const int j = jn;
+        if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
         double d[3];
         disp(ph, xi, a.x[j], a.y[j], a.z[j], d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
