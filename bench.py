@@ -2,6 +2,7 @@
 
     python bench.py [--steps K] [--warmup W] [--workload clustered|turbulence|shock_tube|...]
     python bench.py --copy-probe        # plain device copy of known size (counter calibration)
+    python bench.py --adjoint-only      # forward + adjoint of 10 steps on the 64^3 box only
 
 Metric: unordered particle-pair interactions per second per hydro pass (kernel
 length + gradients + fluxes on particles already in the library's spatial
@@ -110,6 +111,8 @@ def parse():
     ap.add_argument("--no-mfv", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the forward + adjoint timing of 10 steps on the 64^3 box")
     return ap.parse_args()
 
 
@@ -257,6 +260,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     if args.copy_probe:
         copy_probe()
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_timing()}), flush=True)
         return
 
     from paper_1712_01294_amd import mfm, workloads
