@@ -33,14 +33,20 @@ class Evolution:
         self.cfg = cfg or mfm.config_of(w)
         self.ctx = mfm.Context(self.cfg, w.n)
         self.n = w.n
+        # the fixed data, resident on the device once
+        self.dev = {k: torch.as_tensor(v, dtype=torch.float64).cuda() for k, v in w.arrays().items()}
 
     def _state(self):
-        return mfm.State(self.n)
+        # every checkpoint array is copied in before it is read
+        return mfm.State(self.n, zero=False)
 
     def run(self, v0: torch.Tensor, u0: torch.Tensor, keep: bool):
         """Forward; v0 (3, n) and u0 (n) in the input order.  Returns the final
         state (library order) and the checkpoints if keep."""
-        st = mfm.State.from_arrays(self.w.arrays())
+        st = mfm.State(self.n, zero=False)
+        for k in ("x", "y", "z", "m"):
+            getattr(st, k).copy_(self.dev[k])
+        st.H.zero_()                        # cold kernel-length start
         st.vx.copy_(v0[0])
         st.vy.copy_(v0[1])
         st.vz.copy_(v0[2])
@@ -88,11 +94,11 @@ class MFMSteps(torch.autograd.Function):
         au = gu[ids].contiguous()
         ap = torch.zeros(3, n, **f)
         ae = torch.zeros(n, **f)
-        work = mfm.State(n)
+        work = mfm.State(n, zero=False)   # the step adjoint writes it before reading
         for ck in reversed(ctx.cks):
             evo.ctx.step_adjoint(ck, work, evo.dt, ax, av, au, ap, ae)
         # the initial pass produced (dp, dE) of the first state: reverse it
-        st0 = mfm.State(n)
+        st0 = mfm.State(n, zero=False)
         first = ctx.cks[0] if ctx.cks else None
         if first is None:
             raise RuntimeError("MFMSteps needs at least one step")

@@ -156,17 +156,21 @@ class State:
 
     INPUTS = ("x", "y", "z", "m", "vx", "vy", "vz", "u")
 
-    def __init__(self, n: int, device="cuda", alpha: bool = False, ids: bool = True, dm: bool = False):
+    def __init__(self, n: int, device="cuda", alpha: bool = False, ids: bool = True, dm: bool = False,
+                 zero: bool = True):
+        """zero=False leaves the arrays uninitialised (for states whose every
+        array is written before it is read, such as checkpoint copies)."""
         f = dict(dtype=torch.float64, device=device)
+        new = torch.zeros if zero else torch.empty
         self.n = n
         for k in self.INPUTS + ("H", "nk", "V", "rho", "P", "dE", "vsig"):
-            setattr(self, k, torch.zeros(n, **f))
-        self.B = torch.zeros(6, n, **f)
-        self.grad = torch.zeros(15, n, **f)
-        self.dp = torch.zeros(3, n, **f)
-        self.alpha = torch.zeros(5, n, **f) if alpha else None
+            setattr(self, k, new(n, **f))
+        self.B = new(6, n, **f)
+        self.grad = new(15, n, **f)
+        self.dp = new(3, n, **f)
+        self.alpha = new(5, n, **f) if alpha else None
         self.id = torch.arange(n, dtype=torch.int64, device=device) if ids else None
-        self.dm = torch.zeros(n, **f) if dm else None
+        self.dm = new(n, **f) if dm else None
 
     @classmethod
     def from_arrays(cls, arrays: dict, device="cuda", **kw) -> "State":
