@@ -78,10 +78,10 @@ KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/cs
 # known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
 # only for the kernel sources whose fingerprint is recorded with it.
 TRAFFIC = {
-    ("clustered", "solve_h"): {"bytes_per_launch": 140.94e9, "fingerprint": "cf4565ed9dfa17c6"},
-    ("clustered", "gradients"): {"bytes_per_launch": 30.51e9, "fingerprint": "cf4565ed9dfa17c6"},
-    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 13.80e9, "fingerprint": "cf4565ed9dfa17c6"},
-    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 14.18e9, "fingerprint": "cf4565ed9dfa17c6"},
+    ("clustered", "solve_h"): {"bytes_per_launch": 141.36e9, "fingerprint": "f37d0d7110d4f801"},
+    ("clustered", "gradients"): {"bytes_per_launch": 30.50e9, "fingerprint": "f37d0d7110d4f801"},
+    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 13.79e9, "fingerprint": "f37d0d7110d4f801"},
+    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 14.19e9, "fingerprint": "f37d0d7110d4f801"},
 }
 
 
@@ -375,6 +375,19 @@ def main():
                       "fallbacks": cv["fallbacks"]}
         log(f"mfv: " + " ".join(f"{k}={v:.3f}ms" for k, v in tv.items())
             + f" flux kernel {fk['ms_avg']:.3f} ms")
+        if not args.no_mixed:
+            ctx, stvm, tvm, kvm, cvm = run_precision(mfm, w, mfm.MIXED, kw, args, stream, scheme=mfm.SCHEME_MFV)
+            del ctx
+            vm_ms = tvm["solve_h"] + tvm["gradients"] + tvm["fluxes"]
+            errs = None
+            if torch.equal(stv.id, stvm.id):
+                errs = {k: float((getattr(stv, k) - getattr(stvm, k)).abs().max() / getattr(stv, k).abs().max())
+                        for k in ("dm", "dp", "dE")}
+            out["mfv"]["mixed"] = {"value": cvm["pairs"] / (vm_ms * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
+                                   "ms_per_step": vm_ms, "flux_kernel_ms": kvm["hydro_fluxes"]["ms_avg"],
+                                   "normwise_error_vs_fp64": errs}
+            log(f"mfv mixed: flux kernel {kvm['hydro_fluxes']['ms_avg']:.3f} ms errs={errs}")
+            del stvm
         del stv
         torch.cuda.empty_cache()
 

@@ -57,8 +57,8 @@ typedef enum { MFM_FP64 = 0, MFM_MIXED = 1 } mfm_precision;
  * describes).  MFV (the other mesh-free Godunov form that section 2 lists;
  * section 4 on meshes that move): the same pass, but the full HLLC flux of
  * mass, momentum and energy crosses each face, which moves with the mean
- * particle velocity, so masses change at the rate dm.  MFV runs in MFM_FP64
- * only; mfm_step integrates both forms and the adjoints accept only MFM. */
+ * particle velocity, so masses change at the rate dm.  MFV runs in both
+ * precisions; mfm_step integrates both forms and the adjoints accept only MFM. */
 typedef enum { MFM_SCHEME_MFM = 0, MFM_SCHEME_MFV = 1 } mfm_scheme;
 
 typedef struct {
@@ -127,8 +127,8 @@ typedef struct {
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:
- * gamma > 1, n_ngb > 32/3, box > 0, beta > 0, scheme MFM, or MFV with
- * precision MFM_FP64.  Allocates scratch on the
+ * gamma > 1, n_ngb > 32/3, box > 0, beta > 0, scheme MFM or MFV.  Allocates
+ * scratch on the
  * current HIP device.  *out is NULL on failure. */
 mfm_status mfm_create(const mfm_params *params, int64_t capacity, mfm_ctx **out);
 
@@ -175,7 +175,8 @@ mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * MFM_SCHEME_MFV: the same faces, reconstruction, face frame and wave speeds,
  * then the full HLLC flux (F_L, F_L + S_L (U*_L - U_L), F_R + S_R (U*_R - U_R)
  * or F_R by the signs of S_L, S*, S_R) in the face frame, taken back to the lab
- * frame; dm (required) receives the mass rate; no P* clamp applies. */
+ * frame; dm (required) receives the mass rate; no P* clamp applies.  With
+ * MFM_MIXED this flux is formed in FP32 like the MFM one, dm summed in FP64. */
 mfm_status mfm_hydro_fluxes(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* solve_h + gradients + hydro_fluxes on already-ordered particles. */

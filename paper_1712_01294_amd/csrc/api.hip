@@ -212,7 +212,6 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
         if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return MFM_E_INVALID;
     if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return MFM_E_INVALID;
     if (p.scheme != MFM_SCHEME_MFM && p.scheme != MFM_SCHEME_MFV) return MFM_E_INVALID;
-    if (p.scheme == MFM_SCHEME_MFV && p.precision != MFM_FP64) return MFM_E_INVALID;
     if (capacity < 1 || capacity > (1ll << 30)) return MFM_E_INVALID;
     mfm_ctx* c = new mfm_ctx();
     c->p = p;

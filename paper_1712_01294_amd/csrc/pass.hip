@@ -1369,6 +1369,13 @@ void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const i
     fluxes_body<float, false>(a, ph, counts, list, rec, cnt);
 }
 
+// The finite-volume form on the FP32 records of the mixed form.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
+void k_fluxes_mfv_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
+                      const float* __restrict__ rec, Counters* cnt) {
+    fluxes_body<float, true>(a, ph, counts, list, rec, cnt);
+}
+
 // ------------------------------------------------------------------ launchers
 static int blocks_of(int n, int b) { return (n + b - 1) / b; }
 constexpr int kFallbackWaves = 1024;
@@ -1405,7 +1412,9 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
 
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed, int mfv,
                    const void* rec, Counters* cnt, hipStream_t s) {
-    if (mfv)
+    if (mfv && mixed)
+        k_fluxes_mfv_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+    else if (mfv)
         k_fluxes_mfv<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
     else if (mixed)
         k_fluxes_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);

@@ -55,7 +55,7 @@ def test_create_rejects_bad_parameters_before_touching_the_device(lib):
     good = mfm.Config(gamma=5 / 3, box=(1, 1, 1))
     h = C.c_void_p()
     for bad in (dict(gamma=1.0), dict(n_ngb=10.0), dict(box=(1, 0, 1)), dict(beta=0.0),
-                dict(precision=7), dict(scheme=7), dict(scheme=mfm.SCHEME_MFV, precision=mfm.MIXED)):
+                dict(precision=7), dict(scheme=7)):
         cfg = mfm.Config(**{**good.__dict__, **bad})
         assert lib.mfm_create(C.byref(cfg.c()), 1000, C.byref(h)) == -1
         assert not h.value

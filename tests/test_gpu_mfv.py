@@ -102,7 +102,7 @@ def test_mfv_turbulence_full_size_sampled():
 
 
 def test_mfv_argument_and_scheme_checks():
-    """MFV needs dm; the adjoints take MFM only; MFV needs the FP64 form."""
+    """MFV needs dm; the adjoints take MFM only."""
     import torch
 
     from paper_1712_01294_amd import mfm
@@ -123,8 +123,6 @@ def test_mfv_argument_and_scheme_checks():
     with pytest.raises(mfm.MFMError) as e:
         ctx.pass_adjoint(st, z, z[0])
     assert e.value.status == -1
-    with pytest.raises(mfm.MFMError):
-        mfm.Context(mfm.config_of(w, scheme=MFV, precision=mfm.MIXED), w.n)
     torch.cuda.synchronize()
 
 
@@ -230,4 +228,23 @@ def test_mfv_edge_sets(case):
     for k, e in errs.items():
         assert e <= TOL_FP64, (k, e)
     assert ctx.counters()["pairs"] == ref["pairs"]
+    _conserved(st)
+
+
+def test_mfv_mixed_precision_error_and_conservation():
+    """The mixed form of the MFV pass (FP32 records and pair fluxes, FP64 sums)
+    against the FP64 oracle: kernel lengths at the FP64 bar, dm, dp and dE
+    within 1e-5 normwise, and mass, momentum and energy conserved to FP64
+    round-off (each pair's FP32 flux is applied with both signs)."""
+    from paper_1712_01294_amd import mfm
+    w = W.jittered_sine(n_side=16, seed=W.SEED_BASE + 0)
+    ref = O.hydro_pass(_mfv(w), w.arrays())
+    ctx, st = run_pass(w, precision=mfm.MIXED, scheme=MFV)
+    ctx.check()
+    errs = compare_pass(st, ref, ("H", "nk", "V", "dm", "dp", "dE"))
+    _print("mfv mixed", errs)
+    for k in ("H", "nk", "V"):
+        assert errs[k] <= TOL_FP64, (k, errs[k])
+    for k in ("dm", "dp", "dE"):
+        assert errs[k] <= 1e-5, (k, errs[k])
     _conserved(st)
