@@ -85,7 +85,7 @@ typedef struct {
 typedef struct {
     int64_t n;
     double *x, *y, *z;       /* positions in [0, box)                               */
-    double *m;               /* masses (constant: zero mass flux)                   */
+    double *m;               /* masses (constant under MFM; MFV steps update them)  */
     double *vx, *vy, *vz;    /* velocities                                          */
     double *u;               /* specific internal energy                            */
     double *H;               /* kernel support radius: in guess (<=0: cold), out root [solve_h] */
@@ -100,7 +100,7 @@ typedef struct {
     double *dE;              /* total-energy rate dE/dt             [hydro_fluxes]   */
     double *vsig;            /* signal speed                        [hydro_fluxes]   */
     int64_t *id;             /* nullable: carried along every reordering            */
-    double *dm;              /* mass rate dm/dt, MFV only (nullable for MFM) [hydro_fluxes] */
+    double *dm;              /* mass rate dm/dt, MFV only (nullable, not written, under MFM) [hydro_fluxes] */
 } mfm_particles;
 
 typedef struct {
@@ -172,7 +172,7 @@ mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * - min(0, (v_i - v_j).(x_i - x_j)/r)].  Requires mfm_gradients.
  * MFM_MIXED: displacements from FP64 positions, then kernel weights, faces,
  * reconstruction and HLLC in FP32; the per-particle sums of dp and dE in FP64.
- * MFM_SCHEME_MFV: the same faces, reconstruction, face frame and wave speeds,
+ * MFM_SCHEME_MFV (reading R21): the same faces, reconstruction, face frame and wave speeds,
  * then the full HLLC flux (F_L, F_L + S_L (U*_L - U_L), F_R + S_R (U*_R - U_R)
  * or F_R by the signs of S_L, S*, S_R) in the face frame, taken back to the lab
  * frame; dm (required) receives the mass rate; no P* clamp applies.  With
