@@ -222,7 +222,10 @@ constexpr double kClassWindow = MFM_CLASS_WINDOW;
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+#ifndef MFM_SOLVE_WAVES
+#define MFM_SOLVE_WAVES 5
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_SOLVE_WAVES))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                   const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
@@ -420,7 +423,13 @@ constexpr int kWaveBlocks = MFM_WAVE_BLOCKS;   // waves of the list solver, stri
 #endif
 constexpr double kWaveScanScale = MFM_WAVE_SCAN_SCALE;
 
-__global__ __launch_bounds__(64) void k_solve_h_wave(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+// Five waves per SIMD: the list solver fits in 96 registers without spills,
+// and the fifth wave hides more of its scans' load latency than four.
+#ifndef MFM_WAVESOLVE_WAVES
+#define MFM_WAVESOLVE_WAVES 5
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MFM_WAVESOLVE_WAVES))) void k_solve_h_wave(
+                                                      PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                       const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                       const int* __restrict__ fb_list,
                                                       const unsigned long long* __restrict__ fb_count,
