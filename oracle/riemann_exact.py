@@ -1,6 +1,6 @@
 """Exact solution of the 1D Riemann problem for an ideal gamma-law gas.
 
-TEST INFRASTRUCTURE ONLY (used to judge the planar shock tube).
+TEST INFRASTRUCTURE ONLY (used to check the planar shock tube).
 
 The release paper's method is a Godunov scheme (abstract: "mesh-free
 finite-volume Godunov methods"); the reference solution for its shock tube is
