@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (used to check the planar shock tube).
 
-The release paper's method is a Godunov scheme (abstract: "mesh-free
-finite-volume Godunov methods"); the reference solution for its shock tube is
+The release paper's method is a mesh-free finite-volume Godunov scheme (its
+abstract names the family); the reference solution for its shock tube is
 the classical exact Riemann solution: a pressure function per side (shock
 branch from the Rankine-Hugoniot conditions, rarefaction branch from the
 isentropic Riemann invariants), whose root is the star pressure, then
