@@ -344,6 +344,11 @@ def main():
         out["mixed"] = {"value": cmx["pairs"] / (mx_ms * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
                         "ms_per_step": mx_ms, "stage_ms": tmx,
                         "kernel_ms": {k: v["ms_avg"] for k, v in kmx.items()},
+                        # the pair arithmetic of the mixed flux kernel is FP32: its flops
+                        # against the FP32 vector peak
+                        "flux_GFLOPps": algorithmic("hydro_fluxes", n, G, F, P)[1] / (kmx["hydro_fluxes"]["ms_avg"] * 1e-3) / 1e9,
+                        "flux_frac_fp32": algorithmic("hydro_fluxes", n, G, F, P)[1]
+                        / (kmx["hydro_fluxes"]["ms_avg"] * 1e-3) / PEAK_FP32_VALU,
                         "speedup_vs_fp64": pass_ms / mx_ms,
                         "normwise_error_vs_fp64": errs,
                         "momentum_sum_mixed": [float(stmx.dp[c].sum()) for c in range(3)],
