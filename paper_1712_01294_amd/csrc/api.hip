@@ -354,7 +354,7 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     launch_tables(n, c->keys, c->td, c->tab, s);
     launch_pos4(n, p->x, p->y, p->z, c->pos, s);
     c->n_tree = n;
-    c->have_h = c->have_grad = 0;
+    c->have_h = c->have_grad = c->have_flux = 0;
     c->last = s;
     return launched(c, "build_neighbours");
 }
@@ -373,7 +373,7 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     launch_solve_h(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->rl, c->list, c->gcount, c->counts,
                    c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, ev.first, ev.second, s);
     c->have_h = 1;
-    c->have_grad = 0;
+    c->have_grad = c->have_flux = 0;
     c->last = s;
     return launched(c, "solve_h");
 }
@@ -384,6 +384,7 @@ static mfm_status do_gradients(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
     if (!c->have_h || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_solve_h must run first");
     PassArrays a = arrays_of(p);
     c->rec_mixed = c->p.precision == MFM_MIXED;
+    c->have_flux = 0;
     const auto ev = clock_take(c, MFM_KERNEL_GRADIENTS);
     launch_gradients(a, c->ph, c->gcount, c->counts, c->list, c->tails, c->rec_mixed, c->prim, c->rec, c->cnt, ev.first,
                      ev.second, s);
@@ -631,7 +632,7 @@ extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p,
     if (!adj_dp || !adj_dE || !adj_x || !adj_v || !adj_u) return fail(c, MFM_E_INVALID, "null adjoint array");
     if (!p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
         return fail(c, MFM_E_INVALID, "the pass adjoint needs the forward outputs nk, V, B, rho, P, grad");
-    if (!c->have_flux || c->n_tree != p->n)
+    if (!c->have_grad || !c->have_flux || c->n_tree != p->n)
         return fail(c, MFM_E_STATE, "the pass adjoint needs the pass of this state on this context");
     hipSetDevice(c->device);
     if ((st = ensure_adj(c))) return st;

@@ -174,6 +174,25 @@ def test_error_paths_forced_from_host(sine16):
     with pytest.raises(mfm.MFMError) as e:
         ctx.gradients(st)
     assert e.value.status == -8
+    # the pass adjoint needs a complete pass of the current neighbour structure:
+    # after a rebuild, or after a lone kernel-length solve, it is refused
+    f = dict(dtype=torch.float64, device="cuda")
+    ap, ae = torch.zeros(3, w.n, **f), torch.zeros(w.n, **f)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    ctx.pass_adjoint(st, ap, ae)
+    ctx.build_neighbours(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.pass_adjoint(st, ap, ae)
+    assert e.value.status == -8
+    ctx.solve_h(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.pass_adjoint(st, ap, ae)
+    assert e.value.status == -8
+    ctx.gradients(st)
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.pass_adjoint(st, ap, ae)
+    assert e.value.status == -8
     # neighbour-list overflow reported as a capacity error
     ctx = mfm.Context(mfm.config_of(w, max_ngb=8), w.n)
     ctx.build_neighbours(st)

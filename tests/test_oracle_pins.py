@@ -219,6 +219,75 @@ def test_limiter_keeps_linear_fields_on_interior_lattice(oracle_lib):
         assert np.abs(lim[f][:, inner] - g[f][:, None]).max() < 1e-11 * np.abs(g[f]).max()
 
 
+@pytest.mark.parametrize("beta", [1.0, 0.5])
+def test_limiter_active_branch_closed_form(oracle_lib, beta):
+    """R10 with the limiter active (alpha < 1), by construction.  Open 7^3 unit
+    lattice; the nine sites of the +x face of the centre's 3x3x3 block are moved
+    from dx = 1 to dx = 0.8.  The centre's kernel length then lies between the
+    far corner distance sqrt(3) and the second shell at 2, so its gather set is
+    the 27-site block and half its largest distance is sqrt(3)/2.  For the
+    linear fields vx = g x and vy = -g x the gradient is exactly (+-g, 0, 0)
+    (linear exactness), the up and down extents are 0.8 g and 1.0 g in one
+    order for vx and the other for vy, so both limit to
+    alpha = beta * 0.8 / (sqrt(3)/2); vz = g y sees extents 1 and 1 and keeps
+    alpha = min(1, beta / (sqrt(3)/2)).  A dropped min, a swapped extent, the
+    full instead of half distance or a missing beta all move one of these."""
+    nside = 7
+    x, y, z = W.lattice_sites(nside, nside, nside, 1.0)
+    n = x.size
+    c = int(np.flatnonzero((x == 3.5) & (y == 3.5) & (z == 3.5))[0])
+    face = (x == 4.5) & (np.abs(y - 3.5) <= 1) & (np.abs(z - 3.5) <= 1)
+    assert face.sum() == 9
+    x = x.copy()
+    x[face] -= 0.2
+    gs = 0.37
+    w = W.Workload(name="ramp", x=x, y=y, z=z, m=np.ones(n), vx=gs * x, vy=-gs * x, vz=gs * y,
+                   u=np.ones(n), gamma=5 / 3, box=(7.0, 7.0, 7.0), periodic=(0, 0, 0))
+    s = O.Setup.of(w, cell=0.0, beta=beta)
+    H, nk, V, _ = O.solve_h(s, w.x, w.y, w.z)
+    assert math.sqrt(3.0) < H[c] < 2.0
+    gr = O.gradients(s, w.arrays(), H, nk, V)
+    raw = gr["grad_raw"].reshape(5, 3, n)[:, :, c]
+    for f, want in ((1, (gs, 0, 0)), (2, (-gs, 0, 0)), (3, (0, gs, 0))):
+        assert np.abs(raw[f] - np.array(want)).max() <= 1e-13
+    half_span = math.sqrt(3.0) / 2.0
+    a_x = beta * 0.8 / half_span
+    a_z = min(1.0, beta * 1.0 / half_span)
+    assert a_x < 1.0
+    alpha = gr["alpha"][:, c]
+    assert alpha[1] == pytest.approx(a_x, rel=1e-13)
+    assert alpha[2] == pytest.approx(a_x, rel=1e-13)
+    assert alpha[3] == pytest.approx(a_z, rel=1e-13)
+    lim = gr["grad"].reshape(5, 3, n)[:, :, c]
+    assert lim[1][0] == pytest.approx(a_x * gs, rel=1e-13)
+    assert lim[2][0] == pytest.approx(-a_x * gs, rel=1e-13)
+
+
+def test_vsig_two_particles_closed_form(oracle_lib):
+    """R18's signal speed for two particles with hand-set states (identity B,
+    zero gradients): c_a = 1 and c_b = sqrt(3) by construction; approaching
+    along the separation at relative speed 0.9 gives c_a + c_b + 0.9 on both,
+    receding gives c_a + c_b; the tangential relative motion (1.4, -0.3) never
+    enters.  A sign error in the approach term swaps the two cases."""
+    g5 = 5.0 / 3.0
+    r = 0.1
+    s = O.Setup(gamma=g5, n_ngb=32.0, box=(1.0, 1.0, 1.0), periodic=(0, 0, 0))
+    base = dict(x=np.array([0.3, 0.3 + r]), y=np.array([0.5, 0.5]), z=np.array([0.5, 0.5]))
+    H = np.array([0.3, 0.3])
+    V = np.array([1.0, 1.0])
+    g = dict(B=np.array([[1.0, 1.0], [0, 0], [0, 0], [1.0, 1.0], [0, 0], [1.0, 1.0]]),
+             rho=np.array([1.0, 0.5]), P=np.array([0.6, 0.9]), grad=np.zeros((15, 2)))
+    ca, cb = 1.0, math.sqrt(3.0)
+    assert math.sqrt(g5 * 0.6 / 1.0) == pytest.approx(ca, rel=1e-15)
+    assert math.sqrt(g5 * 0.9 / 0.5) == pytest.approx(cb, rel=1e-15)
+    for vxa, vxb, extra in ((0.7, -0.2, 0.9), (-0.2, 0.7, 0.0)):
+        st = dict(base, vx=np.array([vxa, vxb]), vy=np.array([0.4, -1.0]), vz=np.array([0.0, 0.3]))
+        out = O.fluxes(s, st, H, V, g)
+        assert out["pair_entries"] == 2
+        assert out["vsig"][0] == pytest.approx(ca + cb + extra, rel=1e-15)
+        assert out["vsig"][1] == pytest.approx(ca + cb + extra, rel=1e-15)
+
+
 # ------------------------------------------------------------ R14 HLLC
 def test_hllc_identical_states_exact(oracle_lib):
     for (r, u, p) in [(1.0, 0.0, 1.0), (0.3, 1.7, 2.5), (2.0, -0.4, 0.01)]:
