@@ -312,6 +312,11 @@ int or_solve_h(const or_params *p, int64_t n, const double *x, const double *y,
     int rc = grid_build(&g, p, n, x, y, z);
     double vol = p->box[0] * p->box[1] * p->box[2];
     double cold = cbrt(3.0 * p->n_ngb * vol / (4.0 * M_PI * (double)n));
+    /* the root must stay below half of every periodic side (R2); the bracket
+     * may approach that limit but never reach it */
+    double half = INFINITY;
+    for (int a = 0; a < 3; a++)
+        if (p->periodic[a] && 0.5 * p->box[a] < half) half = 0.5 * p->box[a];
     for (int64_t i = 0; i < n && !rc; i++) {
         if (mask && !mask[i]) continue;
         double hi = H[i] > 0.0 ? H[i] : cold;
@@ -323,6 +328,13 @@ int or_solve_h(const or_params *p, int64_t n, const double *x, const double *y,
             if (h_residual(&L, hi, p->n_ngb) >= 0.0) break;
             lo = hi;
             hi *= 1.5;
+            if (!(hi < half)) {
+                /* halve the remaining distance to the limit instead; once that
+                 * no longer moves, no admissible radius reaches the root */
+                double h2 = 0.5 * (lo + half);
+                if (!(h2 > lo && h2 < half)) { rc = OR_E_MINIMAGE; break; }
+                hi = h2;
+            }
         }
         if (rc) break;
         int64_t it = 0;

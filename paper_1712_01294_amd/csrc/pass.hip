@@ -1166,10 +1166,23 @@ __device__ __forceinline__ void mfv_flux(const T qL[5], const T qR[5], const T w
     if (star) {
         const T f = rho * (S - u) / (S - Ss);
         const T du = Ss - u;
-        F[0] += S * (f - rho);
+        if (sizeof(T) == 8) {
+            F[0] += S * (f - rho);
 #pragma unroll
-        for (int c = 0; c < 3; c++) F[1 + c] += S * (f * (vp[c] + du * nh[c]) - rho * vp[c]);
-        F[4] += S * (f * (E / rho + du * (Ss + P / (rho * (S - u)))) - E);
+            for (int c = 0; c < 3; c++) F[1 + c] += S * (f * (vp[c] + du * nh[c]) - rho * vp[c]);
+            F[4] += S * (f * (E / rho + du * (Ss + P / (rho * (S - u)))) - E);
+        } else {
+            // FP32: the same flux in the form S* U*_K + P*_K (0, n, S*), with the
+            // side's star pressure P*_K = P + rho (S - u)(S* - u).  F_K +
+            // S_K (U*_K - U_K) equals it identically (the star state satisfies the
+            // jump conditions across S_K), but subtracts terms much larger than a
+            // slow face's mass flux; this form has no such cancellation.
+            const T Pst = P + rho * (S - u) * du;
+            F[0] = f * Ss;
+#pragma unroll
+            for (int c = 0; c < 3; c++) F[1 + c] = f * (vp[c] + du * nh[c]) * Ss + Pst * nh[c];
+            F[4] = (f * (E / rho + du * (Ss + P / (rho * (S - u)))) + Pst) * Ss;
+        }
     }
     const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     out.Fm = F[0] * Amag;

@@ -12,7 +12,7 @@ full-physics cosmological runs on CPU clusters, with no public dataset; these
 synthetic sets stand in for the five hydro-pass workloads:
 
 * ``jittered_sine``   16^3 jittered lattice, rho = 1 + 0.1 sin(2 pi x), P ~ 1
-* ``shock_tube``      planar Sod-type tube, density ratio 8 by spacing ratio 2
+* ``shock_tube``      planar Sod-type tube, density ratio 8 by spacing ratio 2, jittered
 * ``turbulence``      128^3 jittered lattice, Gaussian k^-4 velocity, Mach 2
 * ``clustered``       256^3 particles drawn from a log-normal density field
 * ``adjoint_box``     the ``jittered_sine`` recipe at 64^3
@@ -120,14 +120,21 @@ def adjoint_box(n_side: int = 64, seed: int = SEED_BASE + 4, steps: int = 10,
 
 
 def shock_tube(n_yz: int = 32, l_yz: float = 0.125, seed: int = SEED_BASE + 1,
-               gamma: float = 5.0 / 3.0, steps: int = 50, cfl: float = 0.25) -> Workload:
+               gamma: float = 5.0 / 3.0, steps: int = 50, cfl: float = 0.25,
+               jitter: float = 0.2) -> Workload:
     """Planar shock tube in [0,2] x [0,l_yz]^2, periodic on every axis.
 
     Left half (x < 1): lattice spacing dL = l_yz / n_yz, rho = 1, P = 1.
     Right half: spacing 2 dL, rho = 1/8, P = 0.1.  All particles have mass dL^3,
-    so the density ratio comes from the spacing ratio alone.  No jitter, v = 0.
-    The x axis is periodic too, so a mirrored interface sits at x = 0 == 2; the
-    profile is compared on 0.5 <= x <= 1.5 only."""
+    so the density ratio comes from the spacing ratio alone.  Each site moves
+    by U(-jitter, jitter) of its own block's spacing per axis (no site crosses
+    x = 1 for jitter < 1/2); the state follows the block.  v = 0.  With
+    jitter = 0 the two lattices are perfect: their planar contact layer is then
+    a symmetric state that any asymmetric rounding perturbs, and that
+    perturbation grows by about 3x per step in the layer.  The x axis is
+    periodic too, so a mirrored interface sits at x = 0 == 2; the profile is
+    compared on 0.5 <= x <= 1.5 only."""
+    rng = _rng(seed)
     dl = l_yz / n_yz
     nxl = int(round(1.0 / dl))
     xl, yl, zl = lattice_sites(nxl, n_yz, n_yz, dl)
@@ -137,17 +144,24 @@ def shock_tube(n_yz: int = 32, l_yz: float = 0.125, seed: int = SEED_BASE + 1,
     x = np.concatenate([xl, xr])
     y = np.concatenate([yl, yr])
     z = np.concatenate([zl, zr])
+    left = np.arange(x.size) < xl.size
+    if jitter > 0.0:
+        sp = np.where(left, dl, dr)
+        j = rng.uniform(-jitter, jitter, size=(3, x.size)) * sp
+        x = _wrap(x + j[0], 2.0)
+        y = _wrap(y + j[1], l_yz)
+        z = _wrap(z + j[2], l_yz)
     m = np.full(x.size, dl ** 3)
-    rho = np.where(x < 1.0, 1.0, 0.125)
-    P = np.where(x < 1.0, 1.0, 0.1)
+    rho = np.where(left, 1.0, 0.125)
+    P = np.where(left, 1.0, 0.1)
     u = P / ((gamma - 1.0) * rho)
     zero = np.zeros(x.size)
     # shuffle the storage order so that neighbour building starts from an unsorted set
-    perm = _rng(seed).permutation(x.size)
+    perm = rng.permutation(x.size)
     return Workload(name="shock_tube", x=x[perm], y=y[perm], z=z[perm], m=m[perm],
                     vx=zero.copy(), vy=zero.copy(), vz=zero.copy(), u=u[perm],
                     gamma=gamma, box=(2.0, l_yz, l_yz), cfl=cfl, steps=steps,
-                    extra={"spacing_left": dl, "spacing_right": dr,
+                    extra={"spacing_left": dl, "spacing_right": dr, "jitter": jitter,
                            "left": (1.0, 0.0, 1.0), "right": (0.125, 0.0, 0.1)})
 
 

@@ -411,14 +411,17 @@ def test_planar_set_flags_singular_gradient_matrix():
     assert e.value.status in (-4, -7)
 
 
-@pytest.mark.parametrize("scheme", ["mfm", "mfv"])
-def test_clustered_full_size_against_stored_oracle_samples(scheme):
+@pytest.mark.parametrize("scheme,precision", [("mfm", 0), ("mfv", 0), ("mfm", 1), ("mfv", 1)],
+                         ids=["mfm-fp64", "mfv-fp64", "mfm-mixed", "mfv-mixed"])
+def test_clustered_full_size_against_stored_oracle_samples(scheme, precision):
     """The benchmark's own set and launch configuration (16,777,216 particles,
     cold start) against oracle outputs at eight particles from the middle
     eighth of the density ranks.  Their dependency closures take the oracle
     minutes, so tests/golden/make_clustered_samples.py (which calls only the
     oracle) computed them once and stored them.  H, n and V are compared
-    element by element; every other field normwise over the targets."""
+    element by element; every other field normwise over the targets.  The
+    mixed form keeps the kernel-length solve, density and pressure in FP64
+    (held at the FP64 bar) and must bring the rest within 1e-5."""
     import json
     import os
 
@@ -429,7 +432,8 @@ def test_clustered_full_size_against_stored_oracle_samples(scheme):
     assert gold["n"] == w.n
     tg = np.asarray(gold["targets"])
     ref = {k: np.asarray(v) for k, v in gold[scheme].items()}
-    ctx, st = run_pass(w, alpha=False, scheme=mfm.SCHEME_MFV if scheme == "mfv" else mfm.SCHEME_MFM)
+    ctx, st = run_pass(w, alpha=False, precision=precision,
+                       scheme=mfm.SCHEME_MFV if scheme == "mfv" else mfm.SCHEME_MFM)
     ctx.check(allow_illcond=True)
     errs = {}
     for k in ("H", "nk", "V"):
@@ -437,6 +441,7 @@ def test_clustered_full_size_against_stored_oracle_samples(scheme):
     fields = ("rho", "P", "B", "grad", "dp", "dE", "vsig") + (("dm",) if scheme == "mfv" else ())
     for k in fields:
         errs[k] = nerr(in_input_order(st, k)[..., tg], ref[k])
-    _print(f"clustered16M {scheme} cond_max={ref['cond'].max():.1e}", errs)
+    _print(f"clustered16M {scheme} precision={precision} cond_max={ref['cond'].max():.1e}", errs)
+    exact = ("H", "nk", "V", "rho", "P")
     for k, e in errs.items():
-        assert e <= TOL_FP64, (k, e)
+        assert e <= (TOL_FP64 if (precision == 0 or k in exact) else TOL_MIXED), (k, e)

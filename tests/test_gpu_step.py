@@ -40,14 +40,19 @@ def _periodic_err(a, b, L):
     return float(np.abs(d).max())
 
 
-def test_step_matches_oracle_small_tube():
-    """10 CFL steps of a 10,368-particle shock tube: positions, velocities and
-    energies within 1e-10 normwise of the oracle's step."""
-    w = W.shock_tube(n_yz=12, l_yz=12 / 64)
+@pytest.mark.parametrize("jitter,steps", [(0.2, 50), (0.0, 10)])
+def test_step_matches_oracle_small_tube(jitter, steps):
+    """CFL steps of a 10,368-particle shock tube: positions, velocities and
+    energies within 1e-10 normwise of the oracle's step.  The jittered tube is
+    held for all 50 steps of the configuration.  The perfect-lattice tube only
+    for 10: its contact layer amplifies any asymmetric rounding by about 3x per
+    step (pinned on the oracle alone in test_oracle_riemann), so past ~15 steps
+    two correct implementations part by more than the bar."""
+    w = W.shock_tube(n_yz=12, l_yz=12 / 64, jitter=jitter)
     ref = O.Stepper(w)
     ref.start()
-    rdt = [ref.step() for _ in range(10)]
-    ctx, st, gdt = _gpu_run(w, 10)
+    rdt = [ref.step() for _ in range(steps)]
+    ctx, st, gdt = _gpu_run(w, steps)
     print("dt gpu", gdt[-1], "oracle", rdt[-1], flush=True)
     assert np.allclose(gdt, rdt, rtol=1e-12, atol=0)
     for k, L in (("x", w.box[0]), ("y", w.box[1]), ("z", w.box[2])):
@@ -59,6 +64,38 @@ def test_step_matches_oracle_small_tube():
     assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
     assert nerr(in_input_order(st, "dp"), ref.last["dp"]) <= 1e-10
     assert nerr(in_input_order(st, "dE"), ref.last["dE"]) <= 1e-10
+
+
+def test_mixed_step_matches_oracle_small_tube():
+    """The mixed form's step (FP32 pair fluxes, FP64 state and sums) against the
+    FP64 oracle's step over 10 CFL steps of the jittered small tube.  Each
+    pass's flux error is within eps_F = 1e-5 of max|flux| (the mixed pass bar);
+    a kick moves v by dt dp/m, and dt max|dp/m| stays below the largest
+    velocity the run reaches, so after k steps the velocity error is at most
+    k eps_F of max|v| when the map does not amplify differences (the jittered
+    tube does not: test_oracle_riemann).  Bar: k eps_F = 1e-4 on v, u, dp
+    and dE normwise, and positions within t k eps_F max|v|."""
+    from paper_1712_01294_amd import mfm
+    k = 10
+    w = W.shock_tube(n_yz=12, l_yz=12 / 64)
+    ref = O.Stepper(w)
+    ref.start()
+    rdt = [ref.step() for _ in range(k)]
+    ctx, st, gdt = _gpu_run(w, k, precision=mfm.MIXED)
+    bar = k * 1e-5
+    vmax = float(np.abs(ref.st["vx"]).max())
+    errs = {q: nerr(in_input_order(st, q), ref.st[q]) for q in ("vx", "u")}
+    errs.update({q: nerr(in_input_order(st, q), ref.last[q]) for q in ("dp", "dE")})
+    errs["v_transverse"] = max(float(np.abs(in_input_order(st, q) - ref.st[q]).max()) for q in ("vy", "vz")) / vmax
+    errs["x"] = max(_periodic_err(in_input_order(st, q), ref.st[q], L)
+                    for q, L in (("x", w.box[0]), ("y", w.box[1]), ("z", w.box[2]))) / (sum(rdt) * vmax)
+    errs["dt"] = float(np.max(np.abs(np.array(gdt) / np.array(rdt) - 1.0)))
+    print("mixed step vs oracle", " ".join(f"{q}={e:.2e}" for q, e in errs.items()), flush=True)
+    for q, e in errs.items():
+        assert e <= bar, (q, e)
+    m = st.m.cpu().numpy()
+    vx = st.vx.cpu().numpy()
+    assert abs(float((m * vx).sum())) <= 1e-13 * float(np.abs(m * vx).sum())
 
 
 def test_fixed_dt_steps_conserve_on_jittered_box():
@@ -84,20 +121,19 @@ def test_fixed_dt_steps_conserve_on_jittered_box():
         assert nerr(in_input_order(st, k), ref.st[k]) <= 1e-11, k
 
 
-def test_shock_tube_full_size_against_exact_riemann():
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_shock_tube_full_size_against_exact_riemann(precision):
     """The 294,912-particle tube (left 256 x 32 x 32 at spacing 1/256, right at
-    1/128), 50 CFL steps: a convergence check against the exact Riemann solution
-    (reported, not parity).  At t = 0.036 the post-shock gas between the contact
-    and the shock spans about eight lattice planes, and the run is sensitive to
-    round-off there: a 1e-14 perturbation of the initial velocities moves the
-    mean over the middle 40% of that region between v = 0.836 and 0.886 and
-    between P = 0.294 and 0.321 (measured; exact 0.841 and 0.294).  The bands
-    are therefore 8% on v and rho and 12% on P.  The binned velocity profile on
-    0.9 <= x <= 1.15 must stay within a mean absolute error of 0.07 (measured
-    0.028-0.045).  The shock sits within two right-hand spacings of the exact
-    one, and momentum along the tube stays at round-off."""
+    1/128, both jittered by +-0.2 spacing), 50 CFL steps, in FP64 and in the
+    mixed form: a convergence check against the exact Riemann solution
+    (reported, not parity).  At t ~ 0.036 the post-shock gas between the
+    contact and the shock spans about eight lattice planes.  The means over the
+    middle 40% of that region must match the exact v and rho within 5% and P
+    within 8%; the binned velocity profile on 0.9 <= x <= 1.15 within a mean
+    absolute error of 0.07; the shock within two right-hand spacings of the
+    exact one; momentum along the tube at round-off."""
     w = W.shock_tube()
-    ctx, st, dts = _gpu_run(w, 50)
+    ctx, st, dts = _gpu_run(w, 50, precision=precision)
     t = float(np.sum(dts))
     gam = w.gamma
     p, u = R.star_state(LEFT, RIGHT, gam)
@@ -116,12 +152,12 @@ def test_shock_tube_full_size_against_exact_riemann():
     b = np.digitize(x, bins) - 1
     prof = np.array([vx[b == k].mean() for k in range(len(xc))])
     l1 = float(np.mean(np.abs(prof - exact_v)))
-    print(f"t={t:.5f} n_sel={sel.sum()} v={vx[sel].mean():.4f} (exact {u:.4f}) "
+    print(f"precision={precision} t={t:.5f} n_sel={sel.sum()} v={vx[sel].mean():.4f} (exact {u:.4f}) "
           f"P={P[sel].mean():.4f} ({p:.4f}) rho={rho[sel].mean():.4f} ({rr:.4f}) L1(v)={l1:.4f}", flush=True)
     assert sel.sum() > 300
-    assert vx[sel].mean() == pytest.approx(u, rel=0.08)
-    assert P[sel].mean() == pytest.approx(p, rel=0.12)
-    assert rho[sel].mean() == pytest.approx(rr, rel=0.08)
+    assert vx[sel].mean() == pytest.approx(u, rel=0.05)
+    assert P[sel].mean() == pytest.approx(p, rel=0.08)
+    assert rho[sel].mean() == pytest.approx(rr, rel=0.05)
     assert l1 <= 0.07
     order = np.argsort(x)
     xs, rs = x[order], rho[order]
