@@ -258,6 +258,31 @@ typedef enum { MFM_KERNEL_SOLVE_H = 0, MFM_KERNEL_GRADIENTS = 1, MFM_KERNEL_FLUX
 mfm_status mfm_set_kernel_timing(mfm_ctx *ctx, int enable);
 mfm_status mfm_kernel_time(mfm_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * pass of mfm_build_neighbours + mfm_hydro_pass without a context.
+ *  - At most 8192 particles (p->n > 8192: MFM_E_CAPACITY, nothing launched),
+ *    params->max_ngb <= 256 (0: 256) and params->tree_levels <= 6 (0: 6);
+ *    larger values, invalid params or a missing output array: MFM_E_INVALID.
+ *  - All scratch (keys, cell tables, flux lists, records, counters: about
+ *    27 MB) lives in one device array inside the library, which each GPU the
+ *    library runs on holds from load until the process ends.  The call makes
+ *    no hipMalloc, hipFree or other allocating call on any path; counters are
+ *    cleared by a kernel, not a memset.
+ *  - Every call on one GPU shares that GPU's array and leaves its contents
+ *    for the next call: calls that overlap on one GPU (from several streams or
+ *    threads) race.
+ *  - Arrays, ordering and outputs are those of the two calls it replaces: p's
+ *    arrays are REORDERED IN PLACE into Morton order (id carried), then H, nk,
+ *    V, B, rho, P, grad, dp, dE, vsig (and dm under MFV) are written.
+ *  - counters (host, nullable): when given, the call synchronises the stream,
+ *    fills it, and returns the status mfm_check would (MFM_E_NOCONV, ...); when
+ *    NULL it only queues the work and never synchronises (graph capture).
+ */
+mfm_status mfm_hydro_pass_noalloc(const mfm_params *params, mfm_particles *p, mfm_counters *counters,
+                                  void *stream);
+
 const char *mfm_status_str(mfm_status s);
 const char *mfm_last_error(const mfm_ctx *ctx);
 

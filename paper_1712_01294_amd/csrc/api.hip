@@ -4,7 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mfm.h"
@@ -52,7 +52,7 @@ struct mfm_ctx {
     hipStream_t last = nullptr;
     int timing = 0;
     KernelClock clk[3];                   // indexed by mfm_kernel
-    std::string err;
+    char err[256] = {0};                  // last error message (a fixed buffer: no allocation on any path)
 };
 
 static void clock_drain(KernelClock& k) {
@@ -91,14 +91,15 @@ static void clock_reset(mfm_ctx* c) {
     }
 }
 
-static mfm_status fail(mfm_ctx* c, mfm_status s, const std::string& m) {
-    if (c) c->err = m;
+static mfm_status fail(mfm_ctx* c, mfm_status s, const char* m) {
+    if (c) snprintf(c->err, sizeof c->err, "%s", m);
     return s;
 }
 
 static mfm_status hip_check(mfm_ctx* c, hipError_t e, const char* what) {
-    if (e != hipSuccess) return fail(c, MFM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-    return MFM_OK;
+    if (e == hipSuccess) return MFM_OK;
+    if (c) snprintf(c->err, sizeof c->err, "%s: %s", what, hipGetErrorString(e));
+    return MFM_E_HIP;
 }
 
 static mfm_status launched(mfm_ctx* c, const char* what) {
@@ -163,6 +164,32 @@ static void setup_tree(mfm_ctx* c) {
     c->tab_len = off;
 }
 
+// mfm_create's parameter checks (see include/mfm.h)
+static bool params_valid(const mfm_params& p) {
+    if (!(p.gamma > 1.0) || !(p.n_ngb > 32.0 / 3.0) || !(p.beta > 0.0) || !(p.cond_max > 0.0)) return false;
+    for (int d = 0; d < 3; d++)
+        if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return false;
+    if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return false;
+    if (p.scheme != MFM_SCHEME_MFM && p.scheme != MFM_SCHEME_MFV) return false;
+    return true;
+}
+
+// parameters, device-side physics and the cell-table layout of a context
+static void init_params(mfm_ctx* c, const mfm_params& p) {
+    c->p = p;
+    c->ph.gamma = p.gamma;
+    c->ph.n_ngb = p.n_ngb;
+    c->ph.beta = p.beta;
+    c->ph.cond_max = p.cond_max;
+    for (int d = 0; d < 3; d++) {
+        c->ph.box[d] = p.box[d];
+        c->ph.periodic[d] = p.periodic[d];
+    }
+    c->ph.h_maxit = p.h_maxit > 0 ? p.h_maxit : 64;
+    c->ph.max_ngb = p.max_ngb > 0 ? p.max_ngb : 256;
+    setup_tree(c);
+}
+
 extern "C" {
 
 const char* mfm_status_str(mfm_status s) {
@@ -180,14 +207,14 @@ const char* mfm_status_str(mfm_status s) {
     return "unknown status";
 }
 
-const char* mfm_last_error(const mfm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* mfm_last_error(const mfm_ctx* c) { return c ? c->err : "null context"; }
 
 int32_t mfm_max_ngb(const mfm_ctx* c) { return c ? c->ph.max_ngb : 0; }
 
 void mfm_destroy(mfm_ctx* c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     for (KernelClock& k : c->clk) {
         clock_drain(k);
         for (auto& e : k.spare) {
@@ -205,29 +232,12 @@ void mfm_destroy(mfm_ctx* c) {
 mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out) {
     if (!out) return MFM_E_INVALID;
     *out = nullptr;
-    if (!params) return MFM_E_INVALID;
-    const mfm_params& p = *params;
-    if (!(p.gamma > 1.0) || !(p.n_ngb > 32.0 / 3.0) || !(p.beta > 0.0) || !(p.cond_max > 0.0)) return MFM_E_INVALID;
-    for (int d = 0; d < 3; d++)
-        if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return MFM_E_INVALID;
-    if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return MFM_E_INVALID;
-    if (p.scheme != MFM_SCHEME_MFM && p.scheme != MFM_SCHEME_MFV) return MFM_E_INVALID;
+    if (!params || !params_valid(*params)) return MFM_E_INVALID;
     if (capacity < 1 || capacity > (1ll << 30)) return MFM_E_INVALID;
     mfm_ctx* c = new mfm_ctx();
-    c->p = p;
     c->cap = capacity;
-    hipGetDevice(&c->device);
-    c->ph.gamma = p.gamma;
-    c->ph.n_ngb = p.n_ngb;
-    c->ph.beta = p.beta;
-    c->ph.cond_max = p.cond_max;
-    for (int d = 0; d < 3; d++) {
-        c->ph.box[d] = p.box[d];
-        c->ph.periodic[d] = p.periodic[d];
-    }
-    c->ph.h_maxit = p.h_maxit > 0 ? p.h_maxit : 64;
-    c->ph.max_ngb = p.max_ngb > 0 ? p.max_ngb : 256;
-    setup_tree(c);
+    (void)hipGetDevice(&c->device);
+    init_params(c, *params);
     const long long n = capacity;
     const int nblocks = (int)((n + 2047) / 2048);
     const long long hist_len = 256ll * nblocks;
@@ -259,12 +269,12 @@ mfm_status mfm_create(const mfm_params* params, int64_t capacity, mfm_ctx** out)
     alloc((void**)&c->vp, sizeof(double) * 3 * n, "predicted v");
     alloc((void**)&c->up, sizeof(double) * n, "predicted u");
     alloc((void**)&c->Ehalf, sizeof(double) * n, "half-step energy");
-    if (p.scheme == MFM_SCHEME_MFV) alloc((void**)&c->mp, sizeof(double) * n, "predicted masses");
+    if (params->scheme == MFM_SCHEME_MFV) alloc((void**)&c->mp, sizeof(double) * n, "predicted masses");
     alloc((void**)&c->dt_part, sizeof(double) * 1024, "dt partials");
     alloc((void**)&c->dt_out, sizeof(double) * 2, "dt");
     alloc((void**)&c->cnt, (size_t)kCounterCopies * kCounterStride, "counters");
     if (st != MFM_OK) {
-        fprintf(stderr, "mfm_create: %s\n", c->err.c_str());
+        fprintf(stderr, "mfm_create: %s\n", c->err);
         mfm_destroy(c);
         return st;
     }
@@ -313,7 +323,7 @@ static PassArrays arrays_of(const mfm_particles* p) {
 // order by key and reorder `extra` arrays too (step scratch)
 static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* const* extra, int nextra) {
     const int n = (int)p->n;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     launch_keys(n, p->x, p->y, p->z, c->td, c->keys, c->idx, s);
     radix_sort(n, c->td.ktot, c->keys, c->idx, c->ktmp, c->vtmp, c->hist, c->scan_tmp, s);
     GatherBatch gb;
@@ -411,7 +421,7 @@ static mfm_status do_fluxes(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
 mfm_status mfm_solve_h(mfm_ctx* c, mfm_particles* p, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     reset_counters(c, (hipStream_t)stream);
     return do_solve_h(c, p, (hipStream_t)stream);
 }
@@ -419,21 +429,21 @@ mfm_status mfm_solve_h(mfm_ctx* c, mfm_particles* p, void* stream) {
 mfm_status mfm_gradients(mfm_ctx* c, mfm_particles* p, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     return do_gradients(c, p, (hipStream_t)stream);
 }
 
 mfm_status mfm_hydro_fluxes(mfm_ctx* c, mfm_particles* p, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     return do_fluxes(c, p, (hipStream_t)stream);
 }
 
 mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     if (c->p.scheme == MFM_SCHEME_MFV && !p->dm) return fail(c, MFM_E_INVALID, "the finite-volume scheme needs dm");
     reset_counters(c, s);
@@ -450,7 +460,7 @@ mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, vo
         return fail(c, MFM_E_INVALID, "mfm_step needs every pass output array");
     if (!c->have_flux || c->n_tree != p->n)
         return fail(c, MFM_E_STATE, "mfm_step needs a pass on the current state (mfm_hydro_pass)");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)p->n;
     if (!(dt > 0.0)) {
@@ -493,7 +503,7 @@ mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, vo
 
 mfm_status mfm_set_kernel_timing(mfm_ctx* c, int enable) {
     if (!c) return MFM_E_INVALID;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     clock_reset(c);
     c->timing = enable ? 1 : 0;
     return MFM_OK;
@@ -501,7 +511,7 @@ mfm_status mfm_set_kernel_timing(mfm_ctx* c, int enable) {
 
 mfm_status mfm_kernel_time(mfm_ctx* c, int kernel, double* total_ms, int64_t* launches) {
     if (!c || kernel < 0 || kernel > 2 || !total_ms || !launches) return fail(c, MFM_E_INVALID, "bad kernel timing query");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     clock_drain(c->clk[kernel]);
     *total_ms = c->clk[kernel].total_ms;
     *launches = c->clk[kernel].launches;
@@ -510,7 +520,7 @@ mfm_status mfm_kernel_time(mfm_ctx* c, int kernel, double* total_ms, int64_t* la
 
 mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     if (!c || !out) return MFM_E_INVALID;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     mfm_status st;
     if ((st = hip_check(c, hipStreamSynchronize(c->last), "sync"))) return st;
     // combine the per-block-group copies: sums, maxima and the smallest index
@@ -567,10 +577,8 @@ mfm_status mfm_get_counters(mfm_ctx* c, mfm_counters* out) {
     return MFM_OK;
 }
 
-mfm_status mfm_check(mfm_ctx* c) {
-    mfm_counters k;
-    mfm_status st = mfm_get_counters(c, &k);
-    if (st) return st;
+// the status that a set of device counters stands for (mfm_check's precedence)
+static mfm_status status_of(mfm_ctx* c, const mfm_counters& k) {
     char buf[160];
     if (k.noconv) {
         snprintf(buf, sizeof buf, "%lld particles without a converged kernel length (first %lld)",
@@ -600,10 +608,17 @@ mfm_status mfm_check(mfm_ctx* c) {
     return MFM_OK;
 }
 
+mfm_status mfm_check(mfm_ctx* c) {
+    mfm_counters k;
+    mfm_status st = mfm_get_counters(c, &k);
+    if (st) return st;
+    return status_of(c, k);
+}
+
 mfm_status mfm_copy_flux_lists(mfm_ctx* c, int32_t* counts, int32_t* list, void* stream) {
     if (!c || !counts || !list) return MFM_E_INVALID;
     if (!c->have_grad) return fail(c, MFM_E_STATE, "no flux lists yet (they are complete after mfm_gradients)");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     const long long n = c->n_tree;
     mfm_status st;
@@ -634,7 +649,7 @@ extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p,
         return fail(c, MFM_E_INVALID, "the pass adjoint needs the forward outputs nk, V, B, rho, P, grad");
     if (!c->have_grad || !c->have_flux || c->n_tree != p->n)
         return fail(c, MFM_E_STATE, "the pass adjoint needs the pass of this state on this context");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     if ((st = ensure_adj(c))) return st;
     hipStream_t s = (hipStream_t)stream;
     PassArrays a = arrays_of(p);
@@ -656,7 +671,7 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     if (!w->dp || !w->dE || !w->vsig || !w->nk || !w->V || !w->B || !w->rho || !w->P || !w->grad)
         return fail(c, MFM_E_INVALID, "the work set needs every pass output array");
     if (!adj_x || !adj_v || !adj_u || !adj_dp || !adj_dE) return fail(c, MFM_E_INVALID, "null adjoint array");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     if ((st = ensure_adj(c))) return st;
     hipStream_t s = (hipStream_t)stream;
     const long long n = ck->n;
@@ -739,4 +754,129 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
     c->last = s;
     return launched(c, "step_adjoint");
+}
+
+// ------------------------------------------------- whole pass without allocation
+// mfm_hydro_pass_noalloc runs mfm_build_neighbours + mfm_hydro_pass for up to
+// kNoAllocMaxN particles with every scratch buffer carved from `scratch`, a
+// file-scope device array that each GPU holds from the library's load until
+// the process ends.  Host code reaches that array only through the address
+// hipGetSymbolAddress returns for it on each device (kept in g_noalloc_ptr).
+namespace {
+
+constexpr long long kNoAllocMaxN = 8192;   // particles per call
+constexpr int kNoAllocMaxNgb = 256;        // flux-list slots per particle
+constexpr int kNoAllocLevels = 6;          // deepest cell-table level
+constexpr int kNoAllocDevices = 64;
+// cells of levels 0..kNoAllocLevels of the implicit octree when every axis refines at every level
+constexpr long long kNoAllocTab = ((1ll << (3 * (kNoAllocLevels + 1))) - 1) / 7;
+constexpr long long kNoAllocScanInts = kNoAllocMaxN + 1024;   // bound on scan_tmp_ints(max(hist, n))
+
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// every scratch buffer of one pass, in carving order (bytes)
+constexpr long long N_ = kNoAllocMaxN;
+constexpr size_t kNoAllocSizes[] = {
+    8 * N_,                                   // keys
+    8 * N_,                                   // ktmp
+    4 * N_,                                   // idx
+    4 * N_,                                   // vtmp
+    4 * 256 * ((N_ + 2047) / 2048),           // hist
+    4 * kNoAllocScanInts,                     // scan_tmp
+    8 * N_ * kGatherMax,                      // gtmp
+    8 * kNoAllocTab,                          // tab
+    32 * N_,                                  // pos
+    8 * N_ * kRCap,                           // rl
+    4 * N_,                                   // counts
+    4 * N_,                                   // gcount
+    4 * N_ * kNoAllocMaxNgb,                  // list
+    4 * N_,                                   // fb_list
+    8,                                        // fb_count
+    4 * N_,                                   // fb2_list
+    8,                                        // fb2_count
+    4 * (size_t)kTailBuf * N_,                // tails
+    8 * 32 * N_,                              // rec
+    32 * 4 * N_,                              // prim
+    (size_t)kCounterCopies * kCounterStride,  // cnt
+};
+constexpr size_t noalloc_total() {
+    size_t t = 0;
+    for (size_t b : kNoAllocSizes) t += align256(b);
+    return t;
+}
+constexpr size_t kNoAllocBytes = noalloc_total();   // about 27 MB
+static_assert(kNoAllocBytes < (32u << 20), "the no-allocation scratch stays modest");
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kNoAllocDevices];   // device address of `scratch` on each device
+mfm_ctx g_noalloc_ctx[kNoAllocDevices]; // host-side context whose buffers point into it
+
+// point every scratch buffer of c into the array at base
+void noalloc_carve(mfm_ctx* c, unsigned char* base) {
+    void** dst[] = {(void**)&c->keys, (void**)&c->ktmp, (void**)&c->idx, (void**)&c->vtmp, (void**)&c->hist,
+                    (void**)&c->scan_tmp, (void**)&c->gtmp, (void**)&c->tab, (void**)&c->pos, (void**)&c->rl,
+                    (void**)&c->counts, (void**)&c->gcount, (void**)&c->list, (void**)&c->fb_list,
+                    (void**)&c->fb_count, (void**)&c->fb2_list, (void**)&c->fb2_count, (void**)&c->tails,
+                    (void**)&c->rec, (void**)&c->prim, (void**)&c->cnt};
+    static_assert(sizeof(dst) / sizeof(dst[0]) == sizeof(kNoAllocSizes) / sizeof(kNoAllocSizes[0]),
+                  "one size per carved buffer");
+    size_t off = 0;
+    for (size_t k = 0; k < sizeof(kNoAllocSizes) / sizeof(kNoAllocSizes[0]); k++) {
+        *dst[k] = base + off;
+        off += align256(kNoAllocSizes[k]);
+    }
+}
+
+}  // namespace
+
+extern "C" mfm_status mfm_hydro_pass_noalloc(const mfm_params* params, mfm_particles* p, mfm_counters* counters,
+                                             void* stream) {
+    if (!params || !params_valid(*params)) return MFM_E_INVALID;
+    if (params->max_ngb > kNoAllocMaxNgb || params->tree_levels > kNoAllocLevels) return MFM_E_INVALID;
+    if (!p || p->n < 1) return MFM_E_INVALID;
+    if (p->n > kNoAllocMaxN) return MFM_E_CAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return MFM_E_HIP;
+    mfm_ctx* c = &g_noalloc_ctx[dev];
+    {
+        // set-up, once per device with that device current: the device address of the array
+        std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+        if (!g_noalloc_ptr[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MFM_E_HIP;
+            g_noalloc_ptr[dev] = ptr;
+        }
+    }
+    mfm_params q = *params;
+    q.max_ngb = q.max_ngb > 0 ? q.max_ngb : kNoAllocMaxNgb;
+    q.tree_levels = q.tree_levels > 0 ? q.tree_levels : kNoAllocLevels;
+    c->cap = kNoAllocMaxN;
+    c->device = dev;
+    c->timing = 0;
+    c->adj = nullptr;
+    c->vp = c->up = c->Ehalf = c->mp = c->dt_part = c->dt_out = nullptr;
+    init_params(c, q);
+    if (c->tab_len > kNoAllocTab || scan_tmp_ints(std::max(256ll * ((p->n + 2047) / 2048), (long long)p->n)) >
+                                        kNoAllocScanInts)
+        return fail(c, MFM_E_CAPACITY, "cell tables or scan scratch exceed the no-allocation scratch");
+    noalloc_carve(c, (unsigned char*)g_noalloc_ptr[dev]);
+    c->n_tree = -1;
+    c->have_h = c->have_grad = c->have_flux = 0;
+    c->err[0] = 0;
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (!p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad || !p->dp || !p->dE || !p->vsig)
+        return fail(c, MFM_E_INVALID, "every pass output array is required");
+    if (q.scheme == MFM_SCHEME_MFV && !p->dm) return fail(c, MFM_E_INVALID, "the finite-volume scheme needs dm");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = build(c, p, s, nullptr, 0))) return st;
+    reset_counters(c, s);
+    if ((st = do_solve_h(c, p, s))) return st;
+    if ((st = do_gradients(c, p, s))) return st;
+    if ((st = do_fluxes(c, p, s))) return st;
+    if (!counters) return MFM_OK;
+    if ((st = mfm_get_counters(c, counters))) return st;
+    return status_of(c, *counters);
 }

@@ -24,7 +24,8 @@ STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV",
 EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "mfm_gradients",
            "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
-           "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_set_kernel_timing", "mfm_kernel_time")
+           "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_set_kernel_timing", "mfm_kernel_time",
+           "mfm_hydro_pass_noalloc")
 
 # kernels that mfm_kernel_time can report (mfm_kernel)
 KERNELS = {"solve_h": 0, "gradients": 1, "hydro_fluxes": 2}
@@ -97,6 +98,7 @@ def lib() -> C.CDLL:
                                        vp, vp, vp]
         L.mfm_set_kernel_timing.argtypes = [vp, C.c_int]
         L.mfm_kernel_time.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.mfm_hydro_pass_noalloc.argtypes = [C.POINTER(Params), C.POINTER(Particles), C.POINTER(Counters), vp]
         _lib = L
     return _lib
 
@@ -294,6 +296,25 @@ class Context:
         self._rc(self._L.mfm_copy_flux_lists(self.h, C.c_void_p(counts.data_ptr()),
                                              C.c_void_p(lst.data_ptr()), _stream(stream)))
         return counts, lst
+
+
+NOALLOC_MAX_N = 8192   # particles per mfm_hydro_pass_noalloc call
+
+
+def hydro_pass_noalloc(cfg: Config, st: State, counters: bool = True, stream=None):
+    """mfm_hydro_pass_noalloc: neighbours and the whole pass without a context or
+    any device allocation (st is reordered in place).  With counters the call
+    synchronises and returns the counter dict (raising on device-side errors
+    as Context.check does, ill-conditioned gradient matrices included); without,
+    it only queues the work and returns None."""
+    L = lib()
+    p = st.struct()
+    out = Counters() if counters else None
+    rc = L.mfm_hydro_pass_noalloc(C.byref(cfg.c()), C.byref(p), C.byref(out) if counters else None,
+                                  _stream(stream))
+    if rc != 0:
+        raise MFMError(rc, "mfm_hydro_pass_noalloc failed")
+    return out.as_dict() if counters else None
 
 
 def config_of(w, precision=FP64, **kw) -> Config:
