@@ -20,6 +20,7 @@ kernel alone on the same stream.  Prints one JSON line on stdout.
 from __future__ import annotations
 
 import argparse
+import contextlib
 import hashlib
 import json
 import os
@@ -34,38 +35,42 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-pair interactions/s per hydro pass, FP64 vs mixed at stated error; fwd+adj time"
 
 PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+# Vector peaks from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s FP64; FP32 twice that with packed FP32 instructions.
 PEAK_FP64_VALU = 78.6e12   # flop/s, FP64 vector
 PEAK_FP32_VALU = 157.3e12  # flop/s, FP32 vector (packed)
 
-# Algorithmic work per unit (each particle's inputs read once and its outputs
-# written once; neighbour data are re-reads).  n particles, G gather entries
-# (self excluded), F directed flux-list entries (= 2 pairs), P unordered pairs.
-#   solve_h:   x (24 B) + H guess (8 B) in; H, n, V (24 B) + two list lengths (8 B)
-#              out; one 4 B index per gather entry.  Flops: distance and root
-#              (sqrt) 9 + two spline evaluations (f, f') 24 per gather entry.
-#   gradients: x, H, V, n, m, v, u (88 B) and the gather list in; B (48 B),
-#              rho, P (16 B), five gradients (120 B) and the transposed flux-list
-#              entries (4 B each) out.  Flops: about 75 per gather entry
-#              (distance, W, E and the 15 weighted differences, extrema) and 200
-#              per particle (inverse, products, limiter).
-#   fluxes:    x, H, V, B, rho, P, v, gradients (248 B) and the flux list in;
-#              dp, dE, vsig (40 B) out.  Flops: 236 per unordered pair (kernel
-#              weights 20, faces 52, reconstruction 70, frame 22, HLLC 31, flux
-#              6, distance 9, accumulation and signal speed 26), add/mul/div/sqrt
-#              counted as one and fma as two.
-#   fluxes, finite-volume form: dm (8 B) more out; the full HLLC flux of the
-#              selected side (state, physical flux, star correction) and the
-#              lab-frame boost replace the P* flux: about 310 flops per pair.
-def algorithmic(kernel, n, G, F, P):
+# Algorithmic work per unit, the per-unit figures of the hot-path scope's
+# measurement section: each particle's inputs read once and outputs written
+# once (neighbour data are re-reads and not counted).  n particles, G gather
+# entries (self excluded), F directed flux-list entries (= 2 pairs), P
+# unordered pairs, I mean kernel-length iterations per particle.
+#   solve_h:   48 B per particle (x 24 B in; H, n, V 24 B out); 20 flops per
+#              gather neighbour per Newton iteration.
+#   gradients: 264 B per particle (x, H, V, m, v, u in; B, rho, P and the five
+#              gradients out); 65 flops per gather neighbour.
+#   fluxes:    288 B per particle (the gradient outputs, x, H, V and v in; dp,
+#              dE, vsig out); 400 flops per unordered pair (two sqrt, ~3 div).
+#   fluxes, finite-volume form: dm (8 B) more out, and the full HLLC flux of the
+#              selected side and the lab-frame boost add ~75 flops per pair.
+# The neighbour-list indices the implementation reads (4 B per gather or flux
+# entry) are reported separately as list_bytes.
+def algorithmic(kernel, n, G, F, P, iters=5.0):
+    """(bytes, flops, list_bytes) per launch."""
     if kernel == "solve_h":
-        return 64.0 * n + 4.0 * G, 33.0 * G
+        return 48.0 * n, 20.0 * G * iters, 4.0 * G
     if kernel == "gradients":
-        return 272.0 * n + 4.0 * F, 75.0 * G + 200.0 * n
+        return 264.0 * n, 65.0 * G, 4.0 * F
     if kernel == "hydro_fluxes":
-        return 288.0 * n + 4.0 * F, 236.0 * P
+        return 288.0 * n, 400.0 * P, 4.0 * F
     if kernel == "hydro_fluxes_mfv":
-        return 296.0 * n + 4.0 * F, 310.0 * P
+        return 296.0 * n, 475.0 * P, 4.0 * F
     raise KeyError(kernel)
+
+
+def binding(frac_hbm, frac_alu):
+    """The roof a kernel is closer to at its algorithmic counts."""
+    return "alu" if frac_alu >= frac_hbm else "hbm"
 
 
 KERNEL_NAMES = {"solve_h": "k_solve_h + k_solve_h_wave + k_solve_h_fallback", "gradients": "k_gradients<false>",
@@ -74,15 +79,16 @@ KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/cs
                   "paper_1712_01294_amd/csrc/kernels.h")
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
-# this benchmark, scaled by what the same counters read for a plain copy of
+# this benchmark, scaled by what the same counters read for plain copies of
 # known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
 # only for the kernel sources whose fingerprint is recorded with it.
-TRAFFIC = {
-    ("clustered", "solve_h"): {"bytes_per_launch": 141.36e9, "fingerprint": "cadc716193b0a796"},
-    ("clustered", "gradients"): {"bytes_per_launch": 30.52e9, "fingerprint": "cadc716193b0a796"},
-    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 13.80e9, "fingerprint": "cadc716193b0a796"},
-    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 14.18e9, "fingerprint": "cadc716193b0a796"},
-}
+TRAFFIC = {}
+
+# VALU counters per launch from rocprofv3 --pmc passes over this benchmark:
+# executed FP64 and FP32 flops (SQ_INSTS_VALU_FLOPS_FP64/FP32), VALU busy
+# percentage (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE, 256 CUs) and VALU
+# instructions issued.  Keyed and fingerprinted like TRAFFIC.
+COUNTERS = {}
 
 
 def source_fingerprint():
@@ -105,7 +111,6 @@ def parse():
     ap.add_argument("--workload", default="clustered")
     ap.add_argument("--tree-levels", type=int, default=0)
     ap.add_argument("--max-ngb", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-mfv", action="store_true")
@@ -117,15 +122,45 @@ def parse():
 
 
 def copy_probe():
-    """Five copies of a 1 GiB device buffer: 1 GiB fetched and 1 GiB written per launch."""
+    """Counter calibration: five plain copies of a 1 GiB device buffer by the
+    runtime's copy kernel, then five by a PyTorch elementwise kernel (b = a * 1):
+    each launch fetches 1 GiB and writes 1 GiB."""
     import torch
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_per_launch": nbytes, "launches": 5}), flush=True)
+    print(json.dumps({"copy_probe_bytes_per_launch": nbytes, "launches": 5,
+                      "kernels": ["__amd_rocclr_copyBuffer", "elementwise mul"]}), flush=True)
+
+
+def copy_ceiling(stream):
+    """Measured HBM ceiling: a 1 GiB device-to-device copy (1 GiB read, 1 GiB
+    written per launch), best of the copy and an elementwise kernel, median of
+    five launches each, timed with HIP events on the stream."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = 0.0
+    for op in (lambda: b.copy_(a), lambda: torch.mul(a, 1.0, out=b)):
+        op()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            op()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        best = max(best, 2.0 * nbytes / float(np.median(ts)))
+    del a, b
+    torch.cuda.empty_cache()
+    return best
 
 
 def timed_pass(ctx, st, steps, warmup, stream):
@@ -162,45 +197,90 @@ def timed_pass(ctx, st, steps, warmup, stream):
     return {k: float(np.mean(v)) for k, v in acc.items()}, kern
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on a bounded sample of the same workload: the particles of a
-    sub-box (all their dependencies computed), pairs of the sample per second."""
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+CPU_QUANTILES = (0.2, 0.4, 0.6, 0.8)
+
+
+def cpu_sample(w, side=0.125, quantiles=CPU_QUANTILES):
+    """Sub-cubes of side `side` (of the unit box) whose particle counts sit at
+    the given quantiles of all sub-cubes' counts, each as an open box with its
+    own origin: bounded pieces of the same particle set, spread over its
+    density range, that the oracle can pass over whole."""
+    from paper_1712_01294_amd import workloads
+    nc = int(round(1.0 / side))
+    X = np.stack([w.x, w.y, w.z]) / np.array(w.box)[:, None]
+    c = np.minimum((X * nc).astype(np.int64), nc - 1)
+    cell = (c[0] * nc + c[1]) * nc + c[2]
+    counts = np.bincount(cell, minlength=nc ** 3)
+    order = np.argsort(counts, kind="stable")
+    subs = []
+    for q in quantiles:
+        pick = int(order[min(len(order) - 1, int(q * len(order)))])
+        sel = np.flatnonzero(cell == pick)
+        o = np.array([pick // (nc * nc), (pick // nc) % nc, pick % nc]) * side
+        subs.append((workloads.Workload(name=w.name + "[sub-cube]", x=w.x[sel] - o[0], y=w.y[sel] - o[1],
+                                        z=w.z[sel] - o[2], m=w.m[sel], vx=w.vx[sel], vy=w.vy[sel],
+                                        vz=w.vz[sel], u=w.u[sel], gamma=w.gamma, box=(side, side, side),
+                                        periodic=(0, 0, 0), n_ngb=w.n_ngb), pick))
+    return subs
+
+
+def cpu_baseline(w):
+    """The FP64 oracle's whole-set pass (kernel lengths, gradients, fluxes) on a
+    bounded sample of the workload: four sub-cubes of the benchmark's own set,
+    each treated as an open box and passed over whole; pairs summed over the
+    four, divided by their summed time.  Single-threaded, then the OpenMP build
+    of the same oracle on every thread OpenMP is given."""
     from oracle import oracle as O
-    s = O.Setup.of(w)
-    X = np.stack([w.x, w.y, w.z], 1)
-    box = np.array(w.box)
-    order = np.argsort(((X / box) ** 2).sum(1))   # nearest the origin corner first
+    subs = cpu_sample(w)
+    info = host_cpu()
+    runs = {}
+    for kind in ("oracle", "oracle_omp"):
+        pairs, t, parts = 0, 0.0, []
+        with (O.openmp() if kind == "oracle_omp" else contextlib.nullcontext()):
+            cores = O.threads()
+            for sub, pick in subs:
+                t0 = time.perf_counter()
+                out = O.hydro_pass(O.Setup.of(sub), sub.arrays())
+                dt = time.perf_counter() - t0
+                pairs += out["pairs"]
+                t += dt
+                parts.append(f"cube {pick}: {sub.n} particles, {out['pairs']} pairs, {dt:.2f} s")
+        runs[kind] = {"value": pairs / t, "unit": "pairs/s", "cores": cores, "kind": kind,
+                      "sample": "whole-set oracle passes (cold kernel lengths) over four sub-cubes (side 1/8 "
+                                "of the box, open boundaries) of the same " + str(w.n) + "-particle set, at the "
+                                "20/40/60/80th percentiles of the 512 sub-cubes' particle counts; "
+                                + "; ".join(parts),
+                      **info}
+    return runs["oracle"], runs["oracle_omp"]
 
-    def run(k):
-        H, nk, V, _ = O.solve_h(s, w.x, w.y, w.z, None, mask=_mask(order[:k], w.n))
-        t0 = time.perf_counter()
-        out = O.sampled_pass(s, w.arrays(), order[:k], h_bound=_hbound(H))
-        return time.perf_counter() - t0, out
 
-    def _mask(idx, n):
-        m = np.zeros(n, dtype=bool)
-        m[idx] = True
-        return m
-
-    def _hbound(H):
-        h = H[H > 0]
-        return float(h.max()) * 1.5
-
-    # double the sample while the next run, extrapolated with the growth of the
-    # last doubling, stays within the budget (the dependency closure, and so the
-    # cost per target, grows with the largest kernel length in the sample)
-    k = 500
-    t, out = run(k)
-    growth = 2.0
-    while k < w.n and t * growth <= budget_s:
-        t_prev = t
-        t_new, out_new = run(int(min(w.n, 2 * k)))
-        k, t, out = int(min(w.n, 2 * k)), t_new, out_new
-        growth = max(2.0, t / max(t_prev, 1e-9))
-    pairs = out["pair_entries"] / 2.0
-    return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} targets nearest one box corner of the same {w.n}-particle set, with every "
-                      f"particle they depend on; {out['pair_entries']} directed flux entries in {t:.1f} s"}
+# Algorithmic traffic of forward + adjoint per particle (10 fixed-dt steps):
+# forward = the initial pass (600 B: 48 + 264 + 288) and 10 steps of a pass plus
+# the kick-drift-kick streaming (~160 B: x, v, u, m, dp, dE in; x, v, u and the
+# predicted v, u out) and one checkpoint copy (96 B read and written); backward
+# = per step the checkpoint restored (192 B), the step recomputed (760 B), the
+# reverse pass (the pass's 600 B plus 88 B of adjoints in and out) and the
+# reverse step streaming (~200 B), then the initial pass recomputed and
+# reversed (1,288 B).  The 64^3 box (~30 kB x 262,144 = 7.8 GB per run) fits
+# in the 256 MB Infinity Cache, so this is a traffic-equivalent rate.
+ADJ_BYTES_PER_PARTICLE = (600 + 10 * (600 + 160 + 192)) + (10 * (192 + 760 + 688 + 200) + 1288)
 
 
 def adjoint_timing(reps=3):
@@ -232,9 +312,15 @@ def adjoint_timing(reps=3):
             bw.append(t2 - t1)
     evo.ctx.check()
     fwd, adj = float(np.median(fw)) * 1e3, float(np.median(bw)) * 1e3
+    b = ADJ_BYTES_PER_PARTICLE * float(w.n)
+    rate = b / ((fwd + adj) * 1e-3)
     return {"workload": f"jittered box 64^3 = {w.n} particles, {w.steps} fixed steps of dt = {w.dt}, "
                         "L = sum m |v|^2 at the end, gradient w.r.t. (v0, u0)",
             "fwd_ms": fwd, "adj_ms": adj, "fwd_adj_ms": fwd + adj, "reps": reps,
+            "roofline": {"bound": "hbm", "achieved": rate / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": rate / PEAK_HBM, "algorithmic_bytes": b,
+                         "note": "algorithmic bytes of forward + adjoint over their wall time; the set fits "
+                                 "in the Infinity Cache"},
             "note": "wall clock with the stream synchronised at both ends; forward keeps one checkpoint per step"}
 
 
@@ -248,6 +334,52 @@ def run_precision(mfm, w, prec, kw, args, stream, scheme=0):
     ctx.check(allow_illcond=True)
     cnt = ctx.counters()
     return ctx, st, tm, kern, cnt
+
+
+def kernel_table(w, kern, n, G, F, P, iters, fp, mixed):
+    """Per-kernel rates against the roofs at the algorithmic counts, with the
+    measured traffic and VALU counters of the same sources when recorded."""
+    kernels = {}
+    for k, v in kern.items():
+        b, f, lb = algorithmic(k, n, G, F, P, iters)
+        s = v["ms_avg"] * 1e-3
+        # the mixed flux kernel's pair arithmetic is FP32; everything else FP64
+        peak = PEAK_FP32_VALU if (mixed and k == "hydro_fluxes") else PEAK_FP64_VALU
+        fh, fa = b / s / PEAK_HBM, f / s / peak
+        e = {"kernel": KERNEL_NAMES[k], "ms_avg": v["ms_avg"], "launches": v["launches"],
+             "algorithmic_bytes": b, "list_bytes": lb, "algorithmic_flops": f,
+             "GBps": b / s / 1e9, "frac_hbm": fh, "GFLOPps": f / s / 1e9,
+             "alu_peak_TFLOPps": peak / 1e12, "frac_alu": fa, "bound": binding(fh, fa)}
+        key = (w.name, k + ("_mixed" if mixed else ""))
+        tr = TRAFFIC.get(key)
+        e["traffic"] = tr["bytes_per_launch"] if tr and tr["fingerprint"] == fp else None
+        if e["traffic"] is not None:
+            e["traffic_GBps"] = e["traffic"] / s / 1e9
+            e["traffic_frac_hbm"] = e["traffic"] / s / PEAK_HBM
+        ct = COUNTERS.get(key)
+        if ct and ct["fingerprint"] == fp:
+            e["counters"] = {"valu_busy_pct": ct["valu_busy_pct"],
+                             "executed_fp64_TFLOPps": ct["fp64_flops_per_launch"] / s / 1e12,
+                             "executed_fp32_TFLOPps": ct["fp32_flops_per_launch"] / s / 1e12,
+                             "valu_insts_per_launch": ct["valu_insts_per_launch"]}
+        kernels[k] = e
+    return kernels
+
+
+def roofline_of(dk, fp):
+    """The bench line's roofline object for one kernel: the roof it is closer to
+    at its algorithmic counts, the other roof beside it."""
+    alu = {"achieved": dk["GFLOPps"] / 1e3, "peak": dk["alu_peak_TFLOPps"], "unit": "TFLOP/s",
+           "frac": dk["frac_alu"], "flops_per_launch": dk["algorithmic_flops"]}
+    hbm = {"achieved": dk["GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": dk["frac_hbm"],
+           "bytes_per_launch": dk["algorithmic_bytes"], "list_bytes_per_launch": dk["list_bytes"]}
+    top = alu if dk["bound"] == "alu" else hbm
+    r = {"kernel": dk["kernel"], "bound": dk["bound"], "achieved": top["achieved"], "peak": top["peak"],
+         "unit": top["unit"], "frac": top["frac"], "traffic": dk["traffic"], "ms_avg": dk["ms_avg"],
+         "hbm": hbm, "alu": alu, "source_fingerprint": fp}
+    if "counters" in dk:
+        r["counters"] = dk["counters"]
+    return r
 
 
 def main():
@@ -282,30 +414,14 @@ def main():
         + " ".join(f"{k}={v:.3f}ms" for k, v in tm.items()))
     del ctx
     n, P, F, G = w.n, cnt["pairs"], cnt["list_entries"], cnt["gather_entries"]
+    iters = cnt["h_iters"] / n
     pass_ms = tm["solve_h"] + tm["gradients"] + tm["fluxes"]
-
-    kernels = {}
-    for k, v in kern.items():
-        b, f = algorithmic(k, n, G, F, P)
-        s = v["ms_avg"] * 1e-3
-        kernels[k] = {"kernel": KERNEL_NAMES[k], "ms_avg": v["ms_avg"], "launches": v["launches"],
-                      "algorithmic_bytes": b, "algorithmic_flops": f,
-                      "GBps": b / s / 1e9, "frac_hbm": b / s / PEAK_HBM,
-                      "GFLOPps": f / s / 1e9, "frac_fp64": f / s / PEAK_FP64_VALU}
     fp = source_fingerprint()
-    for k, v in kernels.items():
-        tr = TRAFFIC.get((w.name, k))
-        v["traffic"] = tr["bytes_per_launch"] if tr and tr["fingerprint"] == fp else None
+    kernels = kernel_table(w, kern, n, G, F, P, iters, fp, mixed=False)
     dom = max(kernels, key=lambda k: kernels[k]["ms_avg"])
-    dk = kernels[dom]
-    traffic = dk["traffic"]
-    # the pass is memory-side at algorithmic intensity (flop/B below the FP64 ridge)
-    roofline = {"kernel": dk["kernel"], "bound": "hbm", "achieved": dk["GBps"], "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": dk["frac_hbm"], "traffic": traffic,
-                "algorithmic_bytes_per_launch": dk["algorithmic_bytes"], "ms_avg": dk["ms_avg"],
-                "fp64_alu": {"achieved": dk["GFLOPps"] / 1e3, "peak": PEAK_FP64_VALU / 1e12,
-                             "unit": "TFLOP/s", "frac": dk["frac_fp64"]},
-                "source_fingerprint": fp}
+    roofline = roofline_of(kernels[dom], fp)
+    ceiling = copy_ceiling(stream)
+    roofline["hbm"]["measured_copy_ceiling_GBps"] = ceiling / 1e9
 
     out = {
         "metric": METRIC,
@@ -341,14 +457,12 @@ def main():
                 b = getattr(stmx, k).double()
                 errs[k] = float((a - b).abs().max() / a.abs().max())
         pm = torch.tensor([float((st64.dp[c]).sum()) for c in range(3)])
+        kx = kernel_table(w, kmx, n, G, F, P, cmx["h_iters"] / n, fp, mixed=True)
+        mdom = max(kx, key=lambda k: kx[k]["ms_avg"])
         out["mixed"] = {"value": cmx["pairs"] / (mx_ms * 1e-3), "unit": "pairs/s", "dtype": "f32/f64",
                         "ms_per_step": mx_ms, "stage_ms": tmx,
                         "kernel_ms": {k: v["ms_avg"] for k, v in kmx.items()},
-                        # the pair arithmetic of the mixed flux kernel is FP32: its flops
-                        # against the FP32 vector peak
-                        "flux_GFLOPps": algorithmic("hydro_fluxes", n, G, F, P)[1] / (kmx["hydro_fluxes"]["ms_avg"] * 1e-3) / 1e9,
-                        "flux_frac_fp32": algorithmic("hydro_fluxes", n, G, F, P)[1]
-                        / (kmx["hydro_fluxes"]["ms_avg"] * 1e-3) / PEAK_FP32_VALU,
+                        "kernels": kx, "roofline": roofline_of(kx[mdom], fp),
                         "speedup_vs_fp64": pass_ms / mx_ms,
                         "normwise_error_vs_fp64": errs,
                         "momentum_sum_mixed": [float(stmx.dp[c].sum()) for c in range(3)],
@@ -363,13 +477,14 @@ def main():
         del ctx
         v_ms = tv["solve_h"] + tv["gradients"] + tv["fluxes"]
         fk = kv["hydro_fluxes"]
-        b, f = algorithmic("hydro_fluxes_mfv", n, cv["gather_entries"], cv["list_entries"], cv["pairs"])
+        b, f, lb = algorithmic("hydro_fluxes_mfv", n, cv["gather_entries"], cv["list_entries"], cv["pairs"])
         s = fk["ms_avg"] * 1e-3
         dm = stv.dm
         out["mfv"] = {"value": cv["pairs"] / (v_ms * 1e-3), "unit": "pairs/s", "dtype": "f64",
                       "ms_per_step": v_ms, "stage_ms": tv,
                       "flux_kernel": {"kernel": "k_fluxes_mfv", "ms_avg": fk["ms_avg"], "launches": fk["launches"],
-                                      "algorithmic_bytes": b, "GBps": b / s / 1e9, "frac_hbm": b / s / PEAK_HBM,
+                                      "algorithmic_bytes": b, "list_bytes": lb, "GBps": b / s / 1e9,
+                                      "frac_hbm": b / s / PEAK_HBM,
                                       "algorithmic_flops": f, "GFLOPps": f / s / 1e9,
                                       "frac_fp64": f / s / PEAK_FP64_VALU},
                       "mass_rate_sum_rel": float(dm.sum().abs() / dm.abs().sum()),
@@ -402,7 +517,9 @@ def main():
         log(f"adjoint: {out['adjoint']['fwd_ms']:.1f} ms fwd + {out['adjoint']['adj_ms']:.1f} ms adj")
     if not args.no_cpu:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"], out["cpu_baseline_omp"] = cpu_baseline(w)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} pairs/s on 1 thread, "
+            f"{out['cpu_baseline_omp']['value']:.3e} on {out['cpu_baseline_omp']['cores']}")
     print(json.dumps(out), flush=True)
 
 

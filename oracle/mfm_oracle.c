@@ -30,12 +30,18 @@
  *
  * Everything is written as plain loops over an explicit neighbour search
  * (brute force, or a uniform bucket grid that the tests pin against brute
- * force).  Compiled with -O2 -ffp-contract=off and no fast-math.
+ * force).  Compiled with -O2 -ffp-contract=off and no fast-math, single-
+ * threaded; a second build with -fopenmp shares the per-particle loops out
+ * over threads (each particle's arithmetic is the same, so are the results).
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_E_INVALID (-1)
@@ -54,6 +60,16 @@ typedef struct {
     double cell;      /* bucket grid cell size; <= 0 selects brute force */
     int32_t scheme;   /* 0: meshless finite mass (R15), 1: meshless finite volume */
 } or_params;
+
+/* threads a pass uses: 1, or the OpenMP team size of an OpenMP build */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* R1: cubic spline, support radius H.  W = 8/(pi H^3) w(r/H).          */
@@ -303,12 +319,53 @@ static double h_residual(const nbr_list *L, double H, double n_ngb)
  * from the mean density), out = root; nk = n(H), V = 1/nk.  iters[i] counts
  * the bisection steps.
  */
+/* the root for one particle i; L is the caller's scratch list */
+static int solve_one(const grid_t *g, const or_params *p, int64_t i, double cold, double half,
+                     nbr_list *L, double *H, double *nk, double *V, int64_t *iters)
+{
+    double hi = H[i] > 0.0 ? H[i] : cold;
+    double lo = 0.0;
+    /* grow the bracket until f(hi) >= 0 */
+    for (;;) {
+        int rc = grid_find(g, i, hi, L);
+        if (rc) return rc;
+        if (h_residual(L, hi, p->n_ngb) >= 0.0) break;
+        lo = hi;
+        hi *= 1.5;
+        if (!(hi < half)) {
+            /* halve the remaining distance to the limit instead; once that
+             * no longer moves, no admissible radius reaches the root */
+            double h2 = 0.5 * (lo + half);
+            if (!(h2 > lo && h2 < half)) return OR_E_MINIMAGE;
+            hi = h2;
+        }
+    }
+    int64_t it = 0;
+    for (; it < 400; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (h_residual(L, mid, p->n_ngb) < 0.0) lo = mid;
+        else hi = mid;
+    }
+    if (it == 400) return OR_E_NOCONV;
+    H[i] = hi;
+    nk[i] = number_density(L, hi);
+    V[i] = 1.0 / nk[i];
+    if (iters) iters[i] = it;
+    return OR_OK;
+}
+
+/*
+ * For every i with mask[i] != 0 (mask may be NULL): H[i] in = guess (<= 0:
+ * from the mean density), out = root; nk = n(H), V = 1/nk.  iters[i] counts
+ * the bisection steps.  Particles are independent: an OpenMP build of this
+ * file shares them out over threads (the result is the same, bit for bit).
+ */
 int or_solve_h(const or_params *p, int64_t n, const double *x, const double *y,
                const double *z, const uint8_t *mask, double *H, double *nk, double *V,
                int64_t *iters)
 {
     grid_t g;
-    nbr_list L = {0};
     int rc = grid_build(&g, p, n, x, y, z);
     double vol = p->box[0] * p->box[1] * p->box[2];
     double cold = cbrt(3.0 * p->n_ngb * vol / (4.0 * M_PI * (double)n));
@@ -317,40 +374,26 @@ int or_solve_h(const or_params *p, int64_t n, const double *x, const double *y,
     double half = INFINITY;
     for (int a = 0; a < 3; a++)
         if (p->periodic[a] && 0.5 * p->box[a] < half) half = 0.5 * p->box[a];
-    for (int64_t i = 0; i < n && !rc; i++) {
-        if (mask && !mask[i]) continue;
-        double hi = H[i] > 0.0 ? H[i] : cold;
-        double lo = 0.0;
-        /* grow the bracket until f(hi) >= 0 */
-        for (;;) {
-            rc = grid_find(&g, i, hi, &L);
-            if (rc) break;
-            if (h_residual(&L, hi, p->n_ngb) >= 0.0) break;
-            lo = hi;
-            hi *= 1.5;
-            if (!(hi < half)) {
-                /* halve the remaining distance to the limit instead; once that
-                 * no longer moves, no admissible radius reaches the root */
-                double h2 = 0.5 * (lo + half);
-                if (!(h2 > lo && h2 < half)) { rc = OR_E_MINIMAGE; break; }
-                hi = h2;
+    if (!rc) {
+#pragma omp parallel
+        {
+            nbr_list L = {0};
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < n; i++) {
+                if (mask && !mask[i]) continue;
+                int e;
+#pragma omp atomic read
+                e = rc;
+                if (e) continue;
+                e = solve_one(&g, p, i, cold, half, &L, H, nk, V, iters);
+                if (e) {
+#pragma omp atomic write
+                    rc = e;
+                }
             }
+            free(L.a);
         }
-        if (rc) break;
-        int64_t it = 0;
-        for (; it < 400; it++) {
-            double mid = 0.5 * (lo + hi);
-            if (!(mid > lo && mid < hi)) break;
-            if (h_residual(&L, mid, p->n_ngb) < 0.0) lo = mid;
-            else hi = mid;
-        }
-        if (it == 400) { rc = OR_E_NOCONV; break; }
-        H[i] = hi;
-        nk[i] = number_density(&L, hi);
-        V[i] = 1.0 / nk[i];
-        if (iters) iters[i] = it;
     }
-    free(L.a);
     grid_free(&g);
     return rc;
 }
@@ -387,6 +430,81 @@ static void invert_sym3(const double E[3][3], double B[3][3], double *det_out)
  * (limited), and optionally grad_raw (unlimited), alpha (5 x n limiter
  * factors), cond (||E||_F ||B||_F).  *n_illcond counts flagged particles.
  */
+/* R6-R8, R10 for one particle i; *ill = 1 when its E is flagged (R7) */
+static int gradients_one(const grid_t *g, const or_params *p, int64_t n, int64_t i, const double *m,
+                         const double *vx, const double *vy, const double *vz, const double *u,
+                         const double *H, const double *nk, const double *V, nbr_list *L, double *B,
+                         double *rho, double *P, double *grad, double *grad_raw, double *alpha,
+                         double *cond, int *ill)
+{
+    int rc = grid_find(g, i, H[i], L);
+    if (rc) return rc;
+    double phi_i[5];
+    double rho_i = m[i] * nk[i];
+    phi_i[0] = rho_i;
+    phi_i[1] = vx[i];
+    phi_i[2] = vy[i];
+    phi_i[3] = vz[i];
+    phi_i[4] = (p->gamma - 1.0) * rho_i * u[i];
+    double E[3][3] = {{0}}, S[5][3] = {{0}};
+    double pmax[5], pmin[5], rmax = 0.0;
+    for (int f = 0; f < 5; f++) pmax[f] = pmin[f] = phi_i[f];
+    for (int64_t k = 0; k < L->n; k++) {
+        int64_t j = L->a[k].j;
+        const double *d = L->a[k].d;
+        double psi = or_kernel_W(L->a[k].r, H[i]) * V[i];
+        double rho_j = m[j] * nk[j];
+        double phi_j[5] = {rho_j, vx[j], vy[j], vz[j], (p->gamma - 1.0) * rho_j * u[j]};
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) E[a][b] += d[a] * d[b] * psi;
+        for (int f = 0; f < 5; f++) {
+            for (int a = 0; a < 3; a++) S[f][a] += (phi_j[f] - phi_i[f]) * d[a] * psi;
+            if (phi_j[f] > pmax[f]) pmax[f] = phi_j[f];
+            if (phi_j[f] < pmin[f]) pmin[f] = phi_j[f];
+        }
+        if (L->a[k].r > rmax) rmax = L->a[k].r;
+    }
+    double Bm[3][3], det;
+    invert_sym3(E, Bm, &det);
+    double fe = 0.0, fb = 0.0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            fe += E[a][b] * E[a][b];
+            fb += Bm[a][b] * Bm[a][b];
+        }
+    double kappa = sqrt(fe) * sqrt(fb);
+    if (!(det > 0.0) || !(kappa <= p->cond_max)) *ill = 1;
+    if (cond) cond[i] = kappa;
+    B[0 * n + i] = Bm[0][0];
+    B[1 * n + i] = Bm[0][1];
+    B[2 * n + i] = Bm[0][2];
+    B[3 * n + i] = Bm[1][1];
+    B[4 * n + i] = Bm[1][2];
+    B[5 * n + i] = Bm[2][2];
+    rho[i] = phi_i[0];
+    P[i] = phi_i[4];
+    double half_span = 0.5 * rmax;
+    for (int f = 0; f < 5; f++) {
+        double gr[3];
+        for (int a = 0; a < 3; a++)
+            gr[a] = Bm[a][0] * S[f][0] + Bm[a][1] * S[f][1] + Bm[a][2] * S[f][2];
+        double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+        double al = 1.0;
+        if (gn > 0.0) {
+            double up = (pmax[f] - phi_i[f]) / (gn * half_span);
+            double dn = (phi_i[f] - pmin[f]) / (gn * half_span);
+            double lim = p->beta * (up < dn ? up : dn);
+            al = lim < 1.0 ? lim : 1.0;
+        }
+        for (int a = 0; a < 3; a++) {
+            if (grad_raw) grad_raw[(3 * f + a) * n + i] = gr[a];
+            grad[(3 * f + a) * n + i] = al * gr[a];
+        }
+        if (alpha) alpha[f * n + i] = al;
+    }
+    return OR_OK;
+}
+
 int or_gradients(const or_params *p, int64_t n, const double *x, const double *y,
                  const double *z, const double *m, const double *vx, const double *vy,
                  const double *vz, const double *u, const double *H, const double *nk,
@@ -395,79 +513,32 @@ int or_gradients(const or_params *p, int64_t n, const double *x, const double *y
                  int64_t *n_illcond)
 {
     grid_t g;
-    nbr_list L = {0};
     int rc = grid_build(&g, p, n, x, y, z);
     int64_t nill = 0;
-    for (int64_t i = 0; i < n && !rc; i++) {
-        if (mask && !mask[i]) continue;
-        rc = grid_find(&g, i, H[i], &L);
-        if (rc) break;
-        double phi_i[5];
-        double rho_i = m[i] * nk[i];
-        phi_i[0] = rho_i;
-        phi_i[1] = vx[i];
-        phi_i[2] = vy[i];
-        phi_i[3] = vz[i];
-        phi_i[4] = (p->gamma - 1.0) * rho_i * u[i];
-        double E[3][3] = {{0}}, S[5][3] = {{0}};
-        double pmax[5], pmin[5], rmax = 0.0;
-        for (int f = 0; f < 5; f++) pmax[f] = pmin[f] = phi_i[f];
-        for (int64_t k = 0; k < L.n; k++) {
-            int64_t j = L.a[k].j;
-            const double *d = L.a[k].d;
-            double psi = or_kernel_W(L.a[k].r, H[i]) * V[i];
-            double rho_j = m[j] * nk[j];
-            double phi_j[5] = {rho_j, vx[j], vy[j], vz[j], (p->gamma - 1.0) * rho_j * u[j]};
-            for (int a = 0; a < 3; a++)
-                for (int b = 0; b < 3; b++) E[a][b] += d[a] * d[b] * psi;
-            for (int f = 0; f < 5; f++) {
-                for (int a = 0; a < 3; a++) S[f][a] += (phi_j[f] - phi_i[f]) * d[a] * psi;
-                if (phi_j[f] > pmax[f]) pmax[f] = phi_j[f];
-                if (phi_j[f] < pmin[f]) pmin[f] = phi_j[f];
+    if (!rc) {
+#pragma omp parallel reduction(+ : nill)
+        {
+            nbr_list L = {0};
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < n; i++) {
+                if (mask && !mask[i]) continue;
+                int e;
+#pragma omp atomic read
+                e = rc;
+                if (e) continue;
+                int ill = 0;
+                e = gradients_one(&g, p, n, i, m, vx, vy, vz, u, H, nk, V, &L, B, rho, P, grad, grad_raw,
+                                  alpha, cond, &ill);
+                nill += ill;
+                if (e) {
+#pragma omp atomic write
+                    rc = e;
+                }
             }
-            if (L.a[k].r > rmax) rmax = L.a[k].r;
-        }
-        double Bm[3][3], det;
-        invert_sym3(E, Bm, &det);
-        double fe = 0.0, fb = 0.0;
-        for (int a = 0; a < 3; a++)
-            for (int b = 0; b < 3; b++) {
-                fe += E[a][b] * E[a][b];
-                fb += Bm[a][b] * Bm[a][b];
-            }
-        double kappa = sqrt(fe) * sqrt(fb);
-        if (!(det > 0.0) || !(kappa <= p->cond_max)) nill++;
-        if (cond) cond[i] = kappa;
-        B[0 * n + i] = Bm[0][0];
-        B[1 * n + i] = Bm[0][1];
-        B[2 * n + i] = Bm[0][2];
-        B[3 * n + i] = Bm[1][1];
-        B[4 * n + i] = Bm[1][2];
-        B[5 * n + i] = Bm[2][2];
-        rho[i] = phi_i[0];
-        P[i] = phi_i[4];
-        double half_span = 0.5 * rmax;
-        for (int f = 0; f < 5; f++) {
-            double gr[3];
-            for (int a = 0; a < 3; a++)
-                gr[a] = Bm[a][0] * S[f][0] + Bm[a][1] * S[f][1] + Bm[a][2] * S[f][2];
-            double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-            double al = 1.0;
-            if (gn > 0.0) {
-                double up = (pmax[f] - phi_i[f]) / (gn * half_span);
-                double dn = (phi_i[f] - pmin[f]) / (gn * half_span);
-                double lim = p->beta * (up < dn ? up : dn);
-                al = lim < 1.0 ? lim : 1.0;
-            }
-            for (int a = 0; a < 3; a++) {
-                if (grad_raw) grad_raw[(3 * f + a) * n + i] = gr[a];
-                grad[(3 * f + a) * n + i] = al * gr[a];
-            }
-            if (alpha) alpha[f * n + i] = al;
+            free(L.a);
         }
     }
     if (n_illcond) *n_illcond = nill;
-    free(L.a);
     grid_free(&g);
     return rc;
 }
@@ -682,6 +753,59 @@ void or_mfv_flux(double gamma, double rL, double uL, double pL, double rR, doubl
  * first-order fallbacks and P* clamps (directed).  With scheme 1 (MFV) the
  * pair flux is the full HLLC one and dm (nullable) receives -s F_m summed.
  */
+/* R2, R9, R11-R16, R18 for one particle i: its flux sums and signal speed */
+static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i, const double *vx,
+                      const double *vy, const double *vz, const double *H, const double *V,
+                      const double *B, const double *rho, const double *P, const double *grad,
+                      double hmax, nbr_list *L, double *dp, double *dE, double *vsig, double *dm,
+                      int64_t *npair, int64_t *nfall, int64_t *nclamp)
+{
+    double R = H[i] > hmax ? H[i] : hmax;
+    int rc = grid_find(g, i, R, L);
+    if (rc) return rc;
+    double acc[4] = {0, 0, 0, 0}, accm = 0.0;
+    double ci = sqrt(p->gamma * P[i] / rho[i]);
+    double vs = 0.0;
+    side_t si, sj;
+    load_side(&si, i, n, H, V, B, rho, vx, vy, vz, P, grad);
+    for (int64_t k = 0; k < L->n; k++) {
+        int64_t j = L->a[k].j;
+        double r = L->a[k].r;
+        if (j == i) continue;
+        if (!(r < H[i] || r < H[j])) continue;
+        (*npair)++;
+        load_side(&sj, j, n, H, V, B, rho, vx, vy, vz, P, grad);
+        pairflux_t o;
+        double s;
+        if (i < j) {
+            pair_flux(&si, &sj, L->a[k].d, r, p->gamma, p->scheme == 1, &o);
+            s = 1.0;
+        } else {
+            double dn[3] = {-L->a[k].d[0], -L->a[k].d[1], -L->a[k].d[2]};
+            pair_flux(&sj, &si, dn, r, p->gamma, p->scheme == 1, &o);
+            s = -1.0;
+        }
+        *nfall += o.fallback;
+        *nclamp += o.clamp;
+        for (int c = 0; c < 3; c++) acc[c] -= s * o.Fp[c];
+        acc[3] -= s * o.FE;
+        accm -= s * o.Fm;
+        double cj = sqrt(p->gamma * P[j] / rho[j]);
+        const double *d = L->a[k].d; /* x_j - x_i */
+        double proj = ((vx[i] - vx[j]) * (-d[0]) + (vy[i] - vy[j]) * (-d[1]) +
+                       (vz[i] - vz[j]) * (-d[2])) / r;
+        double sig = ci + cj - (proj < 0.0 ? proj : 0.0);
+        if (sig > vs) vs = sig;
+    }
+    dp[0 * n + i] = acc[0];
+    dp[1 * n + i] = acc[1];
+    dp[2 * n + i] = acc[2];
+    dE[i] = acc[3];
+    vsig[i] = vs;
+    if (dm) dm[i] = accm;
+    return OR_OK;
+}
+
 int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
               const double *z, const double *vx, const double *vy, const double *vz,
               const double *H, const double *V, const double *B, const double *rho,
@@ -689,61 +813,34 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
               double *dp, double *dE, double *vsig, int64_t *counts, double *dm)
 {
     grid_t g;
-    nbr_list L = {0};
     int rc = grid_build(&g, p, n, x, y, z);
     int64_t npair = 0, nfall = 0, nclamp = 0;
-    for (int64_t i = 0; i < n && !rc; i++) {
-        if (mask && !mask[i]) continue;
-        double R = H[i] > hmax ? H[i] : hmax;
-        rc = grid_find(&g, i, R, &L);
-        if (rc) break;
-        double acc[4] = {0, 0, 0, 0}, accm = 0.0;
-        double ci = sqrt(p->gamma * P[i] / rho[i]);
-        double vs = 0.0;
-        side_t si, sj;
-        load_side(&si, i, n, H, V, B, rho, vx, vy, vz, P, grad);
-        for (int64_t k = 0; k < L.n; k++) {
-            int64_t j = L.a[k].j;
-            double r = L.a[k].r;
-            if (j == i) continue;
-            if (!(r < H[i] || r < H[j])) continue;
-            npair++;
-            load_side(&sj, j, n, H, V, B, rho, vx, vy, vz, P, grad);
-            pairflux_t o;
-            double s;
-            if (i < j) {
-                pair_flux(&si, &sj, L.a[k].d, r, p->gamma, p->scheme == 1, &o);
-                s = 1.0;
-            } else {
-                double dn[3] = {-L.a[k].d[0], -L.a[k].d[1], -L.a[k].d[2]};
-                pair_flux(&sj, &si, dn, r, p->gamma, p->scheme == 1, &o);
-                s = -1.0;
+    if (!rc) {
+#pragma omp parallel reduction(+ : npair, nfall, nclamp)
+        {
+            nbr_list L = {0};
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < n; i++) {
+                if (mask && !mask[i]) continue;
+                int e;
+#pragma omp atomic read
+                e = rc;
+                if (e) continue;
+                e = fluxes_one(&g, p, n, i, vx, vy, vz, H, V, B, rho, P, grad, hmax, &L, dp, dE, vsig, dm,
+                               &npair, &nfall, &nclamp);
+                if (e) {
+#pragma omp atomic write
+                    rc = e;
+                }
             }
-            nfall += o.fallback;
-            nclamp += o.clamp;
-            for (int c = 0; c < 3; c++) acc[c] -= s * o.Fp[c];
-            acc[3] -= s * o.FE;
-            accm -= s * o.Fm;
-            double cj = sqrt(p->gamma * P[j] / rho[j]);
-            const double *d = L.a[k].d; /* x_j - x_i */
-            double proj = ((vx[i] - vx[j]) * (-d[0]) + (vy[i] - vy[j]) * (-d[1]) +
-                           (vz[i] - vz[j]) * (-d[2])) / r;
-            double sig = ci + cj - (proj < 0.0 ? proj : 0.0);
-            if (sig > vs) vs = sig;
+            free(L.a);
         }
-        dp[0 * n + i] = acc[0];
-        dp[1 * n + i] = acc[1];
-        dp[2 * n + i] = acc[2];
-        dE[i] = acc[3];
-        vsig[i] = vs;
-        if (dm) dm[i] = accm;
     }
     if (counts) {
         counts[0] = npair;
         counts[1] = nfall;
         counts[2] = nclamp;
     }
-    free(L.a);
     grid_free(&g);
     return rc;
 }

@@ -13,6 +13,7 @@ with a predicted state.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -23,6 +24,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mfm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")   # the same source built with -fopenmp
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -36,23 +38,44 @@ class OrParams(C.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math), once
+    single-threaded and once with OpenMP over particles."""
+    for lib_path, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(SRC):
+            tmp = lib_path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+                                   "-D_GNU_SOURCE", "-Wno-unknown-pragmas", *extra, "-fPIC", "-shared",
+                                   "-o", tmp, SRC, "-lm"])
+            os.replace(tmp, lib_path)
     return LIB
 
 
-_lib = None
+_libs = {}
+_omp = [False]
+
+
+@contextlib.contextmanager
+def openmp():
+    """Within the block the oracle's passes run on its OpenMP build (all the
+    threads OpenMP is given); results are bitwise those of the serial build."""
+    prev = _omp[0]
+    _omp[0] = True
+    try:
+        yield
+    finally:
+        _omp[0] = prev
+
+
+def threads() -> int:
+    """Threads the active build uses for a pass."""
+    return int(lib().or_threads())
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    key = _omp[0]
+    if key not in _libs:
         build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(LIB_OMP if key else LIB)
         L.or_kernel_W.restype = C.c_double
         L.or_kernel_W.argtypes = [C.c_double, C.c_double]
         L.or_kernel_dWdH.restype = C.c_double
@@ -66,8 +89,9 @@ def lib():
         L.or_face.restype = None
         L.or_mfv_flux.restype = None
         L.or_mfv_flux_moving.restype = None
-        _lib = L
-    return _lib
+        L.or_threads.restype = C.c_int
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a):

@@ -3,6 +3,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
@@ -16,23 +18,35 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_cpu_baseline_reports_the_oracle_on_a_bounded_sample():
+    """A whole-set oracle pass over the median sub-cube of the set, single-
+    threaded and on the OpenMP build, with the host's CPU model."""
     import bench
     from paper_1712_01294_amd import workloads as W
-    w = W.jittered_sine(n_side=12)
-    out = bench.cpu_baseline(w, 0.5)
-    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "pairs/s"
-    assert out["value"] > 0.0
-    assert "targets" in out["sample"]
+    w = W.clustered(n_side=40, seed=W.SEED_BASE + 150)
+    subs = bench.cpu_sample(w)
+    assert len(subs) == 4 and len({p for _, p in subs}) == 4
+    ns = [sub.n for sub, _ in subs]
+    assert ns == sorted(ns) and 0 < ns[0] and ns[-1] < w.n
+    for sub, _ in subs:
+        assert sub.periodic == (0, 0, 0)
+        assert np.all((sub.x >= 0) & (sub.x < 0.125)) and np.all((sub.z >= 0) & (sub.z < 0.125))
+    one, omp = bench.cpu_baseline(w)
+    assert one["kind"] == "oracle" and one["cores"] == 1 and one["unit"] == "pairs/s"
+    assert omp["kind"] == "oracle_omp" and omp["cores"] >= 1
+    assert one["value"] > 0.0 and omp["value"] > 0.0
+    assert "sub-cube" in one["sample"] and one["cpu_model"]
 
 
 def test_algorithmic_units_and_fingerprint():
     import bench
     n, G, F, P = 1000, 20000, 30000, 15000
-    b, f = bench.algorithmic("hydro_fluxes", n, G, F, P)
-    assert b == 288.0 * n + 4.0 * F and f == 236.0 * P
-    b, f = bench.algorithmic("hydro_fluxes_mfv", n, G, F, P)
-    assert b == 296.0 * n + 4.0 * F and f == 310.0 * P
+    assert bench.algorithmic("solve_h", n, G, F, P, 5.0) == (48.0 * n, 20.0 * G * 5.0, 4.0 * G)
+    assert bench.algorithmic("gradients", n, G, F, P) == (264.0 * n, 65.0 * G, 4.0 * F)
+    assert bench.algorithmic("hydro_fluxes", n, G, F, P) == (288.0 * n, 400.0 * P, 4.0 * F)
+    assert bench.algorithmic("hydro_fluxes_mfv", n, G, F, P) == (296.0 * n, 475.0 * P, 4.0 * F)
+    assert bench.binding(0.01, 0.02) == "alu" and bench.binding(0.02, 0.01) == "hbm"
     fp = bench.source_fingerprint()
     assert len(fp) == 16 and int(fp, 16) >= 0
-    for (wl, k), v in bench.TRAFFIC.items():
-        assert v["bytes_per_launch"] > 0 and len(v["fingerprint"]) == 16
+    for table in (bench.TRAFFIC, bench.COUNTERS):
+        for (wl, k), v in table.items():
+            assert len(v["fingerprint"]) == 16
