@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 
 // ---------------------------------------------------------------- gradients
 // Record of one particle for the flux kernel (32 slots, one or two cache lines):
-// 0-2 x, y, z (FP64 record only) | 3 1/H | 4 K = V^2 8/(pi H^3) | 5 rho | 6 P | 7-9 v | 10-15 B |
+// 0-2 x, y, z (FP64 record; the FP32 record holds the FP64 pressure in 0-1) | 3 1/H | 4 K = V^2 8/(pi H^3) | 5 rho | 6 P | 7-9 v | 10-15 B |
 // 16-30 grad | 31 c.  With 1/H and K per particle a face needs no division for its kernel weights:
 // V^2 W(r, H) = K w(r/H).
 #ifndef MFM_FLUX32_WAVES
@@ -1075,7 +1075,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
         } else {
             float* rec = (float*)recp + (long long)i * 32;
             float v[32];
-            v[0] = v[1] = v[2] = 0.0f;
+            // slots 0-1: the pressure in FP64 (its two halves), for the pressure
+            // difference across a face; slot 2 unused
+            const long long pbits = __double_as_longlong(P_i);
+            v[0] = __int_as_float((int)(pbits & 0xffffffffll));
+            v[1] = __int_as_float((int)(pbits >> 32));
+            v[2] = 0.0f;
             v[R_IH] = (float)iH;
             v[R_K] = (float)(Vi * Vi * norm);
             v[R_RHO] = (float)rho_i;
@@ -1227,13 +1232,33 @@ __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T
         qL[f] = mL ? qm : qo;
         qR[f] = mL ? qo : qm;
     }
-    if (!(qL[0] > T(0)) || !(qL[4] > T(0)) || !(qR[0] > T(0)) || !(qR[4] > T(0))) {
+    const bool first = !(qL[0] > T(0)) || !(qL[4] > T(0)) || !(qR[0] > T(0)) || !(qR[4] > T(0));
+    if (first) {
 #pragma unroll
         for (int f = 0; f < 5; f++) {
             qL[f] = mL ? m[slot[f]] : o[slot[f]];
             qR[f] = mL ? o[slot[f]] : m[slot[f]];
         }
         out.fallback = 1;
+    }
+    // pressure difference across the face, P_R - P_L.  With FP32 records the
+    // centre pressures' difference is taken in FP64 first (each record carries
+    // its pressure in FP64): in dense, slow gas that difference is a small part
+    // of P, and rounding each face pressure to FP32 would swamp it (and with it
+    // the contact speed S*); the FP32 reconstruction offsets are added after.
+    T dPRL;
+    if constexpr (sizeof(T) == 8) {
+        dPRL = qR[4] - qL[4];
+    } else {
+        const double Pm = __longlong_as_double(((long long)__float_as_int(m[1]) << 32) |
+                                               (unsigned)__float_as_int(m[0]));
+        const double Po = __longlong_as_double(((long long)__float_as_int(o[1]) << 32) |
+                                               (unsigned)__float_as_int(o[0]));
+        const double dc = mL ? Po - Pm : Pm - Po;
+        // the offsets as the reconstruction formed them: (face - centre) per side
+        const T offL = first ? T(0) : qL[4] - (mL ? m[R_P] : o[R_P]);
+        const T offR = first ? T(0) : qR[4] - (mL ? o[R_P] : m[R_P]);
+        dPRL = (T)dc + (offR - offL);
     }
     // face frame: the mean of the two particle velocities (commutative)
     const T w[3] = {T(0.5) * (m[R_V0] + o[R_V0]), T(0.5) * (m[R_V0 + 1] + o[R_V0 + 1]),
@@ -1245,7 +1270,7 @@ __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T
     const T SL = (uL - cL < uR - cR) ? uL - cL : uR - cR;
     const T SR = (uL + cL > uR + cR) ? uL + cL : uR + cR;
     const T mLf = rL * (SL - uL), mRf = rR * (SR - uR);
-    const T Ss = (pR - pL + mLf * uL - mRf * uR) / (mLf - mRf);
+    const T Ss = (dPRL + mLf * uL - mRf * uR) / (mLf - mRf);
     if (MFV) {
         mfv_flux<T>(qL, qR, w, nh, uL, uR, SL, SR, Ss, gamma, Amag, out);
         return out;
