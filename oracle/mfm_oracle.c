@@ -59,6 +59,10 @@ typedef struct {
     double cond_max;  /* flag threshold on ||E||_F ||B||_F (R7) */
     double cell;      /* bucket grid cell size; <= 0 selects brute force */
     int32_t scheme;   /* 0: meshless finite mass (R15), 1: meshless finite volume */
+    int32_t limiter;  /* 0: per-particle limiter only (R10); 1: + pairwise face limiter (R23)
+                         and a condition-adaptive beta (R24) */
+    double beta_min;  /* R24: beta at cond(E) >= cond_hi (beta itself applies at <= cond_lo) */
+    double cond_lo, cond_hi;
 } or_params;
 
 /* threads a pass uses: 1, or the OpenMP team size of an OpenMP build */
@@ -430,6 +434,23 @@ static void invert_sym3(const double E[3][3], double B[3][3], double *det_out)
  * (limited), and optionally grad_raw (unlimited), alpha (5 x n limiter
  * factors), cond (||E||_F ||B||_F).  *n_illcond counts flagged particles.
  */
+/*
+ * R24: the per-particle limiter constant.  With the pairwise limiter on, a
+ * particle whose gradient matrix is well conditioned (cond <= cond_lo) keeps
+ * beta, one that is badly conditioned (cond >= cond_hi, or singular) takes
+ * beta_min, and in between beta moves linearly in log10(cond).  Without it,
+ * beta for every particle (R10).
+ */
+static double limiter_beta(const or_params *p, double kappa)
+{
+    if (!p->limiter) return p->beta;
+    double t;
+    if (kappa <= p->cond_lo) t = 0.0;
+    else if (kappa < p->cond_hi) t = (log10(kappa) - log10(p->cond_lo)) / (log10(p->cond_hi) - log10(p->cond_lo));
+    else t = 1.0;   /* at or above cond_hi, and a NaN condition number */
+    return p->beta + (p->beta_min - p->beta) * t;
+}
+
 /* R6-R8, R10 for one particle i; *ill = 1 when its E is flagged (R7) */
 static int gradients_one(const grid_t *g, const or_params *p, int64_t n, int64_t i, const double *m,
                          const double *vx, const double *vy, const double *vz, const double *u,
@@ -474,6 +495,7 @@ static int gradients_one(const grid_t *g, const or_params *p, int64_t n, int64_t
         }
     double kappa = sqrt(fe) * sqrt(fb);
     if (!(det > 0.0) || !(kappa <= p->cond_max)) *ill = 1;
+    double beta_i = limiter_beta(p, kappa);
     if (cond) cond[i] = kappa;
     B[0 * n + i] = Bm[0][0];
     B[1 * n + i] = Bm[0][1];
@@ -493,7 +515,7 @@ static int gradients_one(const grid_t *g, const or_params *p, int64_t n, int64_t
         if (gn > 0.0) {
             double up = (pmax[f] - phi_i[f]) / (gn * half_span);
             double dn = (phi_i[f] - pmin[f]) / (gn * half_span);
-            double lim = p->beta * (up < dn ? up : dn);
+            double lim = beta_i * (up < dn ? up : dn);
             al = lim < 1.0 ? lim : 1.0;
         }
         for (int a = 0; a < 3; a++) {
@@ -625,8 +647,41 @@ static void mfv_face_flux(const double qL[5], const double qR[5], const double w
     F[4] = Ff[4] + w[0] * Ff[1] + w[1] * Ff[2] + w[2] * Ff[3] + 0.5 * ww * Ff[0];
 }
 
+/*
+ * R23: the pairwise limiter on one face value.  f is the value side K
+ * extrapolated to the midpoint face, pk and po the centre values of K and of
+ * the other particle.  With lo/hi their min/max and D = hi - lo, the face
+ * value may not pass the midpoint interpolant (pk + po)/2 by more than psi2 D
+ * on the far side, nor leave [lo, hi] by more than psi1 D on the near side;
+ * an expanded bound that would change the sign of lo (hi) is replaced by
+ * lo / (1 + psi1 D / |lo|) (likewise for hi), so a positive field keeps
+ * positive face values.  Equal centre values give the centre value.
+ */
+#define OR_PSI1 0.5
+#define OR_PSI2 0.25
+
+static double pair_limit(double f, double pk, double po)
+{
+    if (pk == po) return pk;
+    double lo = pk < po ? pk : po, hi = pk < po ? po : pk;
+    double D = hi - lo;
+    double mid = 0.5 * (pk + po);
+    if (pk < po) {
+        double lb = lo - OR_PSI1 * D;
+        if (!(lb * lo > 0.0)) lb = lo / (1.0 + OR_PSI1 * D / fabs(lo));
+        double ub = mid + OR_PSI2 * D;
+        double v = f < ub ? f : ub;
+        return v > lb ? v : lb;
+    }
+    double ub = hi + OR_PSI1 * D;
+    if (!(ub * hi > 0.0)) ub = hi / (1.0 + OR_PSI1 * D / fabs(hi));
+    double lb = mid - OR_PSI2 * D;
+    double v = f > lb ? f : lb;
+    return v < ub ? v : ub;
+}
+
 static void pair_flux(const side_t *a, const side_t *b, const double d[3], double r,
-                      double gamma, int mfv, pairflux_t *out)
+                      double gamma, int mfv, int limiter, pairflux_t *out)
 {
     memset(out, 0, sizeof(*out));
     double Wa = or_kernel_W(r, a->H), Wb = or_kernel_W(r, b->H);
@@ -645,6 +700,11 @@ static void pair_flux(const side_t *a, const side_t *b, const double d[3], doubl
     for (int f = 0; f < 5; f++) {
         qL[f] = a->phi[f] + 0.5 * (a->g[f][0] * d[0] + a->g[f][1] * d[1] + a->g[f][2] * d[2]);
         qR[f] = b->phi[f] - 0.5 * (b->g[f][0] * d[0] + b->g[f][1] * d[1] + b->g[f][2] * d[2]);
+        if (limiter) {
+            /* R23 on each side's face value */
+            qL[f] = pair_limit(qL[f], a->phi[f], b->phi[f]);
+            qR[f] = pair_limit(qR[f], b->phi[f], a->phi[f]);
+        }
     }
     if (!(qL[0] > 0.0) || !(qL[4] > 0.0) || !(qR[0] > 0.0) || !(qR[4] > 0.0)) {
         for (int f = 0; f < 5; f++) { qL[f] = a->phi[f]; qR[f] = b->phi[f]; }
@@ -702,7 +762,7 @@ void or_hllc_star(double gamma, double rL, double uL, double pL, double rR, doub
     double w = 0.5 * (uL + uR);
     double d[3] = {1.0, 0.0, 0.0};
     pairflux_t o;
-    pair_flux(&a, &b, d, 1.0, gamma, 0, &o);
+    pair_flux(&a, &b, d, 1.0, gamma, 0, 0, &o);
     *Sstar = o.Sstar + w;
     *Pstar = o.Pstar;
 }
@@ -729,7 +789,7 @@ void or_mfv_flux_moving(double gamma, double vL, double vR, double rL, double uL
     b.g[1][0] = 2.0 * (vR - uR);     /* qR = vR - g/2 = uR */
     double d[3] = {1.0, 0.0, 0.0};
     pairflux_t o;
-    pair_flux(&a, &b, d, 1.0, gamma, 1, &o);
+    pair_flux(&a, &b, d, 1.0, gamma, 1, 0, &o);
     double Amag = 2.0 * or_kernel_W(1.0, 2.0);
     F[0] = o.Fm / Amag;
     F[1] = o.Fp[0] / Amag;
@@ -778,11 +838,11 @@ static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i,
         pairflux_t o;
         double s;
         if (i < j) {
-            pair_flux(&si, &sj, L->a[k].d, r, p->gamma, p->scheme == 1, &o);
+            pair_flux(&si, &sj, L->a[k].d, r, p->gamma, p->scheme == 1, p->limiter, &o);
             s = 1.0;
         } else {
             double dn[3] = {-L->a[k].d[0], -L->a[k].d[1], -L->a[k].d[2]};
-            pair_flux(&sj, &si, dn, r, p->gamma, p->scheme == 1, &o);
+            pair_flux(&sj, &si, dn, r, p->gamma, p->scheme == 1, p->limiter, &o);
             s = -1.0;
         }
         *nfall += o.fallback;
@@ -844,6 +904,12 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
     grid_free(&g);
     return rc;
 }
+
+/* Exported for the tests: R23 on one face value (see pair_limit). */
+double or_pair_limit(double f, double pk, double po) { return pair_limit(f, pk, po); }
+
+/* Exported for the tests: R24's limiter constant at a condition number. */
+double or_limiter_beta(const or_params *p, double kappa) { return limiter_beta(p, kappa); }
 
 /* Exported for the tests: the face vector A_ab of one pair from given sides. */
 void or_face(double Ha, double Va, const double *Ba6, double Hb, double Vb, const double *Bb6,

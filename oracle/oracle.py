@@ -34,7 +34,8 @@ _u8p = C.POINTER(C.c_uint8)
 class OrParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("n_ngb", C.c_double), ("box", C.c_double * 3),
                 ("periodic", C.c_int32 * 3), ("beta", C.c_double), ("cond_max", C.c_double),
-                ("cell", C.c_double), ("scheme", C.c_int32)]
+                ("cell", C.c_double), ("scheme", C.c_int32), ("limiter", C.c_int32),
+                ("beta_min", C.c_double), ("cond_lo", C.c_double), ("cond_hi", C.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -90,6 +91,9 @@ def lib():
         L.or_mfv_flux.restype = None
         L.or_mfv_flux_moving.restype = None
         L.or_threads.restype = C.c_int
+        L.or_pair_limit.restype = C.c_double
+        L.or_pair_limit.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_limiter_beta.restype = C.c_double
         _libs[key] = L
     return _libs[key]
 
@@ -125,6 +129,10 @@ class Setup:
     cond_max: float = 1.0e6
     cell: float = 0.0       # 0: brute-force neighbour search
     scheme: str = "mfm"     # "mfm" (zero mass flux) or "mfv" (full HLLC flux, mass changes)
+    limiter: int = 0        # 1: pairwise face limiter (R23) and condition-adaptive beta (R24)
+    beta_min: float = 1.0   # R24: beta at cond(E) >= cond_hi
+    cond_lo: float = 10.0   # R24: beta applies at cond(E) <= cond_lo
+    cond_hi: float = 1000.0
 
     @classmethod
     def of(cls, w, cell=None, **kw):
@@ -146,6 +154,10 @@ class Setup:
         p.cond_max = self.cond_max
         p.cell = self.cell
         p.scheme = {"mfm": 0, "mfv": 1}[self.scheme]
+        p.limiter = int(self.limiter)
+        p.beta_min = self.beta_min
+        p.cond_lo = self.cond_lo
+        p.cond_hi = self.cond_hi
         return p
 
 
@@ -269,6 +281,17 @@ def mfv_flux_moving(gamma, v_particles, left, right):
                              C.c_double(left[0]), C.c_double(left[1]), C.c_double(left[2]),
                              C.c_double(right[0]), C.c_double(right[1]), C.c_double(right[2]), _p(F))
     return F
+
+
+def pair_limit(f, pk, po):
+    """R23 on one face value f extrapolated by side K (centre pk; other side po)."""
+    return lib().or_pair_limit(float(f), float(pk), float(po))
+
+
+def limiter_beta(s: Setup, cond):
+    """R24: the per-particle limiter constant at condition number cond."""
+    p = s.c()
+    return lib().or_limiter_beta(C.byref(p), C.c_double(cond))
 
 
 def face(Ha, Va, Ba6, Hb, Vb, Bb6, d):
