@@ -75,6 +75,12 @@ typedef struct {
     int32_t max_ngb;       /* flux-list slots per particle (<= 0: 256)                 */
     int32_t tree_levels;   /* cell-table depth (<= 0: from n)                          */
     int32_t scheme;        /* mfm_scheme                                               */
+    int32_t limiter;       /* 0: per-particle limiter only (R10, first order on a
+                              non-positive face state, R12); 1: also the pairwise
+                              face limiter (R23) and a condition-adaptive beta (R24) */
+    double beta_min;       /* R24: limiter constant at cond(E) >= cond_hi               */
+    double cond_lo;        /* R24: beta applies at cond(E) <= cond_lo                   */
+    double cond_hi;        /* R24: between the two, beta moves linearly in log10(cond)  */
 } mfm_params;
 
 /*
@@ -127,9 +133,9 @@ typedef struct {
 } mfm_counters;
 
 /* Create a context for up to `capacity` particles.  Validates params:
- * gamma > 1, n_ngb > 32/3, box > 0, beta > 0, scheme MFM or MFV.  Allocates
- * scratch on the
- * current HIP device.  *out is NULL on failure. */
+ * gamma > 1, n_ngb > 32/3, box > 0, beta > 0, scheme MFM or MFV, limiter 0 or
+ * 1 (with limiter 1: beta_min > 0 and 0 < cond_lo < cond_hi).  Allocates
+ * scratch on the current HIP device.  *out is NULL on failure. */
 mfm_status mfm_create(const mfm_params *params, int64_t capacity, mfm_ctx **out);
 
 /* Free the context's scratch (synchronises its device).  NULL is a no-op. */
@@ -160,7 +166,10 @@ mfm_status mfm_solve_h(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * d = half the largest gather distance.  Requires mfm_solve_h.
  * MFM_MIXED: the pairwise kernel weights W are FP32; the moments E, the
  * gradient sums and the inverse stay FP64; the per-particle record that the
- * flux kernel reads (state, B, limited gradients) is stored in FP32. */
+ * flux kernel reads (state, B, limited gradients) is stored in FP32.
+ * limiter = 1 (reading R24): beta is replaced per particle by
+ * beta + (beta_min - beta) t, t = 0 at cond(E) <= cond_lo, 1 at >= cond_hi
+ * (and for a singular E), linear in log10(cond) between. */
 mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* Fluxes (readings R9, R11-R16, R18): per unordered pair in canonical order
@@ -176,7 +185,13 @@ mfm_status mfm_gradients(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * then the full HLLC flux (F_L, F_L + S_L (U*_L - U_L), F_R + S_R (U*_R - U_R)
  * or F_R by the signs of S_L, S*, S_R) in the face frame, taken back to the lab
  * frame; dm (required) receives the mass rate; no P* clamp applies.  With
- * MFM_MIXED this flux is formed in FP32 like the MFM one, dm summed in FP64. */
+ * MFM_MIXED this flux is formed in FP32 like the MFM one, dm summed in FP64.
+ * limiter = 1 (reading R23): each side's reconstructed face value of each
+ * field is bounded by the two centre values phi_K, phi_O (lo, hi, D = hi - lo):
+ * on the side of the other particle by the midpoint interpolant + D/4, on its
+ * own side by the centre range widened by D/2 (a widened bound that would
+ * change sign is lo / (1 + D / (2|lo|)), likewise for hi), so positive fields
+ * keep positive face states. */
 mfm_status mfm_hydro_fluxes(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
 /* solve_h + gradients + hydro_fluxes on already-ordered particles. */
@@ -198,7 +213,8 @@ mfm_status mfm_hydro_pass(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * kick updates m, v and u in place. */
 mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, void *stream);
 
-/* Adjoint of the pass (reading R20): given the adjoints adj_dp (3 x n) and
+/* Adjoint of the pass (reading R20; MFM scheme with limiter 0 only, else
+ * MFM_E_INVALID): given the adjoints adj_dp (3 x n) and
  * adj_dE (n) of the pass outputs, write the adjoints of its inputs adj_x
  * (3 x n), adj_v (3 x n) and adj_u (n) = (dF/d(x, v, u))^T (adj_dp, adj_dE),
  * FP64, at fixed neighbour sets.  The kernel length enters by the

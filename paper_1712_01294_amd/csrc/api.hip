@@ -171,6 +171,8 @@ static bool params_valid(const mfm_params& p) {
         if (!(p.box[d] > 0.0) || (p.periodic[d] != 0 && p.periodic[d] != 1)) return false;
     if (p.precision != MFM_FP64 && p.precision != MFM_MIXED) return false;
     if (p.scheme != MFM_SCHEME_MFM && p.scheme != MFM_SCHEME_MFV) return false;
+    if (p.limiter != 0 && p.limiter != 1) return false;
+    if (p.limiter && (!(p.beta_min > 0.0) || !(p.cond_lo > 0.0) || !(p.cond_hi > p.cond_lo))) return false;
     return true;
 }
 
@@ -187,6 +189,10 @@ static void init_params(mfm_ctx* c, const mfm_params& p) {
     }
     c->ph.h_maxit = p.h_maxit > 0 ? p.h_maxit : 64;
     c->ph.max_ngb = p.max_ngb > 0 ? p.max_ngb : 256;
+    c->ph.limiter = p.limiter;
+    c->ph.beta_min = p.beta_min;
+    c->ph.cond_lo = p.cond_lo;
+    c->ph.cond_hi = p.cond_hi;
     setup_tree(c);
 }
 
@@ -643,7 +649,8 @@ extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p,
                                              void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
-    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme only");
+    if (c->p.scheme != MFM_SCHEME_MFM || c->p.limiter)
+        return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme with the per-particle limiter only");
     if (!adj_dp || !adj_dE || !adj_x || !adj_v || !adj_u) return fail(c, MFM_E_INVALID, "null adjoint array");
     if (!p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
         return fail(c, MFM_E_INVALID, "the pass adjoint needs the forward outputs nk, V, B, rho, P, grad");
@@ -663,7 +670,8 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
                                        void* stream) {
     mfm_status st = check_particles(c, ck);
     if (st) return st;
-    if (c->p.scheme != MFM_SCHEME_MFM) return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme only");
+    if (c->p.scheme != MFM_SCHEME_MFM || c->p.limiter)
+        return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme with the per-particle limiter only");
     if ((st = check_particles(c, w))) return st;
     if (w->n != ck->n) return fail(c, MFM_E_INVALID, "checkpoint and work sets differ in size");
     if (!(dt > 0.0)) return fail(c, MFM_E_INVALID, "the step adjoint needs a fixed dt > 0");

@@ -37,6 +37,8 @@ struct Phys {
     int periodic[3];
     int h_maxit;
     int max_ngb;
+    int limiter;          // 1: pairwise face limiter and condition-adaptive beta
+    double beta_min, cond_lo, cond_hi;
 };
 
 // Device counters (all updated with atomics, read by the host after a sync).

@@ -1002,6 +1002,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
             flag_index(cnt, i);
         }
         if (cond > 0.0) condbits = __double_as_longlong(cond);
+        // the limiter constant: beta, or with the optional limiters (R24) beta moved
+        // towards beta_min linearly in log10(cond) between cond_lo and cond_hi
+        double beta = ph.beta;
+        if (ph.limiter) {
+            double t;
+            if (cond <= ph.cond_lo) t = 0.0;
+            else if (cond < ph.cond_hi) t = (log10(cond) - log10(ph.cond_lo)) / (log10(ph.cond_hi) - log10(ph.cond_lo));
+            else t = 1.0;
+            beta = ph.beta + (ph.beta_min - ph.beta) * t;
+        }
         double g[15];
         double al[5];
         const double half = 0.5 * rmax;
@@ -1018,7 +1028,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
                 if (gn > 0.0) {
                     const double up = (pmax[f] - phi_i[f]) / (gn * half);
                     const double dn = (phi_i[f] - pmin[f]) / (gn * half);
-                    alpha = fmin(1.0, ph.beta * fmin(up, dn));
+                    alpha = fmin(1.0, beta * fmin(up, dn));
                 }
             } else {
                 const float h0 = (float)g0, h1 = (float)g1, h2 = (float)g2;
@@ -1028,7 +1038,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WA
                     const float hf = (float)half;
                     const float up = (float)(pmax[f] - phi_i[f]) / (gn * hf);
                     const float dn = (float)(phi_i[f] - pmin[f]) / (gn * hf);
-                    af = fminf(1.0f, (float)ph.beta * fminf(up, dn));
+                    af = fminf(1.0f, (float)beta * fminf(up, dn));
                 }
                 alpha = (double)af;
             }
@@ -1196,7 +1206,33 @@ __device__ __forceinline__ void mfv_flux(const T qL[5], const T qR[5], const T w
     out.FE = (F[4] + w[0] * F[1] + w[1] * F[2] + w[2] * F[3] + T(0.5) * ww * F[0]) * Amag;
 }
 
-template <typename T, bool MFV>
+// The optional pairwise limiter (R23) on one side's face value f, with pk that
+// side's centre value and po the other's: on the other particle's side at most
+// D/4 past the midpoint interpolant, on its own side at most D/2 outside the
+// centre range [lo, hi] (D = hi - lo); a widened bound that would change sign is
+// lo / (1 + D / (2|lo|)) (hi likewise).  Each owner evaluates it with the same
+// arguments for the same side, so both copies of a pair agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T pair_limit(T f, T pk, T po) {
+    if (pk == po) return pk;
+    const T lo = pk < po ? pk : po, hi = pk < po ? po : pk;
+    const T D = hi - lo;
+    const T mid = T(0.5) * (pk + po);
+    if (pk < po) {
+        T lb = lo - T(0.5) * D;
+        if (!(lb * lo > T(0))) lb = lo / (T(1) + T(0.5) * D / (lo < T(0) ? -lo : lo));
+        const T ub = mid + T(0.25) * D;
+        const T v = f < ub ? f : ub;
+        return v > lb ? v : lb;
+    }
+    T ub = hi + T(0.5) * D;
+    if (!(ub * hi > T(0))) ub = hi / (T(1) + T(0.5) * D / (hi < T(0) ? -hi : hi));
+    const T lb = mid - T(0.25) * D;
+    const T v = f > lb ? f : lb;
+    return v < ub ? v : ub;
+}
+
+template <typename T, bool MFV, bool LIM>
 __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T* __restrict__ o, bool mL,
                                                 const T d[3], T r, T gamma) {
     PairOut<T> out;
@@ -1227,8 +1263,12 @@ __device__ __forceinline__ PairOut<T> pair_flux(const T* __restrict__ m, const T
     for (int f = 0; f < 5; f++) {
         const T* gm = m + R_G + 3 * f;
         const T* go = o + R_G + 3 * f;
-        const T qm = m[slot[f]] + sm * (gm[0] * d[0] + gm[1] * d[1] + gm[2] * d[2]);
-        const T qo = o[slot[f]] + (-sm) * (go[0] * d[0] + go[1] * d[1] + go[2] * d[2]);
+        T qm = m[slot[f]] + sm * (gm[0] * d[0] + gm[1] * d[1] + gm[2] * d[2]);
+        T qo = o[slot[f]] + (-sm) * (go[0] * d[0] + go[1] * d[1] + go[2] * d[2]);
+        if (LIM) {
+            qm = pair_limit<T>(qm, m[slot[f]], o[slot[f]]);
+            qo = pair_limit<T>(qo, o[slot[f]], m[slot[f]]);
+        }
         qL[f] = mL ? qm : qo;
         qR[f] = mL ? qo : qm;
     }
@@ -1312,7 +1352,7 @@ __device__ __forceinline__ void load_rec<float>(const float* __restrict__ rec, l
     }
 }
 
-template <typename T, bool MFV>
+template <typename T, bool MFV, bool LIM>
 __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
                                             const int* __restrict__ list, const T* __restrict__ rec,
                                             Counters* cnt) {
@@ -1358,7 +1398,7 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             // negation exactly, so both owners of the pair hold the same bits
             const double sg = iL ? 1.0 : -1.0;
             const T dT[3] = {(T)(sg * dij[0]), (T)(sg * dij[1]), (T)(sg * dij[2])};
-            PairOut<T> o = pair_flux<T, MFV>(ri, rj, iL, dT, (T)r, gam);
+            PairOut<T> o = pair_flux<T, MFV, LIM>(ri, rj, iL, dT, (T)r, gam);
             const double s = iL ? 1.0 : -1.0;
             if (MFV) accm -= s * (double)o.Fm;
             acc[0] -= s * (double)o.Fp[0];
@@ -1396,10 +1436,11 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
 #ifndef MFM_FLUX64_WAVES
 #define MFM_FLUX64_WAVES 2
 #endif
+template <bool LIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
-    fluxes_body<double, false>(a, ph, counts, list, rec, cnt);
+    fluxes_body<double, false, LIM>(a, ph, counts, list, rec, cnt);
 }
 
 // The finite-volume form, FP64 records only, at two waves per SIMD like the
@@ -1407,23 +1448,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_
 #ifndef MFM_FLUXMFV_WAVES
 #define MFM_FLUXMFV_WAVES MFM_FLUX64_WAVES
 #endif
+template <bool LIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUXMFV_WAVES))) void k_fluxes_mfv(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
-    fluxes_body<double, true>(a, ph, counts, list, rec, cnt);
+    fluxes_body<double, true, LIM>(a, ph, counts, list, rec, cnt);
 }
 
+template <bool LIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
 void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
                   const float* __restrict__ rec, Counters* cnt) {
-    fluxes_body<float, false>(a, ph, counts, list, rec, cnt);
+    fluxes_body<float, false, LIM>(a, ph, counts, list, rec, cnt);
 }
 
 // The finite-volume form on the FP32 records of the mixed form.
+template <bool LIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
 void k_fluxes_mfv_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
                       const float* __restrict__ rec, Counters* cnt) {
-    fluxes_body<float, true>(a, ph, counts, list, rec, cnt);
+    fluxes_body<float, true, LIM>(a, ph, counts, list, rec, cnt);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1460,16 +1504,25 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
 
+template <bool LIM>
+static void launch_fluxes_lim(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed,
+                              int mfv, const void* rec, Counters* cnt, hipStream_t s) {
+    if (mfv && mixed)
+        k_fluxes_mfv_f32<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+    else if (mfv)
+        k_fluxes_mfv<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+    else if (mixed)
+        k_fluxes_f32<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+    else
+        k_fluxes_f64<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+}
+
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed, int mfv,
                    const void* rec, Counters* cnt, hipStream_t s) {
-    if (mfv && mixed)
-        k_fluxes_mfv_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
-    else if (mfv)
-        k_fluxes_mfv<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
-    else if (mixed)
-        k_fluxes_f32<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
+    if (ph.limiter)
+        launch_fluxes_lim<true>(a, ph, counts, list, mixed, mfv, rec, cnt, s);
     else
-        k_fluxes_f64<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+        launch_fluxes_lim<false>(a, ph, counts, list, mixed, mfv, rec, cnt, s);
 }
 
 }  // namespace mfm

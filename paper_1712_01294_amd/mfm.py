@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("box", C.c_double * 3), ("periodic", C.c_int32 * 3), ("precision", C.c_int32),
                 ("beta", C.c_double), ("cond_max", C.c_double), ("u_floor", C.c_double),
                 ("h_maxit", C.c_int32), ("max_ngb", C.c_int32), ("tree_levels", C.c_int32),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("limiter", C.c_int32), ("beta_min", C.c_double),
+                ("cond_lo", C.c_double), ("cond_hi", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -133,6 +134,10 @@ class Config:
     max_ngb: int = 256
     tree_levels: int = 0
     scheme: int = SCHEME_MFM
+    limiter: int = 0          # 1: pairwise face limiter (R23) and condition-adaptive beta (R24)
+    beta_min: float = 1.0
+    cond_lo: float = 10.0
+    cond_hi: float = 1000.0
 
     def c(self) -> Params:
         p = Params()
@@ -150,6 +155,10 @@ class Config:
         p.max_ngb = self.max_ngb
         p.tree_levels = self.tree_levels
         p.scheme = int(self.scheme)
+        p.limiter = int(self.limiter)
+        p.beta_min = self.beta_min
+        p.cond_lo = self.cond_lo
+        p.cond_hi = self.cond_hi
         return p
 
 
