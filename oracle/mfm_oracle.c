@@ -818,11 +818,16 @@ static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i,
                       const double *vy, const double *vz, const double *H, const double *V,
                       const double *B, const double *rho, const double *P, const double *grad,
                       double hmax, nbr_list *L, double *dp, double *dE, double *vsig, double *dm,
+                      const int64_t *bins, int64_t lmin, int64_t nlev, double *lev,
                       int64_t *npair, int64_t *nfall, int64_t *nclamp)
 {
     double R = H[i] > hmax ? H[i] : hmax;
     int rc = grid_find(g, i, R, L);
     if (rc) return rc;
+    /* R25: the sums of the due levels start again; the others keep their values */
+    if (bins)
+        for (int64_t l = lmin; l < nlev; l++)
+            for (int c = 0; c < 5; c++) lev[(l * 5 + c) * n + i] = 0.0;
     double acc[4] = {0, 0, 0, 0}, accm = 0.0;
     double ci = sqrt(p->gamma * P[i] / rho[i]);
     double vs = 0.0;
@@ -833,6 +838,18 @@ static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i,
         double r = L->a[k].r;
         if (j == i) continue;
         if (!(r < H[i] || r < H[j])) continue;
+        double cj = sqrt(p->gamma * P[j] / rho[j]);
+        const double *d = L->a[k].d; /* x_j - x_i */
+        double proj = ((vx[i] - vx[j]) * (-d[0]) + (vy[i] - vy[j]) * (-d[1]) +
+                       (vz[i] - vz[j]) * (-d[2])) / r;
+        double sig = ci + cj - (proj < 0.0 ? proj : 0.0);
+        if (sig > vs) vs = sig;
+        /* R25: a pair's level is the finer bin of its two particles; only due levels */
+        int64_t lev_ij = 0;
+        if (bins) {
+            lev_ij = bins[i] > bins[j] ? bins[i] : bins[j];
+            if (lev_ij < lmin) continue;
+        }
         (*npair)++;
         load_side(&sj, j, n, H, V, B, rho, vx, vy, vz, P, grad);
         pairflux_t o;
@@ -850,12 +867,11 @@ static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i,
         for (int c = 0; c < 3; c++) acc[c] -= s * o.Fp[c];
         acc[3] -= s * o.FE;
         accm -= s * o.Fm;
-        double cj = sqrt(p->gamma * P[j] / rho[j]);
-        const double *d = L->a[k].d; /* x_j - x_i */
-        double proj = ((vx[i] - vx[j]) * (-d[0]) + (vy[i] - vy[j]) * (-d[1]) +
-                       (vz[i] - vz[j]) * (-d[2])) / r;
-        double sig = ci + cj - (proj < 0.0 ? proj : 0.0);
-        if (sig > vs) vs = sig;
+        if (bins) {
+            for (int c = 0; c < 3; c++) lev[(lev_ij * 5 + c) * n + i] -= s * o.Fp[c];
+            lev[(lev_ij * 5 + 3) * n + i] -= s * o.FE;
+            lev[(lev_ij * 5 + 4) * n + i] -= s * o.Fm;
+        }
     }
     dp[0 * n + i] = acc[0];
     dp[1 * n + i] = acc[1];
@@ -866,11 +882,20 @@ static int fluxes_one(const grid_t *g, const or_params *p, int64_t n, int64_t i,
     return OR_OK;
 }
 
-int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
-              const double *z, const double *vx, const double *vy, const double *vz,
-              const double *H, const double *V, const double *B, const double *rho,
-              const double *P, const double *grad, const uint8_t *mask, double hmax,
-              double *dp, double *dE, double *vsig, int64_t *counts, double *dm)
+/*
+ * As or_fluxes, with R25's levels when bins is not NULL: pair {i, j} has level
+ * max(bins[i], bins[j]); only pairs of level >= lmin are evaluated (and
+ * counted), dp, dE, dm summing those; lev (5 x nlev x n, [(l * 5 + c) * n + i],
+ * c = dp x, y, z, dE, dm) receives each particle's sums per level for the
+ * levels >= lmin and keeps its values for the others.  vsig covers every
+ * flux neighbour.
+ */
+int or_fluxes_levels(const or_params *p, int64_t n, const double *x, const double *y,
+                     const double *z, const double *vx, const double *vy, const double *vz,
+                     const double *H, const double *V, const double *B, const double *rho,
+                     const double *P, const double *grad, const uint8_t *mask, double hmax,
+                     double *dp, double *dE, double *vsig, int64_t *counts, double *dm,
+                     const int64_t *bins, int64_t lmin, int64_t nlev, double *lev)
 {
     grid_t g;
     int rc = grid_build(&g, p, n, x, y, z);
@@ -887,7 +912,7 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
                 e = rc;
                 if (e) continue;
                 e = fluxes_one(&g, p, n, i, vx, vy, vz, H, V, B, rho, P, grad, hmax, &L, dp, dE, vsig, dm,
-                               &npair, &nfall, &nclamp);
+                               bins, lmin, nlev, lev, &npair, &nfall, &nclamp);
                 if (e) {
 #pragma omp atomic write
                     rc = e;
@@ -903,6 +928,16 @@ int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
     }
     grid_free(&g);
     return rc;
+}
+
+int or_fluxes(const or_params *p, int64_t n, const double *x, const double *y,
+              const double *z, const double *vx, const double *vy, const double *vz,
+              const double *H, const double *V, const double *B, const double *rho,
+              const double *P, const double *grad, const uint8_t *mask, double hmax,
+              double *dp, double *dE, double *vsig, int64_t *counts, double *dm)
+{
+    return or_fluxes_levels(p, n, x, y, z, vx, vy, vz, H, V, B, rho, P, grad, mask, hmax, dp, dE, vsig,
+                            counts, dm, NULL, 0, 0, NULL);
 }
 
 /* Exported for the tests: R23 on one face value (see pair_limit). */

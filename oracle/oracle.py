@@ -86,6 +86,7 @@ def lib():
         L.or_solve_h.restype = C.c_int
         L.or_gradients.restype = C.c_int
         L.or_fluxes.restype = C.c_int
+        L.or_fluxes_levels.restype = C.c_int
         L.or_hllc_star.restype = None
         L.or_face.restype = None
         L.or_mfv_flux.restype = None
@@ -217,7 +218,9 @@ def gradients(s: Setup, st: dict, H, nk, V, mask=None):
                 n_illcond=int(nill.value))
 
 
-def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None):
+def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None, bins=None, lmin=0, lev=None):
+    """Fluxes of every flux pair (R9-R16); with bins (R25) only the pairs of
+    level >= lmin, their per-level sums written into lev (5, nlev, n), in place."""
     n = st["x"].size
     a = {k: _f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz")}
     H, V = _f64(H), _f64(V)
@@ -233,19 +236,30 @@ def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None):
     if hmax is None:
         hmax = float(np.max(H if mask is None else H[H > 0]))
     p = s.c()
-    _check(lib().or_fluxes(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
-                           _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
-                           _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
-                           _p(dE), _p(vsig), _p(counts), _p(dm)), "fluxes")
+    if bins is None:
+        _check(lib().or_fluxes(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
+                               _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
+                               _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
+                               _p(dE), _p(vsig), _p(counts), _p(dm)), "fluxes")
+    else:
+        b = np.ascontiguousarray(bins, dtype=np.int64)
+        assert lev.dtype == np.float64 and lev.flags.c_contiguous and lev.shape[0] == 5 * (int(b.max()) + 1) \
+            or lev.shape[:2] == (int(b.max()) + 1, 5)
+        _check(lib().or_fluxes_levels(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
+                                      _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
+                                      _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
+                                      _p(dE), _p(vsig), _p(counts), _p(dm), _p(b), C.c_int64(lmin),
+                                      C.c_int64(lev.shape[0]), _p(lev)), "fluxes")
     return dict(dp=dp.reshape(3, n), dE=dE, dm=dm, vsig=vsig, pair_entries=int(counts[0]),
                 fallbacks=int(counts[1]), clamps=int(counts[2]))
 
 
-def hydro_pass(s: Setup, st: dict, H_guess=None):
-    """Full pass on every particle: kernel lengths, gradients, fluxes."""
+def hydro_pass(s: Setup, st: dict, H_guess=None, bins=None, lmin=0, lev=None):
+    """Full pass on every particle: kernel lengths, gradients, fluxes (with bins,
+    the fluxes of the due levels only, R25; see fluxes)."""
     H, nk, V, it = solve_h(s, st["x"], st["y"], st["z"], H_guess)
     g = gradients(s, st, H, nk, V)
-    f = fluxes(s, st, H, V, g)
+    f = fluxes(s, st, H, V, g, bins=bins, lmin=lmin, lev=lev)
     out = dict(H=H, nk=nk, V=V, iters=it)
     out.update(g)
     out.update(f)
@@ -353,12 +367,87 @@ class Stepper:
         self.H = None
         self.last = None
         self.floors = 0
+        self.bins = None
+        self.lev = None
 
-    def _pass(self, x, y, z, vx, vy, vz, u, m=None):
+    def _pass(self, x, y, z, vx, vy, vz, u, m=None, lmin=None):
         st = dict(x=x, y=y, z=z, m=self.st["m"] if m is None else m, vx=vx, vy=vy, vz=vz, u=u)
-        out = hydro_pass(self.s, st, self.H)
+        if lmin is None:
+            out = hydro_pass(self.s, st, self.H)
+        else:
+            out = hydro_pass(self.s, st, self.H, bins=self.bins, lmin=lmin, lev=self.lev)
         self.H = out["H"]
         return out
+
+    # ---------------------------------------------------------------- R25
+    def set_bins(self, bins):
+        """Power-of-two time bins (R25): particle i steps by T / 2^bins[i].  The
+        per-level rates of the current state are (re)computed by a levelled
+        pass on it: all levels due."""
+        self.bins = np.ascontiguousarray(bins, dtype=np.int64)
+        nlev = int(self.bins.max()) + 1
+        self.lev = np.zeros((nlev, 5, self.bins.size))
+        st = self.st
+        self.last = self._pass(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"], lmin=0)
+        return self.last
+
+    def hier_step(self, T):
+        """One system step of length T with hierarchical power-of-two steps
+        (R25).  With B the largest bin, time advances in 2^B sub-steps of
+        T / 2^B; every particle drifts with its current velocity on each.  A
+        pair {i, j} has level l = max(bins) and step T / 2^l; at a sub-step
+        boundary the levels whose step divides the time elapsed are due.  At
+        each due boundary the pass evaluates the due pairs on the predicted
+        state (velocities and energies advanced by the half kicks the due
+        levels are about to receive, with their previous rates), then each due
+        level's new rates close its pair step with a half kick and, before
+        the end of T, open the next with another; both particles of a pair
+        receive the same kick with opposite signs.  All levels are due at the
+        start and at the end of T.  The MFM form: masses are constant."""
+        assert self.s.scheme == "mfm" and self.lev is not None
+        st, lev = self.st, self.lev
+        m = st["m"]
+        nlev = lev.shape[0]
+        B = nlev - 1
+        K = 1 << B
+        delta = T / K
+        dts = [T / (1 << l) for l in range(nlev)]
+        v = [st[k] for k in ("vx", "vy", "vz")]
+        E = m * (st["u"] + 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
+
+        def kick(v, E, levels):
+            for l in levels:
+                v = [v[c] + 0.5 * dts[l] * lev[l, c] / m for c in range(3)]
+                E = E + 0.5 * dts[l] * lev[l, 3]
+            return v, E
+
+        # opening half kicks of every level
+        v, E = kick(v, E, range(nlev))
+        x = [st["x"], st["y"], st["z"]]
+        out = self.last
+        for k in range(1, K + 1):
+            # drift every particle by one sub-step, wrapped into the box
+            st.update(x=x[0], y=x[1], z=x[2])
+            x = self._drift(v, delta)
+            tz = (k & -k).bit_length() - 1
+            lmin = max(0, B - tz)
+            due = range(lmin, nlev)
+            # predicted state: the due levels' closing kicks with their previous rates
+            vp, Ep = kick(v, E, due)
+            up = Ep / m - 0.5 * (vp[0] ** 2 + vp[1] ** 2 + vp[2] ** 2)
+            up = np.maximum(up, self.u_floor)
+            out = self._pass(x[0], x[1], x[2], vp[0], vp[1], vp[2], up, lmin=lmin)
+            # closing half kicks of the due levels, then the opening ones of their next step
+            v, E = kick(v, E, due)
+            if k < K:
+                v, E = kick(v, E, due)
+        u = E / m - 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+        low = u < self.u_floor
+        self.floors += int(np.count_nonzero(low))
+        u = np.where(low, self.u_floor, u)
+        st.update(x=x[0], y=x[1], z=x[2], vx=v[0], vy=v[1], vz=v[2], u=u)
+        self.last = out
+        return T
 
     def cfl_dt(self, out):
         return self.cfl * float(np.min(out["H"] / out["vsig"]))
