@@ -213,6 +213,38 @@ mfm_status mfm_hydro_pass(mfm_ctx *ctx, mfm_particles *p, void *stream);
  * kick updates m, v and u in place. */
 mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, void *stream);
 
+/* Hierarchical power-of-two time steps (reading R25; the paper's section 3
+ * runs particles on individual time steps): one system step of length T.
+ * bins (device, int64, n, in the particles' current order; REORDERED IN PLACE
+ * with them) gives each particle its bin 0 .. max_bin (max_bin <= 7); particle
+ * i steps by
+ * T / 2^bins[i].  A pair's level is the finer bin of its two particles and its
+ * step T / 2^level.  Time advances in 2^max_bin sub-steps of T / 2^max_bin:
+ * every particle drifts on each; at a sub-step boundary the levels whose step
+ * divides the elapsed time are due, and only their pairs are evaluated, on the
+ * state predicted with those levels' previous rates; each due level's new
+ * rates close its pair step with a half kick and, before the end of T, open
+ * the next one with another, applied with opposite signs to the two
+ * particles of a pair (momentum and energy are conserved to rounding).
+ * Kernel lengths and gradients are recomputed for every particle at each
+ * boundary.  The per-level rates live in the context (allocated on the first
+ * call, 32 doubles per particle); they are computed by a pass over the
+ * current state with every level due when rebin != 0, on the first call, when
+ * max_bin changes, or after any other pass on the context.  With max_bin = 0
+ * the call performs mfm_step's operations for a fixed dt = T (in separate
+ * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64
+ * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE hold the rates of the
+ * last boundary (every level due) and the counters those of its pass. */
+mfm_status mfm_step_hier(mfm_ctx *ctx, mfm_particles *p, int64_t *bins, int32_t max_bin, double T, int32_t rebin,
+                         void *stream);
+
+/* Copy the per-level rates that the last mfm_step_hier left (those of its last
+ * boundary, every level due) into out (device, FP64, 4 x nlev x n,
+ * out[(l * 4 + c) * n + i], c: dp x, y, z, dE; nlev = max_bin + 1), in the
+ * current particle order.  MFM_E_STATE if there are none (no hierarchical
+ * step yet, or another pass since). */
+mfm_status mfm_copy_levels(mfm_ctx *ctx, double *out, void *stream);
+
 /* Adjoint of the pass (reading R20; MFM scheme with limiter 0 only, else
  * MFM_E_INVALID): given the adjoints adj_dp (3 x n) and
  * adj_dE (n) of the pass outputs, write the adjoints of its inputs adj_x

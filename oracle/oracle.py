@@ -243,8 +243,8 @@ def fluxes(s: Setup, st: dict, H, V, g: dict, mask=None, hmax=None, bins=None, l
                                _p(dE), _p(vsig), _p(counts), _p(dm)), "fluxes")
     else:
         b = np.ascontiguousarray(bins, dtype=np.int64)
-        assert lev.dtype == np.float64 and lev.flags.c_contiguous and lev.shape[0] == 5 * (int(b.max()) + 1) \
-            or lev.shape[:2] == (int(b.max()) + 1, 5)
+        assert lev.dtype == np.float64 and lev.flags.c_contiguous and lev.ndim == 3 and lev.shape[1] == 5
+        assert lev.shape[0] >= int(b.max()) + 1 and lev.shape[2] == n
         _check(lib().or_fluxes_levels(C.byref(p), C.c_int64(n), _p(a["x"]), _p(a["y"]), _p(a["z"]),
                                       _p(a["vx"]), _p(a["vy"]), _p(a["vz"]), _p(H), _p(V), _p(B),
                                       _p(rho), _p(P), _p(grad), _p(mk), C.c_double(hmax), _p(dp),
@@ -380,12 +380,14 @@ class Stepper:
         return out
 
     # ---------------------------------------------------------------- R25
-    def set_bins(self, bins):
-        """Power-of-two time bins (R25): particle i steps by T / 2^bins[i].  The
-        per-level rates of the current state are (re)computed by a levelled
-        pass on it: all levels due."""
+    def set_bins(self, bins, max_bin=None):
+        """Power-of-two time bins (R25): particle i steps by T / 2^bins[i], with
+        levels 0 .. max_bin (default the largest bin).  The per-level rates of
+        the current state are (re)computed by a levelled pass on it: all
+        levels due."""
         self.bins = np.ascontiguousarray(bins, dtype=np.int64)
-        nlev = int(self.bins.max()) + 1
+        nlev = (int(self.bins.max()) if max_bin is None else int(max_bin)) + 1
+        assert nlev >= int(self.bins.max()) + 1
         self.lev = np.zeros((nlev, 5, self.bins.size))
         st = self.st
         self.last = self._pass(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"], lmin=0)

@@ -47,6 +47,8 @@ struct mfm_ctx {
     double *dt_part = nullptr, *dt_out = nullptr;
     Counters* cnt = nullptr;
     double* adj = nullptr;                // adjoint scratch, kAdjSlots x cap, allocated on first use
+    double* lev = nullptr;                // per-level rates of hierarchical steps, 4 (kMaxBin+1) x cap, on first use
+    int have_levels = 0, lev_nlev = 0;    // lev holds the rates of the current order, for lev_nlev levels
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
@@ -229,7 +231,7 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj, c->lev};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -390,6 +392,7 @@ static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {
                    c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, ev.first, ev.second, s);
     c->have_h = 1;
     c->have_grad = c->have_flux = 0;
+    c->have_levels = 0;
     c->last = s;
     return launched(c, "solve_h");
 }
@@ -762,6 +765,99 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
     c->last = s;
     return launched(c, "step_adjoint");
+}
+
+// ------------------------------------------------------------ hierarchical steps
+static mfm_status do_fluxes_levels(mfm_ctx* c, mfm_particles* p, const long long* bins, int lmin, int nlev,
+                                   hipStream_t s) {
+    if (!c->have_grad || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_gradients must run first");
+    PassArrays a = arrays_of(p);
+    launch_fluxes_levels(a, c->ph, c->counts, c->list, c->rec, c->cnt, bins, lmin, nlev, c->lev, s);
+    c->have_flux = 1;
+    c->last = s;
+    return launched(c, "hydro_fluxes (levels)");
+}
+
+extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins, int32_t max_bin, double T,
+                                    int32_t rebin, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (c->p.scheme != MFM_SCHEME_MFM || c->p.precision != MFM_FP64)
+        return fail(c, MFM_E_INVALID, "hierarchical steps cover the MFM scheme in FP64");
+    if (!bins) return fail(c, MFM_E_INVALID, "bins is required");
+    if (max_bin < 0 || max_bin > kMaxBin) return fail(c, MFM_E_INVALID, "max_bin must lie in 0 .. 7");
+    if (!(T > 0.0) || !isfinite(T)) return fail(c, MFM_E_INVALID, "T must be positive and finite");
+    if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
+        return fail(c, MFM_E_INVALID, "hierarchical steps need every pass output array");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = p->n;
+    if (!c->lev && (st = hip_check(c, hipMalloc((void**)&c->lev, sizeof(double) * 4 * (kMaxBin + 1) * c->cap),
+                                   "level rates")))
+        return st;
+    const int nlev = max_bin + 1;
+    long long* b = (long long*)bins;
+    double* extra[kGatherMax * 2];
+    auto levels_extra = [&](int first) {
+        int k = first;
+        for (int q = 0; q < 4 * nlev; q++) extra[k++] = c->lev + (long long)q * n;
+        return k;
+    };
+    reset_counters(c, s);
+    if (rebin || !c->have_levels || c->lev_nlev != nlev || c->n_tree != p->n) {
+        // the per-level rates of the current state, every level due
+        extra[0] = (double*)b;
+        if ((st = build(c, p, s, extra, 1))) return st;
+        if ((st = do_solve_h(c, p, s))) return st;
+        if ((st = do_gradients(c, p, s))) return st;
+        if ((st = do_fluxes_levels(c, p, b, 0, nlev, s))) return st;
+    } else if (!c->have_flux) {
+        return fail(c, MFM_E_STATE, "hierarchical steps continue from a hierarchical step on this state");
+    }
+    const int K = 1 << max_bin;
+    const double delta = T / (double)K;
+    launch_hier_begin((int)n, p->m, p->vx, p->vy, p->vz, p->u, c->Ehalf, c->lev, nlev, T, s);
+    PassArrays a = arrays_of(p);
+    for (int k = 1; k <= K; k++) {
+        launch_hier_drift(a, c->ph, delta, s);
+        const int tz = __builtin_ctz((unsigned)k);
+        const int lmin = max_bin - tz > 0 ? max_bin - tz : 0;
+        launch_hier_predict((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, lmin, nlev, T, c->p.u_floor, c->vp,
+                            c->up, s);
+        extra[0] = c->vp;
+        extra[1] = c->vp + n;
+        extra[2] = c->vp + 2 * n;
+        extra[3] = c->up;
+        extra[4] = c->Ehalf;
+        extra[5] = (double*)b;
+        const int ne = levels_extra(6);
+        if ((st = build(c, p, s, extra, ne))) return st;
+        mfm_particles q = *p;
+        q.vx = c->vp;
+        q.vy = c->vp + n;
+        q.vz = c->vp + 2 * n;
+        q.u = c->up;
+        if ((st = do_solve_h(c, &q, s))) return st;
+        if ((st = do_gradients(c, &q, s))) return st;
+        if ((st = do_fluxes_levels(c, &q, b, lmin, nlev, s))) return st;
+        a = arrays_of(p);
+        launch_hier_kick((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, lmin, nlev, T, k < K ? 2 : 1, s);
+    }
+    launch_hier_finish((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->p.u_floor, p->u, c->cnt, s);
+    c->have_levels = 1;
+    c->lev_nlev = nlev;
+    c->last = s;
+    return launched(c, "step_hier");
+}
+
+extern "C" mfm_status mfm_copy_levels(mfm_ctx* c, double* out, void* stream) {
+    if (!c || !out) return MFM_E_INVALID;
+    if (!c->have_levels || !c->lev) return fail(c, MFM_E_STATE, "no per-level rates (run mfm_step_hier first)");
+    (void)hipSetDevice(c->device);
+    const long long n = c->n_tree;
+    return hip_check(c, hipMemcpyAsync(out, c->lev, sizeof(double) * 4 * c->lev_nlev * n, hipMemcpyDeviceToDevice,
+                                       (hipStream_t)stream),
+                     "copy levels");
 }
 
 // ------------------------------------------------- whole pass without allocation

@@ -58,6 +58,11 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
                       hipStream_t s);
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list,
                    int mixed, int mfv, const void* rec, Counters* cnt, hipStream_t s);
+// hierarchical steps: the pairs of level >= lmin (level = the finer bin of the
+// two), their per-level sums into lev[(l * 4 + c) * n + i] (FP64 records, MFM)
+constexpr int kMaxBin = 7;
+void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts, const int* list, const void* rec,
+                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev, hipStream_t s);
 
 // step.hip
 void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor,
@@ -71,6 +76,21 @@ void launch_kick2_mfv(const PassArrays& a, double dt, double u_floor, const doub
 void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts,
                    double* out, hipStream_t s);
 int dt_min_parts(int n);
+// hierarchical steps: E = m (u + |v|^2/2) into E and the opening kicks of every
+// level (begin); kicks of the levels >= lmin with their sums in lev, each of
+// weight T / 2^(l+1), applied `times` times (v and E in place); drift
+// x += dt v; predicted v, u of the pass; the recovery u = E/m - |v|^2/2
+// (floored) at the end
+void launch_hier_begin(int n, const double* m, double* vx, double* vy, double* vz, const double* u, double* E,
+                       const double* lev, int nlev, double T, hipStream_t s);
+void launch_hier_kick(int n, const double* m, double* vx, double* vy, double* vz, double* E, const double* lev,
+                      int lmin, int nlev, double T, int times, hipStream_t s);
+void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s);
+void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
+                         const double* E, const double* lev, int lmin, int nlev, double T, double u_floor,
+                         double* vp, double* up, hipStream_t s);
+void launch_hier_finish(int n, const double* m, const double* vx, const double* vy, const double* vz,
+                        const double* E, double u_floor, double* u, Counters* cnt, hipStream_t s);
 
 // adjoint.hip
 // Adjoint scratch, doubles per particle: 0-27 pass accumulators, 28-55 step

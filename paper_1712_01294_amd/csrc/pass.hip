@@ -1352,10 +1352,23 @@ __device__ __forceinline__ void load_rec<float>(const float* __restrict__ rec, l
     }
 }
 
-template <typename T, bool MFV, bool LIM>
+// Hierarchical steps (the levelled pass): a pair {i, j} has level max(bin_i,
+// bin_j); only pairs of level >= lmin are evaluated, and each particle's sums
+// per level go to lev[(l * 4 + c) * n + i] (c: dp x, y, z, dE) for the levels
+// >= lmin, the others keeping their values.  The sums of levels bin_i ..
+// bin_i + kLevWin - 1 (a particle's pairs are never coarser than its own bin)
+// are kept in registers; finer levels are summed in place in lev.
+constexpr int kLevWin = 4;
+struct Levels {
+    const long long* bin;
+    int lmin, nlev;
+    double* lev;
+};
+
+template <typename T, bool MFV, bool LIM, bool LEV = false>
 __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
                                             const int* __restrict__ list, const T* __restrict__ rec,
-                                            Counters* cnt) {
+                                            Counters* cnt, Levels lv = Levels{nullptr, 0, 0, nullptr}) {
     cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
@@ -1372,6 +1385,17 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         double vs = 0.0;
         const T gam = (T)ph.gamma;
         const int cnum = counts[i];
+        int bi = 0;
+        double lacc[kLevWin][4];
+        if (LEV) {
+            bi = (int)lv.bin[i];
+#pragma unroll
+            for (int w = 0; w < kLevWin; w++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) lacc[w][c] = 0.0;
+            for (int l = max(lv.lmin, bi + kLevWin); l < lv.nlev; l++)
+                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = 0.0;
+        }
         // the next list entry is loaded one pair ahead, so the record loads of
         // a pair do not wait for its index
         int jn = cnum > 0 ? list[i] : 0;
@@ -1394,6 +1418,21 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             displacement(ph, xi, xj[0], xj[1], xj[2], dij);   // x_j - x_i
             const double r = sqrt(dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2]);
             const bool iL = i < j;
+            // signal speed over every flux neighbour, due or not
+            auto signal = [&]() {
+                const double cj = (double)rj[R_C];
+                const double proj = -((vi[0] - (double)rj[R_V0]) * dij[0] + (vi[1] - (double)rj[R_V0 + 1]) * dij[1] +
+                                      (vi[2] - (double)rj[R_V0 + 2]) * dij[2]) / r;
+                vs = fmax(vs, ci + cj - fmin(proj, 0.0));
+            };
+            int lj = 0;
+            if (LEV) {
+                lj = max(bi, (int)lv.bin[j]);
+                if (lj < lv.lmin) {   // the pair is not due
+                    signal();
+                    continue;
+                }
+            }
             // canonical displacement x_R - x_L: the minimum image commutes with
             // negation exactly, so both owners of the pair hold the same bits
             const double sg = iL ? 1.0 : -1.0;
@@ -1407,10 +1446,31 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             acc[3] -= s * (double)o.FE;
             nfall += o.fallback;
             nclamp += o.clamp;
-            const double cj = (double)rj[R_C];
-            const double proj = -((vi[0] - (double)rj[R_V0]) * dij[0] + (vi[1] - (double)rj[R_V0 + 1]) * dij[1] +
-                                  (vi[2] - (double)rj[R_V0 + 2]) * dij[2]) / r;
-            vs = fmax(vs, ci + cj - fmin(proj, 0.0));
+            signal();
+            if (LEV) {
+                const double F[4] = {(double)o.Fp[0], (double)o.Fp[1], (double)o.Fp[2], (double)o.FE};
+                const int w = lj - bi;
+                if (w < kLevWin) {
+#pragma unroll
+                    for (int q = 0; q < kLevWin; q++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) lacc[q][c] = (q == w) ? lacc[q][c] - s * F[c] : lacc[q][c];
+                } else {
+                    for (int c = 0; c < 4; c++) lv.lev[((long long)lj * 4 + c) * n + i] -= s * F[c];
+                }
+            }
+        }
+        if (LEV) {
+#pragma unroll
+            for (int w = 0; w < kLevWin; w++) {
+                const int l = bi + w;
+                if (l >= lv.lmin && l < lv.nlev)
+#pragma unroll
+                    for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = lacc[w][c];
+            }
+            // due levels coarser than the particle's own bin hold no pair of it
+            for (int l = lv.lmin; l < min(bi, lv.nlev); l++)
+                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = 0.0;
         }
         a.dp[i] = acc[0];
         a.dp[n + i] = acc[1];
@@ -1441,6 +1501,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
     fluxes_body<double, false, LIM>(a, ph, counts, list, rec, cnt);
+}
+
+// The levelled pass of hierarchical steps (MFM, FP64 records).
+template <bool LIM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_levels(
+    PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
+    const double* __restrict__ rec, Counters* cnt, Levels lv) {
+    fluxes_body<double, false, LIM, true>(a, ph, counts, list, rec, cnt, lv);
 }
 
 // The finite-volume form, FP64 records only, at two waves per SIMD like the
@@ -1515,6 +1583,15 @@ static void launch_fluxes_lim(const PassArrays& a, const Phys& ph, const int* co
         k_fluxes_f32<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const float*)rec, cnt);
     else
         k_fluxes_f64<LIM><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt);
+}
+
+void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts, const int* list, const void* rec,
+                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev, hipStream_t s) {
+    const Levels lv{bin, lmin, nlev, lev};
+    if (ph.limiter)
+        k_fluxes_levels<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt, lv);
+    else
+        k_fluxes_levels<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt, lv);
 }
 
 void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const int* list, int mixed, int mfv,

@@ -149,6 +149,118 @@ __global__ void k_kick2_mfv(PassArrays a, double dt, double u_floor, const doubl
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt->floors, s);
 }
 
+// ------------------------------------------------------------ hierarchical steps
+// The per-level rates of particle i sit at lev[(l * 4 + c) * n + i] (c: dp x, y,
+// z, dE); level l steps by T / 2^l.  The expressions follow k_kick_drift and
+// k_kick2 term by term, so with a single level the sequence of operations is
+// the global step's.
+
+// start of a step: total energy E = m (u + |v|^2/2), then the opening half kicks
+// of every level (in registers, as k_kick_drift forms E and kicks it)
+__global__ void k_hier_begin(int n, const double* __restrict__ m, double* __restrict__ vx, double* __restrict__ vy,
+                             double* __restrict__ vz, const double* __restrict__ u, double* __restrict__ E,
+                             const double* __restrict__ lev, int nlev, double T) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long nn = n;
+    const double mi = m[i];
+    double v[3] = {vx[i], vy[i], vz[i]};
+    double e = mi * (u[i] + 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    for (int l = 0; l < nlev; l++) {
+        const double dt = T / (double)(1ll << l);
+        for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + i] / mi;
+        e = e + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + i];
+    }
+    vx[i] = v[0];
+    vy[i] = v[1];
+    vz[i] = v[2];
+    E[i] = e;
+}
+
+// half kicks of the levels lmin .. nlev-1, `times` times over (a closing and an opening kick)
+__global__ void k_hier_kick(int n, const double* __restrict__ m, double* __restrict__ vx, double* __restrict__ vy,
+                            double* __restrict__ vz, double* __restrict__ E, const double* __restrict__ lev, int lmin,
+                            int nlev, double T, int times) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long nn = n;
+    const double mi = m[i];
+    double v[3] = {vx[i], vy[i], vz[i]};
+    double e = E[i];
+    for (int t = 0; t < times; t++)
+        for (int l = lmin; l < nlev; l++) {
+            const double dt = T / (double)(1ll << l);
+            for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + i] / mi;
+            e = e + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + i];
+        }
+    vx[i] = v[0];
+    vy[i] = v[1];
+    vz[i] = v[2];
+    E[i] = e;
+}
+
+// drift by dt with the current velocity, wrapped into the box
+__global__ void k_hier_drift(PassArrays a, Phys ph, double dt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double v[3] = {a.vx[i], a.vy[i], a.vz[i]};
+    double* xs[3] = {(double*)a.x, (double*)a.y, (double*)a.z};
+    for (int c = 0; c < 3; c++) {
+        double xc = xs[c][i] + dt * v[c];
+        if (ph.periodic[c]) {
+            const double L = ph.box[c];
+            xc = xc - L * floor(xc / L);
+            if (xc >= L) xc = 0.0;
+        }
+        xs[c][i] = xc;
+    }
+}
+
+// predicted velocity and u for the pass: the due levels' kicks with their previous rates
+__global__ void k_hier_predict(int n, const double* __restrict__ m, const double* __restrict__ vx,
+                               const double* __restrict__ vy, const double* __restrict__ vz,
+                               const double* __restrict__ E, const double* __restrict__ lev, int lmin, int nlev,
+                               double T, double u_floor, double* __restrict__ vp, double* __restrict__ up) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long nn = n;
+    const double mi = m[i];
+    double q[3] = {vx[i], vy[i], vz[i]};
+    double Ep = E[i];
+    for (int l = lmin; l < nlev; l++) {
+        const double dt = T / (double)(1ll << l);
+        for (int c = 0; c < 3; c++) q[c] = q[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + i] / mi;
+        Ep = Ep + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + i];
+    }
+    double uu = Ep / mi - 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    uu = fmax(uu, u_floor);
+    vp[i] = q[0];
+    vp[nn + i] = q[1];
+    vp[2 * nn + i] = q[2];
+    up[i] = uu;
+}
+
+// u = E/m - |v|^2/2 at the end of the step, floored (and counted)
+__global__ void k_hier_finish(int n, const double* __restrict__ m, const double* __restrict__ vx,
+                              const double* __restrict__ vy, const double* __restrict__ vz,
+                              const double* __restrict__ E, double u_floor, double* __restrict__ u, Counters* cnt) {
+    cnt = counter_copy(cnt);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long fl = 0;
+    if (i < n) {
+        const double v[3] = {vx[i], vy[i], vz[i]};
+        double uu = E[i] / m[i] - 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (uu < u_floor) {
+            uu = u_floor;
+            fl = 1;
+        }
+        u[i] = uu;
+    }
+    unsigned long long s = fl;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt->floors, s);
+}
+
 // min_i H_i / vsig_i: per-block partial minima, then one block over the partials
 __global__ __launch_bounds__(256) void k_dt_partial(int n, const double* __restrict__ H,
                                                      const double* __restrict__ vsig, double* __restrict__ part) {
@@ -203,6 +315,31 @@ void launch_kick_drift_mfv(const PassArrays& a, const Phys& ph, double dt, doubl
 void launch_kick2_mfv(const PassArrays& a, double dt, double u_floor, const double* Ehalf, double* u,
                       Counters* cnt, hipStream_t s) {
     k_kick2_mfv<<<(a.n + 255) / 256, 256, 0, s>>>(a, dt, u_floor, Ehalf, u, cnt);
+}
+
+void launch_hier_begin(int n, const double* m, double* vx, double* vy, double* vz, const double* u, double* E,
+                       const double* lev, int nlev, double T, hipStream_t s) {
+    k_hier_begin<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, u, E, lev, nlev, T);
+}
+
+void launch_hier_kick(int n, const double* m, double* vx, double* vy, double* vz, double* E, const double* lev,
+                      int lmin, int nlev, double T, int times, hipStream_t s) {
+    k_hier_kick<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, lmin, nlev, T, times);
+}
+
+void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s) {
+    k_hier_drift<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt);
+}
+
+void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
+                         const double* E, const double* lev, int lmin, int nlev, double T, double u_floor,
+                         double* vp, double* up, hipStream_t s) {
+    k_hier_predict<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, lmin, nlev, T, u_floor, vp, up);
+}
+
+void launch_hier_finish(int n, const double* m, const double* vx, const double* vy, const double* vz,
+                        const double* E, double u_floor, double* u, Counters* cnt, hipStream_t s) {
+    k_hier_finish<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, u_floor, u, cnt);
 }
 
 void launch_dt_min(int n, const double* H, const double* vsig, double* partial, int nparts, double* out,

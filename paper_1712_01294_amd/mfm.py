@@ -25,7 +25,7 @@ EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "
            "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
            "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_set_kernel_timing", "mfm_kernel_time",
-           "mfm_hydro_pass_noalloc")
+           "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels")
 
 # kernels that mfm_kernel_time can report (mfm_kernel)
 KERNELS = {"solve_h": 0, "gradients": 1, "hydro_fluxes": 2}
@@ -100,6 +100,8 @@ def lib() -> C.CDLL:
         L.mfm_set_kernel_timing.argtypes = [vp, C.c_int]
         L.mfm_kernel_time.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.mfm_hydro_pass_noalloc.argtypes = [C.POINTER(Params), C.POINTER(Particles), C.POINTER(Counters), vp]
+        L.mfm_step_hier.argtypes = [vp, C.POINTER(Particles), vp, C.c_int32, C.c_double, C.c_int32, vp]
+        L.mfm_copy_levels.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -253,6 +255,22 @@ class Context:
         used = C.c_double(0.0)
         self._rc(self._L.mfm_step(self.h, C.byref(p), C.c_double(dt), C.byref(used), _stream(stream)))
         return used.value
+
+    def step_hier(self, st: State, bins, max_bin: int, T: float, rebin: bool = False, stream=None):
+        """One system step of length T with hierarchical power-of-two steps
+        (mfm_step_hier); bins (int64 device tensor, n) is reordered with st."""
+        if bins.dtype != torch.int64 or not bins.is_cuda or not bins.is_contiguous():
+            raise ValueError("bins must be a contiguous int64 device tensor")
+        p = st.struct()
+        self._rc(self._L.mfm_step_hier(self.h, C.byref(p), C.c_void_p(bins.data_ptr()), C.c_int32(max_bin),
+                                       C.c_double(T), C.c_int32(1 if rebin else 0), _stream(stream)))
+
+    def levels(self, n: int, nlev: int, stream=None):
+        """The per-level rates of the last hierarchical step's last boundary,
+        (nlev, 4, n): dp x, y, z and dE per level, in the current order."""
+        out = torch.empty(nlev, 4, n, dtype=torch.float64, device="cuda")
+        self._rc(self._L.mfm_copy_levels(self.h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
 
     def pass_adjoint(self, st: State, adj_dp, adj_dE, stream=None):
         """(dF/d(x, v, u))^T (adj_dp, adj_dE) for the pass last run on st;

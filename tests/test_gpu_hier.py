@@ -1,0 +1,147 @@
+"""Hierarchical power-of-two time steps on the GPU (mfm_step_hier, through the
+C ABI) against the oracle's hierarchical stepper (R25), and against the
+library's own global step when every particle shares one bin."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1712_01294_amd import workloads as W
+
+from .gpu_util import in_input_order, nerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _smooth(n_side, seed):
+    w0 = W.jittered_sine(n_side=n_side, seed=seed)
+    tp = 2.0 * np.pi
+    return dataclasses.replace(w0, vx=0.5 * np.sin(tp * w0.y), vy=0.5 * np.sin(tp * w0.z),
+                               vz=0.5 * np.sin(tp * w0.x))
+
+
+def _gpu(w, **kw):
+    from paper_1712_01294_amd import mfm
+    ctx = mfm.Context(mfm.config_of(w, u_floor=0.0, **kw), w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    return ctx, st
+
+
+def test_one_bin_is_the_global_step():
+    """max_bin = 0: the hierarchical step performs the global step's operations
+    in separate kernels (the global step fuses kick, drift and prediction in one,
+    where the compiler contracts a few products into fused multiply-adds
+    differently), so after three steps the two agree to rounding; on the oracle
+    the same reduction is bitwise."""
+    import torch
+    w = _smooth(16, W.SEED_BASE + 170)
+    c1, s1 = _gpu(w)
+    c2, s2 = _gpu(w)
+    bins = torch.zeros(w.n, dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        c1.step(s1, 1e-3)
+        c2.step_hier(s2, bins, 0, 1e-3)
+    c1.check()
+    c2.check()
+    assert torch.equal(s1.id, s2.id)
+    diffs = {k: float((getattr(s1, k) - getattr(s2, k)).abs().max() / getattr(s1, k).abs().max()) for k in
+             ("x", "y", "z", "vx", "vy", "vz", "u", "H", "dp", "dE", "vsig")}
+    print("one bin vs global step:", diffs, flush=True)
+    assert all(v <= 1e-13 for v in diffs.values()), diffs
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_hierarchical_steps_match_oracle(levels):
+    """Two system steps with particles binned by x into `levels` bins, on a
+    4096-particle box with smooth velocities: positions, velocities, energies
+    and the last rates within 1e-10 normwise of the oracle's R25 stepper."""
+    import torch
+    w = _smooth(16, W.SEED_BASE + 171)
+    bins = np.minimum((w.x * levels).astype(np.int64), levels - 1)
+    T = 0.004
+    ref = O.Stepper(w, u_floor=0.0)
+    ref.set_bins(bins)
+    for _ in range(2):
+        ref.hier_step(T)
+    ctx, st = _gpu(w)
+    # bins in the particles' current (library) order
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    for k in range(2):
+        ctx.step_hier(st, b, levels - 1, T, rebin=(k == 0))
+    ctx.check()
+    L = np.array(w.box)
+    for c, k in enumerate(("x", "y", "z")):
+        d = in_input_order(st, k) - ref.st[k]
+        d -= L[c] * np.round(d / L[c])
+        assert np.abs(d).max() <= 1e-10 * L[c], k
+    vmax = max(np.abs(ref.st[k]).max() for k in ("vx", "vy", "vz"))
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= 1e-10 * vmax, k
+    assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
+    assert nerr(in_input_order(st, "dp"), ref.last["dp"]) <= 1e-10
+    assert nerr(in_input_order(st, "dE"), ref.last["dE"]) <= 1e-10
+    # the bins travelled with the particles, and the per-level rates of the last
+    # boundary equal the oracle's level by level
+    ids = st.id.cpu().numpy()
+    assert np.array_equal(b.cpu().numpy(), bins[ids])
+    lv = ctx.levels(w.n, levels).cpu().numpy()
+    lio = np.empty_like(lv)
+    lio[..., ids] = lv
+    assert nerr(lio, ref.lev[:, :4]) <= 1e-10
+
+
+def test_hierarchical_steps_conserve_on_the_shock_tube():
+    """The jittered small tube with the left half in bin 1 and the right half in
+    bin 0 (its wave speeds are the larger): 3 system steps, momentum and energy
+    conserved to rounding, and the state within 1e-10 of the oracle."""
+    import torch
+    w = W.shock_tube(n_yz=12, l_yz=12 / 64)
+    bins = (w.x < 1.0).astype(np.int64)
+    T = 0.004
+    ref = O.Stepper(w)
+    ref.set_bins(bins)
+    for _ in range(3):
+        ref.hier_step(T)
+    from paper_1712_01294_amd import mfm
+    ctx = mfm.Context(mfm.config_of(w), w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    for k in range(3):
+        ctx.step_hier(st, b, 1, T, rebin=(k == 0))
+    ctx.check()
+    m = st.m.cpu().numpy()
+    v = [getattr(st, k).cpu().numpy() for k in ("vx", "vy", "vz")]
+    u = st.u.cpu().numpy()
+    p0 = [float((w.m * getattr(w, k)).sum()) for k in ("vx", "vy", "vz")]
+    E0 = float((w.m * (w.u + 0.5 * (w.vx ** 2 + w.vy ** 2 + w.vz ** 2))).sum())
+    E = float((m * (u + 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2))).sum())
+    scale = float(np.abs(m * v[0]).sum())
+    for c in range(3):
+        assert abs(float((m * v[c]).sum()) - p0[c]) <= 1e-13 * scale
+    assert E == pytest.approx(E0, rel=1e-13)
+    vmax = np.abs(ref.st["vx"]).max()
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= 1e-10 * vmax, k
+    assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
+
+
+def test_hierarchical_step_argument_checks():
+    import torch
+
+    from paper_1712_01294_amd import mfm
+    w = W.jittered_sine(n_side=8)
+    ctx, st = _gpu(w)
+    b = torch.zeros(w.n, dtype=torch.int64, device="cuda")
+    for args in ((b, 8, 1e-3), (b, -1, 1e-3), (b, 1, 0.0)):
+        with pytest.raises(mfm.MFMError) as e:
+            ctx.step_hier(st, *args)
+        assert e.value.status == -1
+    cm, sm = _gpu(w, precision=mfm.MIXED)
+    with pytest.raises(mfm.MFMError) as e:
+        cm.step_hier(sm, b, 1, 1e-3)
+    assert e.value.status == -1
