@@ -340,14 +340,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_ADJ_PAI
 // sums, keeps the terms for i, and writes a record of what the terms for the
 // neighbours need; part two (one thread per j) walks j's flux list, which holds
 // every i whose gather set contains j, and adds the terms for j from the
-// records.  No thread writes another particle's sums except for the few
-// limiter extrema and the farthest neighbour, which take atomics in part one.
+// records.  No thread writes another particle's sums: the terms that i's
+// limiter gives single neighbours (the farthest one, which sets its length, and
+// the holders of each field's extrema) travel in i's record too, with those
+// neighbours' indices, and part two adds them when it meets i.  Every sum is
+// then taken in a fixed order and the reverse is bitwise deterministic.
 //
 // Record per particle (kRec doubles): x, y, z, H, V, phi (5), the adjoint of
-// E as a full 3x3 matrix (9), the adjoints of the gradient sums S (15).
+// E as a full 3x3 matrix (9), the adjoints of the gradient sums S (15); then
+// 12 int32 indices in 6 slots (the farthest neighbour, the holders of the 5
+// maxima and of the 5 minima; -1 where no term goes to a neighbour), the
+// adjoint of the limiter length, and the maxima's and minima's terms.
 constexpr int kRec = kAdjRec;
-enum { P_X = 0, P_H = 3, P_V = 4, P_PHI = 5, P_LE = 10, P_LS = 19 };
-static_assert(P_LS + 15 <= kRec, "record slots");
+enum { P_X = 0, P_H = 3, P_V = 4, P_PHI = 5, P_LE = 10, P_LS = 19, P_IDX = 34, P_LHALF = 40, P_LMAX = 41,
+       P_LMIN = 46 };
+static_assert(P_LMIN + 5 <= kRec, "record slots");
 // own-side adjoints of part one, read back by part two: phi (5), x (3)
 static_assert(kAdjOwn == 8, "own-side slots");
 
@@ -549,22 +556,31 @@ __global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, con
         for (int c = 0; c < 3; c++) lxi[c] -= ld[c];
         if (j == jr && r > 0.0)
             for (int c = 0; c < 3; c++) {
-                // the farthest neighbour sets the limiter's length: its term goes by atomic
+                // the farthest neighbour sets the limiter's length; its own term goes
+                // through the record (part two adds the same th for j)
                 const double th = 0.5 * lhalf * d[c] / r;
-                atomicAdd(&aj.acc_x[c * n + j], th);
                 lxi[c] -= th;
             }
     }
+    int* ix = (int*)(rc + P_IDX);
+    ix[0] = jr != i ? jr : -1;
+    rc[P_LHALF] = lhalf;
     for (int f = 0; f < 5; f++) {
+        int tmax = -1, tmin = -1;
         if (lmax[f] != 0.0) {
             if (jmax[f] == i) lphi_i[f] += lmax[f];
-            else atomicAdd(&aj.acc_phi[f * n + jmax[f]], lmax[f]);
+            else tmax = jmax[f];
         }
         if (lmin[f] != 0.0) {
             if (jmin[f] == i) lphi_i[f] += lmin[f];
-            else atomicAdd(&aj.acc_phi[f * n + jmin[f]], lmin[f]);
+            else tmin = jmin[f];
         }
+        ix[1 + f] = tmax;
+        ix[6 + f] = tmin;
+        rc[P_LMAX + f] = lmax[f];
+        rc[P_LMIN + f] = lmin[f];
     }
+    ix[11] = -1;
     for (int f = 0; f < 5; f++) pa.own[f * n + i] = lphi_i[f];
     for (int c = 0; c < 3; c++) pa.own[(5 + c) * n + i] = lxi[c];
     aj.acc_H[i] += lH;
@@ -600,6 +616,16 @@ __global__ __launch_bounds__(256) void k_adj_grad_pull(PassArrays a, Phys ph, co
         grad_pair_terms(d, r, Hi, rc[P_V], LE, lS, dphi, t, ld, lpsi, W, dWH);
         for (int f = 0; f < 5; f++) lphi[f] += t[f];
         for (int c = 0; c < 3; c++) lx[c] += ld[c];
+        // i's limiter terms addressed to j: its length (j the farthest) and extrema
+        const int* ix = (const int*)(rc + P_IDX);
+        if (ix[0] == j && r > 0.0) {
+            const double lhalf = rc[P_LHALF];
+            for (int c = 0; c < 3; c++) lx[c] += 0.5 * lhalf * d[c] / r;
+        }
+        for (int f = 0; f < 5; f++) {
+            if (ix[1 + f] == j) lphi[f] += rc[P_LMAX + f];
+            if (ix[6 + f] == j) lphi[f] += rc[P_LMIN + f];
+        }
     }
     for (int f = 0; f < 5; f++) aj.acc_phi[f * n + j] += lphi[f];
     for (int c = 0; c < 3; c++) aj.acc_x[c * n + j] += lx[c];

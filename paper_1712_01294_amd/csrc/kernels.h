@@ -96,7 +96,7 @@ void launch_hier_finish(int n, const double* m, const double* vx, const double* 
 // Adjoint scratch, doubles per particle: 0-27 pass accumulators, 28-55 step
 // reverse, then the per-particle records the pass reverse pulls through the
 // flux lists (kAdjRec) and its own-side terms (kAdjOwn).
-constexpr int kAdjRec = 36;
+constexpr int kAdjRec = 52;
 constexpr int kAdjOwn = 8;
 constexpr int kAdjPullOffset = 56;
 constexpr int kAdjSlots = kAdjPullOffset + kAdjRec + kAdjOwn;

@@ -85,14 +85,15 @@ def _loss_grads_gpu(w, steps, dt, u_floor):
     return float(L.detach()), v0.grad.cpu().numpy(), u0.grad.cpu().numpy()
 
 
-def test_two_step_adjoint_matches_torch_autograd():
-    """8^3 jittered box, two fixed-dt steps, L = sum m |v|^2 at the end:
-    gradients w.r.t. the initial v and u against autodiff of the reference."""
+@pytest.mark.parametrize("steps", [2, 10])
+def test_multi_step_adjoint_matches_torch_autograd(steps):
+    """8^3 jittered box, fixed dt = 1e-3, L = sum m |v|^2 at the end: gradients
+    w.r.t. the initial v and u against autodiff of the reference."""
     w = W.jittered_sine(n_side=8, seed=W.SEED_BASE + 141)
     u_floor = 1e-10 * float(np.mean(w.u))
-    Lt, gvt, gut = _loss_grads_torch(w, 2, 1e-3, u_floor)
-    Lg, gvg, gug = _loss_grads_gpu(w, 2, 1e-3, u_floor)
-    print("L", Lg, Lt, "errs v", nerr(gvg, gvt), "u", nerr(gug, gut), flush=True)
+    Lt, gvt, gut = _loss_grads_torch(w, steps, 1e-3, u_floor)
+    Lg, gvg, gug = _loss_grads_gpu(w, steps, 1e-3, u_floor)
+    print("steps", steps, "L", Lg, Lt, "errs v", nerr(gvg, gvt), "u", nerr(gug, gut), flush=True)
     assert abs(Lg - Lt) <= 1e-13 * abs(Lt)
     assert nerr(gvg, gvt) <= TOL_AD
     assert nerr(gug, gut) <= TOL_AD
@@ -101,7 +102,8 @@ def test_two_step_adjoint_matches_torch_autograd():
 @pytest.fixture(scope="module")
 def adjoint_box_grad():
     """64^3 jittered box, 10 fixed steps of dt = 1e-3, L = sum m |v|^2: the adjoint
-    gradient w.r.t. (v0, u0), and a function giving L(+) - L(-) for a direction."""
+    gradient w.r.t. (v0, u0), a function giving (L(+) - L(-)) / 2 eps for a
+    direction, and one giving L(a) - L(b) for two input sets."""
     import torch
 
     from paper_1712_01294_amd import autodiff
@@ -117,14 +119,16 @@ def adjoint_box_grad():
         out[:, st.id] = torch.stack([st.vx, st.vy, st.vz])
         return out
 
-    def central(d, eps):
-        # L(+) - L(-) accumulated particle by particle: the difference of the two
+    def diff(va, ua, vb, ub):
+        # L(a) - L(b) accumulated particle by particle: the difference of the two
         # sums would be quantised at the FP64 resolution of L itself
+        pa, pb = final_v(va, ua), final_v(vb, ub)
+        return float((m * ((pa - pb) * (pa + pb)).sum(0)).sum())
+
+    def central(d, eps):
         dv = torch.tensor(d[: 3 * w.n].reshape(3, w.n), device="cuda")
         du = torch.tensor(d[3 * w.n:], device="cuda")
-        vp = final_v(v0 + eps * dv, u0 + eps * du)
-        vm = final_v(v0 - eps * dv, u0 - eps * du)
-        return float((m * ((vp - vm) * (vp + vm)).sum(0)).sum()) / (2 * eps)
+        return diff(v0 + eps * dv, u0 + eps * du, v0 - eps * dv, u0 - eps * du) / (2 * eps)
 
     vr = v0.clone().requires_grad_(True)
     ur = u0.clone().requires_grad_(True)
@@ -132,60 +136,142 @@ def adjoint_box_grad():
     L = (m * (vk * vk).sum(0)).sum()
     L.backward()
     g = np.concatenate([vr.grad.cpu().numpy().ravel(), ur.grad.cpu().numpy()])
-    return w, g, central
+    return dict(w=w, g=g, central=central, diff=diff, v0=v0, u0=u0)
 
 
-def test_adjoint_box_finite_differences_unit_directions(adjoint_box_grad):
-    """16 seeded random unit directions in (v0, u0) (4N = 1,048,576 components),
-    central differences at eps = 1e-6, retried at 1e-7 when they miss (a neighbour
-    crossing the support edge moves the limiter's extrema: a jump, not an adjoint
-    error).  With unit directions the difference L(+) - L(-) is ~1e-13 of L and the
-    rounding of the forward pass bounds the agreement at about 1e-5 (the error
-    scales as 1/eps below eps = 1e-5); asserted at 2e-4, the values are reported."""
-    w, g, central = adjoint_box_grad
-    rng = np.random.default_rng(W.SEED_BASE + 4)
-    rels = []
-    for k in range(16):
-        d = rng.normal(size=4 * w.n)
-        d /= np.linalg.norm(d)
+def _fd_directions(box, directions, eps):
+    """Central differences (L(+eps d) - L(-eps d)) / 2 eps for each direction
+    (a dense vector over the 4N components (vx, vy, vz, u) in the input order)."""
+    return [box["central"](d, eps) for d in directions]
+
+
+def _particle_directions(n, count, seed):
+    """Unit directions, each supported on the (vx, vy, vz, u) of one random particle."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        i = int(rng.integers(n))
+        e = rng.normal(size=4)
+        d = np.zeros(4 * n)
+        d[np.arange(4) * n + i] = e / np.linalg.norm(e)
+        out.append((i, d))
+    return out
+
+
+def test_adjoint_box_finite_differences_64_particle_directions(adjoint_box_grad):
+    """The 64^3 box of 10 steps: 64 seeded unit directions, each supported on the
+    four inputs (v, u) of one random particle, central differences at one
+    eps = 4e-6 (no retries).  Every direction agrees within 1e-6 of the gradient's
+    norm on its support, |g_S| (the largest directional derivative a unit
+    direction on that support can have, so the bar does not shrink for
+    directions nearly orthogonal to g_S); the plain relative error is reported."""
+    box = adjoint_box_grad
+    w, g = box["w"], box["g"]
+    n = w.n
+    dirs = _particle_directions(n, 64, W.SEED_BASE + 4)
+    fds = _fd_directions(box, [d for _, d in dirs], 4e-6)
+    nrel, rel = [], []
+    for k, ((i, d), fd) in enumerate(zip(dirs, fds)):
+        gS = g[np.arange(4) * n + i]
         ad = float(g @ d)
-        best = None
-        for eps in (1e-6, 1e-7):
-            fd = central(d, eps)
-            rel = abs(fd - ad) / abs(ad)
-            best = rel if best is None else min(best, rel)
-            if rel <= 1e-6:
-                break
-        print(f"unit direction {k}: adjoint {ad:.12e} fd {fd:.12e} rel {best:.2e}", flush=True)
-        rels.append(best)
-    print("median", float(np.median(rels)), "max", max(rels), flush=True)
-    assert max(rels) <= 2e-4
+        nrel.append(abs(fd - ad) / np.linalg.norm(gS))
+        rel.append(abs(fd - ad) / abs(ad))
+        print(f"particle {i}: adjoint {ad:+.10e} fd {fd:+.10e} err/|g_S| {nrel[-1]:.2e} rel {rel[-1]:.2e}",
+              flush=True)
+    nrel, rel = np.array(nrel), np.array(rel)
+    print(f"within 1e-6 of |g_S|: {int((nrel <= 1e-6).sum())} of 64 (median {np.median(nrel):.2e}, "
+          f"max {nrel.max():.2e}); plain relative within 1e-6: {int((rel <= 1e-6).sum())} of 64 "
+          f"(median {np.median(rel):.2e})", flush=True)
+    assert np.all(nrel <= 1e-6), nrel
 
 
-def test_adjoint_box_finite_differences_local_directions(adjoint_box_grad):
-    """16 random unit directions supported on the (v, u) of 64 random particles,
-    eps = 1e-5 (retried at 2e-6): the larger per-particle signal takes most
-    directions to <= 1e-6 (9 of 16 when measured); the rest sit at the same
-    FP64 evaluation floor as the unit directions.  Median <= 1e-5, max <= 2e-4."""
-    w, g, central = adjoint_box_grad
-    rng = np.random.default_rng(W.SEED_BASE + 44)
-    rels = []
-    for k in range(16):
-        d = np.zeros(4 * w.n)
-        sel = rng.choice(w.n, 64, replace=False)
-        for c in range(4):
-            d[c * w.n + sel] = rng.normal(size=64)
-        d /= np.linalg.norm(d)
+def _global_directions(n, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = rng.normal(size=4 * n)
+        out.append(d / np.linalg.norm(d))
+    return out
+
+
+def test_adjoint_box_finite_differences_64_global_directions(adjoint_box_grad):
+    """The 64^3 box: 64 seeded unit directions over all 4N = 1,048,576 inputs,
+    central differences at eps = 4e-6 (no retries).  Along directions that move
+    every particle the difference quotient resolves the derivative only to
+    1e-6 .. 2e-5 at this size (measured: median 1.6e-6, max 1.6e-5; on the 8^3
+    box it does to 1e-7, and the same gradient meets 1e-6 on single-particle
+    directions here, so the gap is a property of the difference quotient of this
+    piecewise-smooth map over 262,144 particles, not of the adjoint).  The error
+    is taken relative to max(|<g, d>|, |g| / sqrt(4N)) (the second is the typical
+    directional derivative of a random unit direction); bars: median 5e-6,
+    every direction 5e-5."""
+    box = adjoint_box_grad
+    w, g = box["w"], box["g"]
+    dirs = _global_directions(w.n, 64, W.SEED_BASE + 4)
+    fds = _fd_directions(box, dirs, 4e-6)
+    typical = np.linalg.norm(g) / np.sqrt(4 * w.n)
+    errs = []
+    for k, (d, fd) in enumerate(zip(dirs, fds)):
         ad = float(g @ d)
-        best = None
-        for eps in (1e-5, 2e-6):
-            fd = central(d, eps)
-            rel = abs(fd - ad) / abs(ad)
-            best = rel if best is None else min(best, rel)
-            if rel <= 1e-6:
-                break
-        print(f"local direction {k}: adjoint {ad:.12e} fd {fd:.12e} rel {best:.2e}", flush=True)
-        rels.append(best)
-    print("median", float(np.median(rels)), "max", max(rels), flush=True)
-    assert float(np.median(rels)) <= 1e-5
-    assert max(rels) <= 2e-4
+        errs.append(abs(fd - ad) / max(abs(ad), typical))
+        print(f"direction {k}: adjoint {ad:+.10e} fd {fd:+.10e} err {errs[-1]:.2e}", flush=True)
+    errs = np.array(errs)
+    print(f"within 1e-6: {int((errs <= 1e-6).sum())} of 64; median {np.median(errs):.2e} max {errs.max():.2e}",
+          flush=True)
+    assert float(np.median(errs)) <= 5e-6
+    assert errs.max() <= 5e-5
+
+
+def test_adjoint_small_box_finite_differences_64_global_directions():
+    """The same 10-step run on the 8^3 box: 64 unit directions over all 2048
+    inputs, eps = 1e-6, every direction within 1e-6 (relative)."""
+    import torch
+
+    from paper_1712_01294_amd import autodiff
+    w = W.adjoint_box(n_side=8)
+    evo = autodiff.Evolution(w, w.steps, w.dt)
+    m = torch.tensor(w.m, device="cuda")
+    v0 = torch.tensor(np.stack([w.vx, w.vy, w.vz]), device="cuda")
+    u0 = torch.tensor(w.u, device="cuda")
+
+    def final_v(v, u):
+        st, _ = evo.run(v, u, keep=False)
+        out = torch.empty(3, w.n, dtype=torch.float64, device="cuda")
+        out[:, st.id] = torch.stack([st.vx, st.vy, st.vz])
+        return out
+
+    vr = v0.clone().requires_grad_(True)
+    ur = u0.clone().requires_grad_(True)
+    vk, uk = autodiff.MFMSteps.apply(vr, ur, evo)
+    (m * (vk * vk).sum(0)).sum().backward()
+    g = np.concatenate([vr.grad.cpu().numpy().ravel(), ur.grad.cpu().numpy()])
+    rels = []
+    for d in _global_directions(w.n, 64, W.SEED_BASE + 4):
+        dv = torch.tensor(d[: 3 * w.n].reshape(3, w.n), device="cuda")
+        du = torch.tensor(d[3 * w.n:], device="cuda")
+        pa, pb = final_v(v0 + 1e-6 * dv, u0 + 1e-6 * du), final_v(v0 - 1e-6 * dv, u0 - 1e-6 * du)
+        fd = float((m * ((pa - pb) * (pa + pb)).sum(0)).sum()) / 2e-6
+        ad = float(g @ d)
+        rels.append(abs(fd - ad) / abs(ad))
+    rels = np.array(rels)
+    print(f"8^3: median {np.median(rels):.2e} max {rels.max():.2e}", flush=True)
+    assert np.all(rels <= 1e-6), rels
+
+
+def test_adjoint_is_bitwise_deterministic():
+    """The reverse pass and step sum every term in a fixed order (no atomics):
+    two backward runs give the same bits."""
+    import torch
+
+    from paper_1712_01294_amd import autodiff
+    w = W.adjoint_box(n_side=24)
+    evo = autodiff.Evolution(w, 3, w.dt)
+    m = torch.tensor(w.m, device="cuda")
+    grads = []
+    for _ in range(2):
+        vr = torch.tensor(np.stack([w.vx, w.vy, w.vz]), device="cuda").requires_grad_(True)
+        ur = torch.tensor(w.u, device="cuda").requires_grad_(True)
+        vk, uk = autodiff.MFMSteps.apply(vr, ur, evo)
+        (m * (vk * vk).sum(0)).sum().backward()
+        grads.append((vr.grad.clone(), ur.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
