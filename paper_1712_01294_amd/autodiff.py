@@ -19,8 +19,10 @@ _CK = ("x", "y", "z", "m", "vx", "vy", "vz", "u", "H", "dp", "dE", "id")
 
 
 def _copy_state(dst: mfm.State, src: mfm.State):
-    for k in _CK:
-        getattr(dst, k).copy_(getattr(src, k))
+    # one multi-tensor copy per dtype instead of a copy per array
+    f64 = [k for k in _CK if k != "id"]
+    torch._foreach_copy_([getattr(dst, k) for k in f64], [getattr(src, k) for k in f64])
+    dst.id.copy_(src.id)
 
 
 class Evolution:
@@ -44,13 +46,9 @@ class Evolution:
         """Forward; v0 (3, n) and u0 (n) in the input order.  Returns the final
         state (library order) and the checkpoints if keep."""
         st = mfm.State(self.n, zero=False)
-        for k in ("x", "y", "z", "m"):
-            getattr(st, k).copy_(self.dev[k])
+        torch._foreach_copy_([st.x, st.y, st.z, st.m, st.vx, st.vy, st.vz, st.u],
+                             [self.dev["x"], self.dev["y"], self.dev["z"], self.dev["m"], v0[0], v0[1], v0[2], u0])
         st.H.zero_()                        # cold kernel-length start
-        st.vx.copy_(v0[0])
-        st.vy.copy_(v0[1])
-        st.vz.copy_(v0[2])
-        st.u.copy_(u0)
         self.ctx.build_neighbours(st)
         self.ctx.hydro_pass(st)
         cks = []

@@ -347,20 +347,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_ADJ_PAI
 // then taken in a fixed order and the reverse is bitwise deterministic.
 //
 // Record per particle (kRec doubles): x, y, z, H, V, phi (5), the adjoint of
-// E as a full 3x3 matrix (9), the adjoints of the gradient sums S (15); then
-// 12 int32 indices in 6 slots (the farthest neighbour, the holders of the 5
-// maxima and of the 5 minima; -1 where no term goes to a neighbour), the
-// adjoint of the limiter length, and the maxima's and minima's terms.
+// E as a full 3x3 matrix (9), the adjoints of the gradient sums S (15).  The
+// limiter terms addressed to single neighbours sit in a block of their own, so
+// that the records every pair reads stay small: 16 int32 indices per particle
+// in one 64-byte line (the farthest neighbour, the holders of the 5 maxima and
+// of the 5 minima; -1 where no term goes to a neighbour; 4 unused), read by
+// every pair, and 12 values (the adjoint of the limiter length, the maxima's
+// and the minima's terms; 1 unused), read only where an index matches.
 constexpr int kRec = kAdjRec;
-enum { P_X = 0, P_H = 3, P_V = 4, P_PHI = 5, P_LE = 10, P_LS = 19, P_IDX = 34, P_LHALF = 40, P_LMAX = 41,
-       P_LMIN = 46 };
-static_assert(P_LMIN + 5 <= kRec, "record slots");
+enum { P_X = 0, P_H = 3, P_V = 4, P_PHI = 5, P_LE = 10, P_LS = 19 };
+static_assert(P_LS + 15 <= kRec, "record slots");
+enum { L_HALF = 0, L_MAX = 1, L_MIN = 6 };
+static_assert(kAdjLim * 2 >= 16 + 2 * 12, "limiter block");
 // own-side adjoints of part one, read back by part two: phi (5), x (3)
 static_assert(kAdjOwn == 8, "own-side slots");
 
 struct PullArrays {
     double* rec;   // kRec x n, particle-major
     double* own;   // kOwn x n, field-major
+    int* lix;      // 16 x n int32, particle-major
+    double* lval;  // 12 x n, particle-major
 };
 
 // the term that pair (i -> j) of i's gather set gives j: adds to lphi (5) and
@@ -562,9 +568,10 @@ __global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, con
                 lxi[c] -= th;
             }
     }
-    int* ix = (int*)(rc + P_IDX);
+    int ix[16];
+    double* lv = pa.lval + (long long)i * 12;
     ix[0] = jr != i ? jr : -1;
-    rc[P_LHALF] = lhalf;
+    lv[L_HALF] = lhalf;
     for (int f = 0; f < 5; f++) {
         int tmax = -1, tmin = -1;
         if (lmax[f] != 0.0) {
@@ -577,10 +584,12 @@ __global__ __launch_bounds__(256) void k_adj_grad_own(PassArrays a, Phys ph, con
         }
         ix[1 + f] = tmax;
         ix[6 + f] = tmin;
-        rc[P_LMAX + f] = lmax[f];
-        rc[P_LMIN + f] = lmin[f];
+        lv[L_MAX + f] = lmax[f];
+        lv[L_MIN + f] = lmin[f];
     }
-    ix[11] = -1;
+    for (int q = 11; q < 16; q++) ix[q] = -1;
+    int4* ixo = (int4*)(pa.lix + (long long)i * 16);
+    for (int q = 0; q < 4; q++) ixo[q] = make_int4(ix[4 * q], ix[4 * q + 1], ix[4 * q + 2], ix[4 * q + 3]);
     for (int f = 0; f < 5; f++) pa.own[f * n + i] = lphi_i[f];
     for (int c = 0; c < 3; c++) pa.own[(5 + c) * n + i] = lxi[c];
     aj.acc_H[i] += lH;
@@ -617,14 +626,21 @@ __global__ __launch_bounds__(256) void k_adj_grad_pull(PassArrays a, Phys ph, co
         for (int f = 0; f < 5; f++) lphi[f] += t[f];
         for (int c = 0; c < 3; c++) lx[c] += ld[c];
         // i's limiter terms addressed to j: its length (j the farthest) and extrema
-        const int* ix = (const int*)(rc + P_IDX);
-        if (ix[0] == j && r > 0.0) {
-            const double lhalf = rc[P_LHALF];
-            for (int c = 0; c < 3; c++) lx[c] += 0.5 * lhalf * d[c] / r;
-        }
-        for (int f = 0; f < 5; f++) {
-            if (ix[1 + f] == j) lphi[f] += rc[P_LMAX + f];
-            if (ix[6 + f] == j) lphi[f] += rc[P_LMIN + f];
+        const int4* ixp = (const int4*)(pa.lix + (long long)i * 16);
+        const int4 q0 = ixp[0], q1 = ixp[1], q2 = ixp[2];
+        const int ix[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+        bool any = false;
+        for (int q = 0; q < 11; q++) any |= ix[q] == j;
+        if (any) {
+            const double* lv = pa.lval + (long long)i * 12;
+            if (ix[0] == j && r > 0.0) {
+                const double lhalf = lv[L_HALF];
+                for (int c = 0; c < 3; c++) lx[c] += 0.5 * lhalf * d[c] / r;
+            }
+            for (int f = 0; f < 5; f++) {
+                if (ix[1 + f] == j) lphi[f] += lv[L_MAX + f];
+                if (ix[6 + f] == j) lphi[f] += lv[L_MIN + f];
+            }
         }
     }
     for (int f = 0; f < 5; f++) aj.acc_phi[f * n + j] += lphi[f];
@@ -733,6 +749,8 @@ void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts,
     PullArrays pa;
     pa.rec = scratch + kAdjPullOffset * n;
     pa.own = pa.rec + kAdjRec * n;
+    pa.lix = (int*)(pa.own + kAdjOwn * n);   // 16 int32 = 8 doubles per particle
+    pa.lval = pa.own + (kAdjOwn + 8) * n;
     const int blocks = (int)((n + 255) / 256);
     k_adj_side_pack<<<blocks, 256, 0, s>>>(a, lam_dp, lam_dE, pa.rec);
     k_adj_pairs<<<blocks, 256, 0, s>>>(a, ph, counts, list, pa.rec, aj);

@@ -334,16 +334,21 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     (void)hipSetDevice(c->device);
     launch_keys(n, p->x, p->y, p->z, c->td, c->keys, c->idx, s);
     radix_sort(n, c->td.ktot, c->keys, c->idx, c->ktmp, c->vtmp, c->hist, c->scan_tmp, s);
-    GatherBatch gb;
-    gb.count = 0;
+    // each batch: one launch copies its arrays to the staging, one gathers them back in key order
+    GatherBatch gb, cb;
+    gb.count = cb.count = 0;
+    auto flush = [&]() {
+        launch_copy_batch(n, cb, s);
+        launch_gather(n, gb, c->idx, s);
+        gb.count = cb.count = 0;
+    };
     auto add = [&](void* ptr) {
         if (!ptr) return;
-        if (gb.count == kGatherMax) {   // staging full: reorder this batch, then reuse the staging
-            launch_gather(n, gb, c->idx, s);
-            gb.count = 0;
-        }
+        if (gb.count == kGatherMax) flush();   // staging full: reorder this batch, then reuse the staging
         unsigned long long* stage = c->gtmp + (long long)gb.count * n;
-        hipMemcpyAsync(stage, ptr, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        cb.src[cb.count] = (const unsigned long long*)ptr;
+        cb.dst[cb.count] = stage;
+        cb.count++;
         gb.src[gb.count] = stage;
         gb.dst[gb.count] = (unsigned long long*)ptr;
         gb.count++;
@@ -367,7 +372,7 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     add(p->dm);
     add(p->id);
     for (int k = 0; k < nextra; k++) add(extra[k]);
-    launch_gather(n, gb, c->idx, s);
+    flush();
     launch_fill_u64(c->tab_len, (unsigned long long*)c->tab, 0ull, s);
     launch_tables(n, c->keys, c->td, c->tab, s);
     launch_pos4(n, p->x, p->y, p->z, c->pos, s);

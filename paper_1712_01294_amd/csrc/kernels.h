@@ -95,11 +95,14 @@ void launch_hier_finish(int n, const double* m, const double* vx, const double* 
 // adjoint.hip
 // Adjoint scratch, doubles per particle: 0-27 pass accumulators, 28-55 step
 // reverse, then the per-particle records the pass reverse pulls through the
-// flux lists (kAdjRec) and its own-side terms (kAdjOwn).
-constexpr int kAdjRec = 52;
+// flux lists (kAdjRec) and its own-side terms (kAdjOwn), then the limiter
+// terms part one addresses to single neighbours (kAdjLim: 16 int32 indices and
+// 12 values per particle).
+constexpr int kAdjRec = 36;
 constexpr int kAdjOwn = 8;
+constexpr int kAdjLim = 20;
 constexpr int kAdjPullOffset = 56;
-constexpr int kAdjSlots = kAdjPullOffset + kAdjRec + kAdjOwn;
+constexpr int kAdjSlots = kAdjPullOffset + kAdjRec + kAdjOwn + kAdjLim;
 
 void launch_pass_adjoint(const PassArrays& a, const Phys& ph, const int* counts, const int* gcount,
                          const int* list, const double* lam_dp, const double* lam_dE, double* scratch,
