@@ -60,8 +60,8 @@ struct mfm_ctx {
 static void clock_drain(KernelClock& k) {
     for (auto& e : k.pending) {
         float ms = 0.0f;
-        hipEventSynchronize(e.second);
-        hipEventElapsedTime(&ms, e.first, e.second);
+        (void)hipEventSynchronize(e.second);
+        (void)hipEventElapsedTime(&ms, e.first, e.second);
         k.total_ms += ms;
         k.launches++;
         k.spare.push_back(e);
@@ -201,7 +201,12 @@ static void init_params(mfm_ctx* c, const mfm_params& p) {
 extern "C" {
 
 const char* mfm_status_str(mfm_status s) {
-    switch (s) {
+    // a C caller may pass any int: copy the bits out rather than load an
+    // enum value outside the enumeration's range
+    static_assert(sizeof(mfm_status) == sizeof(int), "mfm_status is an int");
+    int v;
+    memcpy(&v, &s, sizeof v);
+    switch (v) {
         case MFM_OK: return "ok";
         case MFM_E_INVALID: return "invalid argument";
         case MFM_E_HIP: return "HIP runtime error";
