@@ -133,6 +133,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-mfv", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the forward + adjoint timing of 10 steps on the 64^3 box")
@@ -528,6 +529,33 @@ def main():
             del stvm
         del stv
         torch.cuda.empty_cache()
+
+    if not args.no_limited:
+        # the optional limiters (pairwise face limiter and condition-adaptive
+        # beta): FP64 and mixed in both schemes, the mixed form's error against
+        # FP64 under the same limiters, and the first-order switches each takes
+        lk = dict(kw, limiter=1, beta=2.0, beta_min=1.0, cond_lo=10.0, cond_hi=1000.0)
+        out["limited"] = {"params": {k: lk[k] for k in ("limiter", "beta", "beta_min", "cond_lo", "cond_hi")}}
+        for name, sch in (("mfm", mfm.SCHEME_MFM), ("mfv", mfm.SCHEME_MFV)):
+            ctx, s64, t64, _, c64 = run_precision(mfm, w, mfm.FP64, lk, args, stream, scheme=sch)
+            del ctx
+            ctx, s32, t32, _, c32 = run_precision(mfm, w, mfm.MIXED, lk, args, stream, scheme=sch)
+            del ctx
+            ms64 = t64["solve_h"] + t64["gradients"] + t64["fluxes"]
+            ms32 = t32["solve_h"] + t32["gradients"] + t32["fluxes"]
+            errs = None
+            if torch.equal(s64.id, s32.id):
+                errs = {k: float((getattr(s64, k) - getattr(s32, k)).abs().max() / getattr(s64, k).abs().max())
+                        for k in (("dm", "dp", "dE") if name == "mfv" else ("dp", "dE"))}
+            out["limited"][name] = {"value": c64["pairs"] / (ms64 * 1e-3), "unit": "pairs/s", "dtype": "f64",
+                                    "ms_per_step": ms64, "first_order_faces": c64["fallbacks"],
+                                    "mixed": {"value": c32["pairs"] / (ms32 * 1e-3), "unit": "pairs/s",
+                                              "dtype": "f32/f64", "ms_per_step": ms32,
+                                              "first_order_faces": c32["fallbacks"],
+                                              "normwise_error_vs_fp64": errs}}
+            log(f"limited {name}: fp64 {ms64:.3f} ms, mixed {ms32:.3f} ms, errs={errs}")
+            del s64, s32
+            torch.cuda.empty_cache()
 
     if not args.no_adjoint:
         log("adjoint ...")
