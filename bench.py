@@ -290,16 +290,17 @@ def cpu_baseline(w):
     return runs["oracle"], runs["oracle_omp"]
 
 
-# Algorithmic traffic of forward + adjoint per particle (10 fixed-dt steps):
-# forward = the initial pass (600 B: 48 + 264 + 288) and 10 steps of a pass plus
-# the kick-drift-kick streaming (~160 B: x, v, u, m, dp, dE in; x, v, u and the
-# predicted v, u out) and one checkpoint copy (96 B read and written); backward
-# = per step the checkpoint restored (192 B), the step recomputed (760 B), the
-# reverse pass (the pass's 600 B plus 88 B of adjoints in and out) and the
-# reverse step streaming (~200 B), then the initial pass recomputed and
-# reversed (1,288 B).  The 64^3 box (~30 kB x 262,144 = 7.8 GB per run) fits
-# in the 256 MB Infinity Cache, so this is a traffic-equivalent rate.
-ADJ_BYTES_PER_PARTICLE = (600 + 10 * (600 + 160 + 192)) + (10 * (192 + 760 + 688 + 200) + 1288)
+# Algorithmic traffic of forward + adjoint per particle (10 fixed-dt steps,
+# taped): forward = the initial pass (600 B: 48 + 264 + 288) and 10 steps of a
+# pass plus the kick-drift-kick streaming (~160 B: x, v, u, m, dp, dE in; x, v,
+# u and the predicted v, u out), one checkpoint copy (192 B read and written)
+# and the tape written (~465 B: 42 doubles, 3 int32 and the ~29 used list
+# entries); backward = per step the tape read (465 B), the reverse pass (the
+# pass's 600 B plus 88 B of adjoints in and out) and the reverse step streaming
+# (~200 B), then the initial pass recomputed and reversed (1,288 B).  One
+# step's working set on the 64^3 box (~100 MB) fits in the 256 MB Infinity
+# Cache, so this is a traffic-equivalent rate, not an HBM measurement.
+ADJ_BYTES_PER_PARTICLE = (600 + 10 * (600 + 160 + 192 + 465)) + (10 * (465 + 688 + 200) + 1288)
 
 
 def adjoint_timing(reps=3):
@@ -340,7 +341,7 @@ def adjoint_timing(reps=3):
                          "frac": rate / PEAK_HBM, "algorithmic_bytes": b,
                          "note": "algorithmic bytes of forward + adjoint over their wall time; the set fits "
                                  "in the Infinity Cache"},
-            "note": "wall clock with the stream synchronised at both ends; forward keeps one checkpoint per step"}
+            "note": "wall clock with the stream synchronised at both ends; forward keeps one checkpoint and one tape per step, the backward reads the tapes"}
 
 
 def run_precision(mfm, w, prec, kw, args, stream, scheme=0):

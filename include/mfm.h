@@ -254,7 +254,7 @@ mfm_status mfm_copy_levels(mfm_ctx *ctx, double *out, void *stream);
  * fallback follow the branch the forward took.  Requires that the last pass
  * on this context ran on p (its outputs nk, V, B, rho, P, grad are read).
  * All arrays are device memory in p's current order.  The first adjoint call
- * on a context allocates its adjoint scratch (100 doubles per particle). */
+ * on a context allocates its adjoint scratch (120 doubles per particle). */
 mfm_status mfm_hydro_pass_adjoint(mfm_ctx *ctx, const mfm_particles *p, const double *adj_dp,
                                   const double *adj_dE, double *adj_x, double *adj_v, double *adj_u,
                                   void *stream);
@@ -269,6 +269,29 @@ mfm_status mfm_hydro_pass_adjoint(mfm_ctx *ctx, const mfm_particles *p, const do
 mfm_status mfm_step_adjoint(mfm_ctx *ctx, const mfm_particles *ckpt, mfm_particles *work, double dt,
                             double *adj_x, double *adj_v, double *adj_u, double *adj_dp, double *adj_dE,
                             void *stream);
+
+/* A step's tape: memory in place of recomputation for the reverse sweep
+ * (reading R17/R20).  mfm_tape_bytes gives the size of one step's tape for
+ * the context's capacity (about 42 doubles and 3 + max_ngb int32 per
+ * particle), or -1 for a null context.
+ *
+ * mfm_step_taped is mfm_step with a fixed dt > 0 (MFM, per-particle limiter
+ * only) that also writes into `tape` (caller-owned device memory of
+ * mfm_tape_bytes bytes, overwritten) what the step's reverse reads: the state
+ * after its drift and first kick, the predicted state, the pass outputs, the
+ * step's permutation and its flux lists, in the order the step leaves the
+ * particles.  The step itself is the same as mfm_step's, bit for bit.
+ *
+ * mfm_step_adjoint_taped is mfm_step_adjoint without the recomputation: it
+ * reads the step from a tape written by mfm_step_taped on the state that ckpt
+ * holds (ckpt: x, m, vx, vy, vz of the state at the step's start, in its
+ * order; read only), and gives the same adjoints bit for bit.  The tape must
+ * come from the same context parameters and particle count. */
+int64_t mfm_tape_bytes(const mfm_ctx *ctx);
+mfm_status mfm_step_taped(mfm_ctx *ctx, mfm_particles *p, double dt, void *tape, void *stream);
+mfm_status mfm_step_adjoint_taped(mfm_ctx *ctx, const mfm_particles *ckpt, const void *tape, double dt,
+                                  double *adj_x, double *adj_v, double *adj_u, double *adj_dp, double *adj_dE,
+                                  void *stream);
 
 /* Synchronise the stream of the last call and report device counters. */
 mfm_status mfm_get_counters(mfm_ctx *ctx, mfm_counters *out);

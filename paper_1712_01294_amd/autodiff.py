@@ -3,9 +3,12 @@ library's fixed-dt kick-drift-kick steps, with the hand-written adjoint.
 
 Forward runs the initial pass and k steps on the GPU and keeps one checkpoint
 of the state per step (positions, velocities, energies, kernel lengths and the
-pass outputs dp, dE).  Backward walks the steps from last to first: each
-mfm_step_adjoint recomputes its step from the checkpoint and applies the
-reverse step; the initial pass is reversed last with mfm_hydro_pass_adjoint.
+pass outputs dp, dE).  With `tape` (the default) each step also records its
+tape (mfm_step_taped: the step's predicted state, pass outputs, permutation and
+flux lists, about 1.4 kB per particle with 256 list slots), and the backward
+reads it (mfm_step_adjoint_taped); without, each mfm_step_adjoint recomputes
+its step from the checkpoint.  Backward walks the steps from last to first;
+the initial pass is reversed last with mfm_hydro_pass_adjoint.
 Only v and u of the initial state are differentiable inputs; positions and
 masses are fixed data.
 """
@@ -28,10 +31,11 @@ def _copy_state(dst: mfm.State, src: mfm.State):
 class Evolution:
     """Fixed data of one differentiable run: positions, masses, parameters."""
 
-    def __init__(self, w, steps: int, dt: float, cfg: mfm.Config | None = None):
+    def __init__(self, w, steps: int, dt: float, cfg: mfm.Config | None = None, tape: bool = True):
         self.w = w
         self.steps = int(steps)
         self.dt = float(dt)
+        self.tape = bool(tape)
         self.cfg = cfg or mfm.config_of(w)
         self.ctx = mfm.Context(self.cfg, w.n)
         self.n = w.n
@@ -44,7 +48,8 @@ class Evolution:
 
     def run(self, v0: torch.Tensor, u0: torch.Tensor, keep: bool):
         """Forward; v0 (3, n) and u0 (n) in the input order.  Returns the final
-        state (library order) and the checkpoints if keep."""
+        state (library order) and, if keep, the checkpoints (with each step's
+        tape as `ck.tape` when taping)."""
         st = mfm.State(self.n, zero=False)
         torch._foreach_copy_([st.x, st.y, st.z, st.m, st.vx, st.vy, st.vz, st.u],
                              [self.dev["x"], self.dev["y"], self.dev["z"], self.dev["m"], v0[0], v0[1], v0[2], u0])
@@ -52,11 +57,16 @@ class Evolution:
         self.ctx.build_neighbours(st)
         self.ctx.hydro_pass(st)
         cks = []
+        nb = self.ctx.tape_bytes() if (keep and self.tape) else 0
         for _ in range(self.steps):
             if keep:
                 ck = self._state()
                 _copy_state(ck, st)
                 cks.append(ck)
+                if self.tape:
+                    ck.tape = torch.empty(nb, dtype=torch.uint8, device="cuda")
+                    self.ctx.step_taped(st, self.dt, ck.tape)
+                    continue
             self.ctx.step(st, self.dt)
         return st, cks
 
@@ -92,8 +102,15 @@ class MFMSteps(torch.autograd.Function):
         au = gu[ids].contiguous()
         ap = torch.zeros(3, n, **f)
         ae = torch.zeros(n, **f)
-        work = mfm.State(n, zero=False)   # the step adjoint writes it before reading
+        work = None
         for ck in reversed(ctx.cks):
+            tape = getattr(ck, "tape", None)
+            if tape is not None:
+                evo.ctx.step_adjoint_taped(ck, tape, evo.dt, ax, av, au, ap, ae)
+                ck.tape = None
+                continue
+            if work is None:
+                work = mfm.State(n, zero=False)   # the step adjoint writes it before reading
             evo.ctx.step_adjoint(ck, work, evo.dt, ax, av, au, ap, ae)
         # the initial pass produced (dp, dE) of the first state: reverse it
         st0 = mfm.State(n, zero=False)

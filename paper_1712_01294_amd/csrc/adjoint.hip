@@ -876,6 +876,19 @@ void launch_step_rev3(int n, const double* m, const double* vx, const double* vy
     k_step_rev3<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, lE0, lv);
 }
 
+// the used entries of each particle's flux list (k < counts[i]), for a step's tape
+__global__ void k_copy_lists(int n, const int* __restrict__ counts, const int* __restrict__ src,
+                             int* __restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = counts[i];
+    for (int k = 0; k < c; k++) dst[(long long)k * n + i] = src[(long long)k * n + i];
+}
+
+void launch_copy_lists(int n, const int* counts, const int* src, int* dst, hipStream_t s) {
+    k_copy_lists<<<(n + 255) / 256, 256, 0, s>>>(n, counts, src, dst);
+}
+
 void launch_unpermute(int n, const GatherBatch& gb, const int* idx, hipStream_t s) {
     k_unpermute<<<(n + 255) / 256, 256, 0, s>>>(n, gb, idx);
 }

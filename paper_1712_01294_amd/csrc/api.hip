@@ -471,7 +471,100 @@ mfm_status mfm_hydro_pass(mfm_ctx* c, mfm_particles* p, void* stream) {
     return do_fluxes(c, p, s);
 }
 
+// One step's tape (caller-owned device memory): in the step's own order, after
+// its reorder, kTapeD doubles per particle (component-major, [slot * n + i]),
+// then the step's permutation, the list counts, the gather counts and the flux
+// lists ([k * n + i], max_ngb slots).
+enum { T_X = 0, T_M = 3, T_V1 = 4, T_EH = 7, T_VP = 8, T_UP = 11, T_DP = 12, T_DE = 15, T_H = 16, T_NK = 17,
+       T_V = 18, T_B = 19, T_RHO = 25, T_P = 26, T_GRAD = 27, kTapeD = 42 };
+
+static long long tape_bytes(const mfm_ctx* c, long long n) {
+    return (long long)sizeof(double) * kTapeD * n + (long long)sizeof(int) * (3 + (long long)c->ph.max_ngb) * n;
+}
+
+struct TapeView {
+    double* d;
+    int *idx, *counts, *gcount, *list;
+};
+
+static TapeView tape_view(void* t, long long n) {
+    TapeView v;
+    v.d = (double*)t;
+    int* ib = (int*)(v.d + (long long)kTapeD * n);
+    v.idx = ib;
+    v.counts = ib + n;
+    v.gcount = ib + 2 * n;
+    v.list = ib + 3 * n;
+    return v;
+}
+
+// after the step's pass, before its closing kick: the state, the predicted
+// state, the pass outputs, the permutation and the lists, into the tape
+static mfm_status write_tape(mfm_ctx* c, const mfm_particles* p, void* tape, hipStream_t s) {
+    const long long n = p->n;
+    TapeView t = tape_view(tape, n);
+    GatherBatch cb;
+    cb.count = 0;
+    auto cp = [&](int slot, const double* src) {
+        if (cb.count == kGatherMax) {
+            launch_copy_batch((int)n, cb, s);
+            cb.count = 0;
+        }
+        cb.src[cb.count] = (const unsigned long long*)src;
+        cb.dst[cb.count] = (unsigned long long*)(t.d + (long long)slot * n);
+        cb.count++;
+    };
+    cp(T_X, p->x);
+    cp(T_X + 1, p->y);
+    cp(T_X + 2, p->z);
+    cp(T_M, p->m);
+    cp(T_V1, p->vx);
+    cp(T_V1 + 1, p->vy);
+    cp(T_V1 + 2, p->vz);
+    cp(T_EH, c->Ehalf);
+    for (int k = 0; k < 3; k++) cp(T_VP + k, c->vp + k * n);
+    cp(T_UP, c->up);
+    for (int k = 0; k < 3; k++) cp(T_DP + k, p->dp + k * n);
+    cp(T_DE, p->dE);
+    cp(T_H, p->H);
+    cp(T_NK, p->nk);
+    cp(T_V, p->V);
+    for (int k = 0; k < 6; k++) cp(T_B + k, p->B + k * n);
+    cp(T_RHO, p->rho);
+    cp(T_P, p->P);
+    for (int k = 0; k < 15; k++) cp(T_GRAD + k, p->grad + k * n);
+    launch_copy_batch((int)n, cb, s);
+    mfm_status st;
+    if ((st = hip_check(c, hipMemcpyAsync(t.idx, c->idx, sizeof(int) * n, hipMemcpyDeviceToDevice, s), "tape idx")))
+        return st;
+    if ((st = hip_check(c, hipMemcpyAsync(t.counts, c->counts, sizeof(int) * n, hipMemcpyDeviceToDevice, s),
+                        "tape counts")))
+        return st;
+    if ((st = hip_check(c, hipMemcpyAsync(t.gcount, c->gcount, sizeof(int) * n, hipMemcpyDeviceToDevice, s),
+                        "tape gather counts")))
+        return st;
+    launch_copy_lists((int)n, c->counts, c->list, t.list, s);
+    return MFM_OK;
+}
+
+static mfm_status do_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* tape, void* stream);
+
 mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* stream) {
+    return do_step(c, p, dt, dt_used, nullptr, stream);
+}
+
+extern "C" int64_t mfm_tape_bytes(const mfm_ctx* c) { return c ? (int64_t)tape_bytes(c, c->cap) : -1; }
+
+extern "C" mfm_status mfm_step_taped(mfm_ctx* c, mfm_particles* p, double dt, void* tape, void* stream) {
+    if (!c) return MFM_E_INVALID;
+    if (!tape) return fail(c, MFM_E_INVALID, "null tape");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, MFM_E_INVALID, "a taped step needs a fixed dt > 0");
+    if (c->p.scheme != MFM_SCHEME_MFM || c->p.limiter)
+        return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme with the per-particle limiter only");
+    return do_step(c, p, dt, nullptr, tape, stream);
+}
+
+static mfm_status do_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, void* tape, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
     const int mfv = c->p.scheme == MFM_SCHEME_MFV;
@@ -511,6 +604,7 @@ mfm_status mfm_step(mfm_ctx* c, mfm_particles* p, double dt, double* dt_used, vo
     if ((st = do_solve_h(c, &q, s))) return st;
     if ((st = do_gradients(c, &q, s))) return st;
     if ((st = do_fluxes(c, &q, s))) return st;
+    if (tape && (st = write_tape(c, p, tape, s))) return st;
     a = arrays_of(p);
     if (mfv)
         launch_kick2_mfv(a, dt, c->p.u_floor, c->Ehalf, p->u, c->cnt, s);
@@ -775,6 +869,87 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
     c->last = s;
     return launched(c, "step_adjoint");
+}
+
+// The step's reverse from its tape: the same kernels as mfm_step_adjoint's
+// part two and three, on the taped arrays instead of a recomputed step.
+extern "C" mfm_status mfm_step_adjoint_taped(mfm_ctx* c, const mfm_particles* ck, const void* tape, double dt,
+                                             double* adj_x, double* adj_v, double* adj_u, double* adj_dp,
+                                             double* adj_dE, void* stream) {
+    mfm_status st = check_particles(c, ck);
+    if (st) return st;
+    if (c->p.scheme != MFM_SCHEME_MFM || c->p.limiter)
+        return fail(c, MFM_E_INVALID, "the adjoints cover the MFM scheme with the per-particle limiter only");
+    if (!tape) return fail(c, MFM_E_INVALID, "null tape");
+    if (!(dt > 0.0)) return fail(c, MFM_E_INVALID, "the step adjoint needs a fixed dt > 0");
+    if (!adj_x || !adj_v || !adj_u || !adj_dp || !adj_dE) return fail(c, MFM_E_INVALID, "null adjoint array");
+    (void)hipSetDevice(c->device);
+    if ((st = ensure_adj(c))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = ck->n;
+    TapeView t = tape_view(const_cast<void*>(tape), n);
+    double* d = t.d;
+    auto col = [&](int slot) { return d + (long long)slot * n; };
+    mfm_particles q;
+    memset(&q, 0, sizeof q);
+    q.n = n;
+    q.x = col(T_X);
+    q.y = col(T_X + 1);
+    q.z = col(T_X + 2);
+    q.m = col(T_M);
+    q.vx = col(T_VP);
+    q.vy = col(T_VP + 1);
+    q.vz = col(T_VP + 2);
+    q.u = col(T_UP);
+    q.H = col(T_H);
+    q.nk = col(T_NK);
+    q.V = col(T_V);
+    q.B = col(T_B);
+    q.rho = col(T_RHO);
+    q.P = col(T_P);
+    q.grad = col(T_GRAD);
+    q.dp = col(T_DP);
+    q.dE = col(T_DE);
+    double* A = c->adj;
+    double* lxF = A + 28 * n;
+    double* lvp = A + 31 * n;
+    double* lup = A + 34 * n;
+    double* lp2 = A + 35 * n;
+    double* le2 = A + 38 * n;
+    double* lv1 = A + 39 * n;
+    double* lE1 = A + 42 * n;
+    double* olx = A + 43 * n;
+    double* olv = A + 46 * n;
+    double* olu = A + 49 * n;
+    double* olp = A + 50 * n;
+    double* ole = A + 53 * n;
+    double* olE0 = A + 54 * n;
+    double* lE0 = A + 55 * n;
+    launch_step_rev1((int)n, q.m, col(T_V1), col(T_V1 + 1), col(T_V1 + 2), col(T_EH), q.dp, q.dE, dt, c->p.u_floor,
+                     adj_x, adj_v, adj_u, adj_dp, adj_dE, lp2, le2, lv1, lE1, s);
+    PassArrays qa = arrays_of(&q);
+    launch_pass_adjoint(qa, c->ph, t.counts, t.gcount, t.list, lp2, le2, A, lxF, lvp, lup, s);
+    launch_step_rev2((int)n, q.m, col(T_VP), col(T_UP), dt, c->p.u_floor, adj_x, lxF, lvp, lup, lv1, lE1, olx, olv,
+                     olu, olp, ole, olE0, s);
+    GatherBatch gb;
+    gb.count = 0;
+    auto add = [&](const double* src, double* dst) {
+        gb.src[gb.count] = (const unsigned long long*)src;
+        gb.dst[gb.count] = (unsigned long long*)dst;
+        gb.count++;
+    };
+    for (int k = 0; k < 3; k++) {
+        add(olx + k * n, adj_x + k * n);
+        add(olv + k * n, adj_v + k * n);
+        add(olp + k * n, adj_dp + k * n);
+    }
+    add(olu, adj_u);
+    add(ole, adj_dE);
+    add(olE0, lE0);
+    launch_unpermute((int)n, gb, t.idx, s);
+    launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
+    c->last = s;
+    return launched(c, "step_adjoint_taped");
 }
 
 // ------------------------------------------------------------ hierarchical steps

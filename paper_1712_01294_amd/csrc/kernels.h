@@ -118,5 +118,6 @@ void launch_step_rev2(int n, const double* m, const double* vp, const double* up
 void launch_step_rev3(int n, const double* m, const double* vx, const double* vy, const double* vz,
                       const double* lE0, double* lv, hipStream_t s);
 void launch_unpermute(int n, const GatherBatch& gb, const int* idx, hipStream_t s);
+void launch_copy_lists(int n, const int* counts, const int* src, int* dst, hipStream_t s);
 
 }  // namespace mfm

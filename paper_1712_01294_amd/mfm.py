@@ -24,7 +24,8 @@ STATUS = {0: "MFM_OK", -1: "MFM_E_INVALID", -2: "MFM_E_HIP", -3: "MFM_E_NOCONV",
 EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "mfm_gradients",
            "mfm_hydro_fluxes", "mfm_hydro_pass", "mfm_step", "mfm_get_counters", "mfm_check",
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
-           "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_set_kernel_timing", "mfm_kernel_time",
+           "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_tape_bytes", "mfm_step_taped",
+           "mfm_step_adjoint_taped", "mfm_set_kernel_timing", "mfm_kernel_time",
            "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels")
 
 # kernels that mfm_kernel_time can report (mfm_kernel)
@@ -97,6 +98,10 @@ def lib() -> C.CDLL:
         L.mfm_hydro_pass_adjoint.argtypes = [vp, C.POINTER(Particles), vp, vp, vp, vp, vp, vp]
         L.mfm_step_adjoint.argtypes = [vp, C.POINTER(Particles), C.POINTER(Particles), C.c_double, vp, vp, vp,
                                        vp, vp, vp]
+        L.mfm_tape_bytes.argtypes = [vp]
+        L.mfm_tape_bytes.restype = C.c_int64
+        L.mfm_step_taped.argtypes = [vp, C.POINTER(Particles), C.c_double, vp, vp]
+        L.mfm_step_adjoint_taped.argtypes = [vp, C.POINTER(Particles), vp, C.c_double, vp, vp, vp, vp, vp, vp]
         L.mfm_set_kernel_timing.argtypes = [vp, C.c_int]
         L.mfm_kernel_time.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.mfm_hydro_pass_noalloc.argtypes = [C.POINTER(Params), C.POINTER(Particles), C.POINTER(Counters), vp]
@@ -291,6 +296,23 @@ class Context:
         v = lambda t: C.c_void_p(t.data_ptr())
         self._rc(self._L.mfm_step_adjoint(self.h, C.byref(pc), C.byref(pw), C.c_double(dt), v(ax), v(av), v(au),
                                           v(ap), v(ae), _stream(stream)))
+
+    def tape_bytes(self) -> int:
+        return int(self._L.mfm_tape_bytes(self.h))
+
+    def step_taped(self, st: State, dt: float, tape, stream=None):
+        """mfm_step with a fixed dt that also records the step's tape (a device
+        uint8 tensor of tape_bytes() bytes)."""
+        p = st.struct()
+        self._rc(self._L.mfm_step_taped(self.h, C.byref(p), C.c_double(dt), C.c_void_p(tape.data_ptr()),
+                                        _stream(stream)))
+
+    def step_adjoint_taped(self, ckpt: State, tape, dt: float, ax, av, au, ap, ae, stream=None):
+        """step_adjoint reading the step from its tape instead of recomputing it."""
+        pc = ckpt.struct()
+        v = lambda t: C.c_void_p(t.data_ptr())
+        self._rc(self._L.mfm_step_adjoint_taped(self.h, C.byref(pc), v(tape), C.c_double(dt), v(ax), v(av), v(au),
+                                                v(ap), v(ae), _stream(stream)))
 
     def counters(self) -> dict:
         c = Counters()

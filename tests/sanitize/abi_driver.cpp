@@ -81,6 +81,14 @@ int main() {
     expect("solve_h: null context", mfm_solve_h(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("hydro_pass: null context", mfm_hydro_pass(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("get_counters: null context", mfm_get_counters(nullptr, &cnt), MFM_E_INVALID);
+    if (mfm_tape_bytes(nullptr) != -1) {
+        printf("tape_bytes of a null context is not -1\n");
+        failures++;
+    }
+    expect("step_taped: null context", mfm_step_taped(nullptr, &none, 1e-3, nullptr, nullptr), MFM_E_INVALID);
+    expect("step_adjoint_taped: null context",
+           mfm_step_adjoint_taped(nullptr, &none, nullptr, 1e-3, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr),
+           MFM_E_INVALID);
     expect("noalloc: null params", mfm_hydro_pass_noalloc(nullptr, &none, nullptr, nullptr), MFM_E_INVALID);
     mfm_params q = valid_params();
     q.gamma = 0.5;
@@ -103,6 +111,8 @@ int main() {
         expect("step: null arrays", mfm_step(ctx, &none, 1e-3, nullptr, nullptr), MFM_E_INVALID);
         int64_t bins[1] = {0};
         expect("step_hier: null arrays", mfm_step_hier(ctx, &none, bins, 1, 1e-3, 1, nullptr), MFM_E_INVALID);
+        expect("step_taped: null tape", mfm_step_taped(ctx, &none, 1e-3, nullptr, nullptr), MFM_E_INVALID);
+        expect("step_taped: dt <= 0", mfm_step_taped(ctx, &none, 0.0, bins, nullptr), MFM_E_INVALID);
         printf("last error: %s\n", mfm_last_error(ctx));
         mfm_destroy(ctx);
     } else if (st != MFM_E_HIP) {

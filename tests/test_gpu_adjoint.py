@@ -258,6 +258,27 @@ def test_adjoint_small_box_finite_differences_64_global_directions():
     assert np.all(rels <= 1e-6), rels
 
 
+def test_taped_steps_and_adjoint_equal_the_recomputed_ones_bitwise():
+    """mfm_step_taped leaves the same state as mfm_step, and the reverse read
+    from the tapes (the default) gives the same gradient, bit for bit, as the
+    reverse that recomputes every step from its checkpoint."""
+    import torch
+
+    from paper_1712_01294_amd import autodiff
+    w = W.adjoint_box(n_side=24)
+    m = torch.tensor(w.m, device="cuda")
+    out = {}
+    for tape in (True, False):
+        evo = autodiff.Evolution(w, 3, w.dt, tape=tape)
+        vr = torch.tensor(np.stack([w.vx, w.vy, w.vz]), device="cuda").requires_grad_(True)
+        ur = torch.tensor(w.u, device="cuda").requires_grad_(True)
+        vk, uk = autodiff.MFMSteps.apply(vr, ur, evo)
+        (m * (vk * vk).sum(0)).sum().backward()
+        out[tape] = (vk.detach().clone(), uk.detach().clone(), vr.grad.clone(), ur.grad.clone())
+    for a, b in zip(out[True], out[False]):
+        assert torch.equal(a, b)
+
+
 def test_adjoint_is_bitwise_deterministic():
     """The reverse pass and step sum every term in a fixed order (no atomics):
     two backward runs give the same bits."""
