@@ -288,10 +288,8 @@ __device__ __forceinline__ void side_of(const double* __restrict__ rc, Side& s) 
 // pair's canonical left/right order, as the forward) and keeps its own side.
 // Both records are loaded per pair in left/right order (the own one stays in
 // cache), so one inlined reverse serves both orders.
-#ifndef MFM_ADJ_PAIR_WAVES
-#define MFM_ADJ_PAIR_WAVES 1
-#endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_ADJ_PAIR_WAVES))) void k_adj_pairs(PassArrays a, Phys ph, const int* __restrict__ counts,
+constexpr int kAdjPairWaves = 1;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdjPairWaves))) void k_adj_pairs(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     AdjArrays aj) {
     const int i = xcd_block_adj() * 256 + threadIdx.x;

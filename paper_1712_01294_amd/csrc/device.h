@@ -127,10 +127,7 @@ __device__ __forceinline__ double min_image(double d, double L, int periodic) {
 // cell or particle counts and no lane waits on a dependent gather of its own.
 // Cell keys come from per-axis cell coordinates deposited into the key bits of
 // that axis (cells per axis are a power of two).
-#ifndef MFM_SCAN_SCALE
-#define MFM_SCAN_SCALE 0.35
-#endif
-constexpr double kScanScale = MFM_SCAN_SCALE;
+constexpr double kScanScale = 0.35;
 
 // scatter the low bits of v into the set bits of mask (lowest first); bits of v
 // beyond the mask's population are dropped, which reduces v modulo 2^popcount

@@ -8,10 +8,7 @@
 namespace mfm {
 
 constexpr int kGatherMax = 20;
-#ifndef MFM_RCAP
-#define MFM_RCAP 160
-#endif
-constexpr int kRCap = MFM_RCAP;  // radii slots per particle in the kernel-length solve
+constexpr int kRCap = 160;  // radii slots per particle in the kernel-length solve
 
 // up to kGatherMax arrays of 8-byte elements reordered by one launch: dst[i] = src[idx[i]]
 struct GatherBatch {

@@ -218,35 +218,18 @@ __device__ bool newton_h(const double* __restrict__ rl, long long n, int i, int 
 // bracket yet, or more radii than the list holds) go to the per-particle solver,
 // which is cheaper for them than further group passes over a sparse class.
 constexpr int kScanRounds = 1;
-#ifndef MFM_COLD_PAD
-#define MFM_COLD_PAD 1.05
-#endif
-constexpr double kColdPad = MFM_COLD_PAD;   // first scan radius over a cold guess
-#ifndef MFM_WARM_PAD
-#define MFM_WARM_PAD 1.03
-#endif
-constexpr double kWarmPad = MFM_WARM_PAD;   // first scan radius over the previous H
-#ifndef MFM_STORE_COLD
-#define MFM_STORE_COLD 1.05
-#endif
-constexpr double kStoreCold = MFM_STORE_COLD;   // radii listed by a cold first scan, over the guess
+constexpr double kColdPad = 1.05;   // first scan radius over a cold guess
+constexpr double kWarmPad = 1.03;   // first scan radius over the previous H
+constexpr double kStoreCold = 1.05;   // radii listed by a cold first scan, over the guess
 // a scan pass takes the lanes with R >= kClassRatio Rref within kClassWindow Rref
 // of the first of them on every axis (Rref: the largest trial radius pending)
-#ifndef MFM_CLASS_RATIO
-#define MFM_CLASS_RATIO 0.5
-#endif
-#ifndef MFM_CLASS_WINDOW
-#define MFM_CLASS_WINDOW 2.0
-#endif
-constexpr double kClassRatio = MFM_CLASS_RATIO;
-constexpr double kClassWindow = MFM_CLASS_WINDOW;
+constexpr double kClassRatio = 0.5;
+constexpr double kClassWindow = 2.0;
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
-#ifndef MFM_SOLVE_WAVES
-#define MFM_SOLVE_WAVES 5
-#endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_SOLVE_WAVES))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+constexpr int kSolveWaves = 5;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSolveWaves))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                   const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
@@ -437,22 +420,14 @@ constexpr int kWaveScans = 16;
 // At five waves per SIMD 5,120 waves are resident; 32,768 single-wave blocks
 // (about 87 particles each on the clustered set) balance the end of the
 // launch better than 16,384 (45.2 -> 44.5 ms for the solve stage).
-#ifndef MFM_WAVE_BLOCKS
-#define MFM_WAVE_BLOCKS 32768
-#endif
-constexpr int kWaveBlocks = MFM_WAVE_BLOCKS;   // waves of the list solver, striding over its particles
+constexpr int kWaveBlocks = 32768;   // waves of the list solver, striding over its particles
 // a single sphere's scan enumerates its cells at a coarser level than a group's
-#ifndef MFM_WAVE_SCAN_SCALE
-#define MFM_WAVE_SCAN_SCALE 0.5
-#endif
-constexpr double kWaveScanScale = MFM_WAVE_SCAN_SCALE;
+constexpr double kWaveScanScale = 0.5;
 
 // Five waves per SIMD: the list solver fits in 96 registers without spills,
 // and the fifth wave hides more of its scans' load latency than four.
-#ifndef MFM_WAVESOLVE_WAVES
-#define MFM_WAVESOLVE_WAVES 5
-#endif
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MFM_WAVESOLVE_WAVES))) void k_solve_h_wave(
+constexpr int kWaveSolveWaves = 5;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveSolveWaves))) void k_solve_h_wave(
                                                       PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                       const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                       const int* __restrict__ fb_list,
@@ -890,9 +865,6 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 // 0-2 x, y, z (FP64 record; the FP32 record holds the FP64 pressure in 0-1) | 3 1/H | 4 K = V^2 8/(pi H^3) | 5 rho | 6 P | 7-9 v | 10-15 B |
 // 16-30 grad | 31 c.  With 1/H and K per particle a face needs no division for its kernel weights:
 // V^2 W(r, H) = K w(r/H).
-#ifndef MFM_FLUX32_WAVES
-#define MFM_FLUX32_WAVES 4
-#endif
 enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
 // What the gradient kernel reads of a neighbour, packed into one 128-byte line
@@ -909,11 +881,9 @@ __global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcoun
 // Four waves per SIMD (128 VGPRs, no spills): the kernel waits on the gathers
 // of its neighbours' records, and a fourth wave hides more of that than the
 // register budget it takes costs.
-#ifndef MFM_GRAD_WAVES
-#define MFM_GRAD_WAVES 4
-#endif
+constexpr int kGradWaves = 4;
 template <bool MIXED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_GRAD_WAVES))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
                                                     int* __restrict__ counts, int* __restrict__ list, int* __restrict__ tails,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
                                                     Counters* cnt) {
@@ -1550,11 +1520,10 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
 // the list index loaded a pair ahead, a third wave (a few spilled loop
 // invariants, and twice the HBM traffic as more records compete for L2) no
 // longer pays.
-#ifndef MFM_FLUX64_WAVES
-#define MFM_FLUX64_WAVES 2
-#endif
+constexpr int kFlux64Waves = 2;
+constexpr int kFluxMfvWaves = kFlux64Waves;
 template <bool LIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFlux64Waves))) void k_fluxes_f64(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
     fluxes_body<double, false, LIM>(a, ph, counts, list, rec, cnt);
@@ -1562,7 +1531,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_
 
 // The levelled pass of hierarchical steps (MFM, FP64 records).
 template <bool LIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_WAVES))) void k_fluxes_levels(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFlux64Waves))) void k_fluxes_levels(
     PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
     const double* __restrict__ rec, Counters* cnt, Levels lv) {
     fluxes_body<double, false, LIM, true>(a, ph, counts, list, rec, cnt, lv);
@@ -1570,18 +1539,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX64_
 
 // The finite-volume form, FP64 records only, at two waves per SIMD like the
 // FP64 form (at three its extra live values spill).
-#ifndef MFM_FLUXMFV_WAVES
-#define MFM_FLUXMFV_WAVES MFM_FLUX64_WAVES
-#endif
 template <bool LIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUXMFV_WAVES))) void k_fluxes_mfv(PassArrays a, Phys ph, const int* __restrict__ counts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFluxMfvWaves))) void k_fluxes_mfv(PassArrays a, Phys ph, const int* __restrict__ counts,
                                                     const int* __restrict__ list, const double* __restrict__ rec,
                                                     Counters* cnt) {
     fluxes_body<double, true, LIM>(a, ph, counts, list, rec, cnt);
 }
 
+constexpr int kFlux32Waves = 4;
 template <bool LIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFlux32Waves)))
 void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
                   const float* __restrict__ rec, Counters* cnt) {
     fluxes_body<float, false, LIM>(a, ph, counts, list, rec, cnt);
@@ -1589,7 +1556,7 @@ void k_fluxes_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const i
 
 // The finite-volume form on the FP32 records of the mixed form.
 template <bool LIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFM_FLUX32_WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFlux32Waves)))
 void k_fluxes_mfv_f32(PassArrays a, Phys ph, const int* __restrict__ counts, const int* __restrict__ list,
                       const float* __restrict__ rec, Counters* cnt) {
     fluxes_body<float, true, LIM>(a, ph, counts, list, rec, cnt);
