@@ -772,6 +772,56 @@ extern "C" mfm_status mfm_hydro_pass_adjoint(mfm_ctx* c, const mfm_particles* p,
     return launched(c, "hydro_pass_adjoint");
 }
 
+// The reverse of one step (part two and three of the step adjoint): from the
+// adjoints of the state after the step to those of the checkpoint, given the
+// step's pass arrays q (predicted state and pass outputs, in the step's
+// order), its state after the first kick v1, its half-step energy, its flux
+// lists and its permutation idx (step order -> checkpoint order).
+static void reverse_step(mfm_ctx* c, const mfm_particles* q, const double* v1x, const double* v1y,
+                         const double* v1z, const double* Ehalf, const int* counts, const int* gcount,
+                         const int* list, const int* idx, const mfm_particles* ck, double dt, double* adj_x,
+                         double* adj_v, double* adj_u, double* adj_dp, double* adj_dE, hipStream_t s) {
+    const long long n = ck->n;
+    double* A = c->adj;
+    double* lxF = A + 28 * n;
+    double* lvp = A + 31 * n;
+    double* lup = A + 34 * n;
+    double* lp2 = A + 35 * n;
+    double* le2 = A + 38 * n;
+    double* lv1 = A + 39 * n;
+    double* lE1 = A + 42 * n;
+    double* olx = A + 43 * n;
+    double* olv = A + 46 * n;
+    double* olu = A + 49 * n;
+    double* olp = A + 50 * n;
+    double* ole = A + 53 * n;
+    double* olE0 = A + 54 * n;
+    double* lE0 = A + 55 * n;
+    launch_step_rev1((int)n, q->m, v1x, v1y, v1z, Ehalf, q->dp, q->dE, dt, c->p.u_floor, adj_x, adj_v, adj_u, adj_dp,
+                     adj_dE, lp2, le2, lv1, lE1, s);
+    PassArrays qa = arrays_of(q);
+    launch_pass_adjoint(qa, c->ph, counts, gcount, list, lp2, le2, A, lxF, lvp, lup, s);
+    launch_step_rev2((int)n, q->m, q->vx, q->u, dt, c->p.u_floor, adj_x, lxF, lvp, lup, lv1, lE1, olx, olv, olu, olp,
+                     ole, olE0, s);
+    GatherBatch gb;
+    gb.count = 0;
+    auto add = [&](const double* src, double* dst) {
+        gb.src[gb.count] = (const unsigned long long*)src;
+        gb.dst[gb.count] = (unsigned long long*)dst;
+        gb.count++;
+    };
+    for (int k = 0; k < 3; k++) {
+        add(olx + k * n, adj_x + k * n);
+        add(olv + k * n, adj_v + k * n);
+        add(olp + k * n, adj_dp + k * n);
+    }
+    add(olu, adj_u);
+    add(ole, adj_dE);
+    add(olE0, lE0);
+    launch_unpermute((int)n, gb, idx, s);
+    launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
+}
+
 extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_particles* w, double dt,
                                        double* adj_x, double* adj_v, double* adj_u, double* adj_dp, double* adj_dE,
                                        void* stream) {
@@ -827,46 +877,9 @@ extern "C" mfm_status mfm_step_adjoint(mfm_ctx* c, const mfm_particles* ck, mfm_
     if ((st = do_solve_h(c, &q, s))) return st;
     if ((st = do_gradients(c, &q, s))) return st;
     if ((st = do_fluxes(c, &q, s))) return st;
-    // 2. reverse, in the recomputed order
-    double* A = c->adj;
-    double* lxF = A + 28 * n;
-    double* lvp = A + 31 * n;
-    double* lup = A + 34 * n;
-    double* lp2 = A + 35 * n;
-    double* le2 = A + 38 * n;
-    double* lv1 = A + 39 * n;
-    double* lE1 = A + 42 * n;
-    double* olx = A + 43 * n;
-    double* olv = A + 46 * n;
-    double* olu = A + 49 * n;
-    double* olp = A + 50 * n;
-    double* ole = A + 53 * n;
-    double* olE0 = A + 54 * n;
-    double* lE0 = A + 55 * n;
-    launch_step_rev1((int)n, w->m, w->vx, w->vy, w->vz, c->Ehalf, w->dp, w->dE, dt, c->p.u_floor, adj_x, adj_v,
-                     adj_u, adj_dp, adj_dE, lp2, le2, lv1, lE1, s);
-    PassArrays qa = arrays_of(&q);
-    launch_pass_adjoint(qa, c->ph, c->counts, c->gcount, c->list, lp2, le2, A, lxF, lvp, lup, s);
-    launch_step_rev2((int)n, w->m, c->vp, c->up, dt, c->p.u_floor, adj_x, lxF, lvp, lup, lv1, lE1, olx, olv, olu, olp,
-                     ole, olE0, s);
-    // 3. back to the checkpoint's order, then the v-dependent energy term
-    GatherBatch gb;
-    gb.count = 0;
-    auto add = [&](const double* src, double* dst) {
-        gb.src[gb.count] = (const unsigned long long*)src;
-        gb.dst[gb.count] = (unsigned long long*)dst;
-        gb.count++;
-    };
-    for (int k = 0; k < 3; k++) {
-        add(olx + k * n, adj_x + k * n);
-        add(olv + k * n, adj_v + k * n);
-        add(olp + k * n, adj_dp + k * n);
-    }
-    add(olu, adj_u);
-    add(ole, adj_dE);
-    add(olE0, lE0);
-    launch_unpermute((int)n, gb, c->idx, s);
-    launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
+    // 2. reverse, in the recomputed order; 3. back to the checkpoint's order
+    reverse_step(c, &q, w->vx, w->vy, w->vz, c->Ehalf, c->counts, c->gcount, c->list, c->idx, ck, dt, adj_x, adj_v,
+                 adj_u, adj_dp, adj_dE, s);
     c->last = s;
     return launched(c, "step_adjoint");
 }
@@ -910,44 +923,8 @@ extern "C" mfm_status mfm_step_adjoint_taped(mfm_ctx* c, const mfm_particles* ck
     q.grad = col(T_GRAD);
     q.dp = col(T_DP);
     q.dE = col(T_DE);
-    double* A = c->adj;
-    double* lxF = A + 28 * n;
-    double* lvp = A + 31 * n;
-    double* lup = A + 34 * n;
-    double* lp2 = A + 35 * n;
-    double* le2 = A + 38 * n;
-    double* lv1 = A + 39 * n;
-    double* lE1 = A + 42 * n;
-    double* olx = A + 43 * n;
-    double* olv = A + 46 * n;
-    double* olu = A + 49 * n;
-    double* olp = A + 50 * n;
-    double* ole = A + 53 * n;
-    double* olE0 = A + 54 * n;
-    double* lE0 = A + 55 * n;
-    launch_step_rev1((int)n, q.m, col(T_V1), col(T_V1 + 1), col(T_V1 + 2), col(T_EH), q.dp, q.dE, dt, c->p.u_floor,
-                     adj_x, adj_v, adj_u, adj_dp, adj_dE, lp2, le2, lv1, lE1, s);
-    PassArrays qa = arrays_of(&q);
-    launch_pass_adjoint(qa, c->ph, t.counts, t.gcount, t.list, lp2, le2, A, lxF, lvp, lup, s);
-    launch_step_rev2((int)n, q.m, col(T_VP), col(T_UP), dt, c->p.u_floor, adj_x, lxF, lvp, lup, lv1, lE1, olx, olv,
-                     olu, olp, ole, olE0, s);
-    GatherBatch gb;
-    gb.count = 0;
-    auto add = [&](const double* src, double* dst) {
-        gb.src[gb.count] = (const unsigned long long*)src;
-        gb.dst[gb.count] = (unsigned long long*)dst;
-        gb.count++;
-    };
-    for (int k = 0; k < 3; k++) {
-        add(olx + k * n, adj_x + k * n);
-        add(olv + k * n, adj_v + k * n);
-        add(olp + k * n, adj_dp + k * n);
-    }
-    add(olu, adj_u);
-    add(ole, adj_dE);
-    add(olE0, lE0);
-    launch_unpermute((int)n, gb, t.idx, s);
-    launch_step_rev3((int)n, ck->m, ck->vx, ck->vy, ck->vz, lE0, adj_v, s);
+    reverse_step(c, &q, col(T_V1), col(T_V1 + 1), col(T_V1 + 2), col(T_EH), t.counts, t.gcount, t.list, t.idx, ck,
+                 dt, adj_x, adj_v, adj_u, adj_dp, adj_dE, s);
     c->last = s;
     return launched(c, "step_adjoint_taped");
 }
