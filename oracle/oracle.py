@@ -352,6 +352,10 @@ def sampled_pass(s: Setup, st: dict, targets, h_bound: float):
 
 # --------------------------------------------------------------------------
 # R17/R18: kick-drift-kick step with a predicted state, one pass per step.
+# what an inactive particle keeps between its active boundaries (R26)
+FROZEN = ("H", "nk", "V", "B", "grad")
+
+
 # --------------------------------------------------------------------------
 class Stepper:
     """Plain FP64 time integration of the gas (global time step).  scheme "mfm"
@@ -369,6 +373,7 @@ class Stepper:
         self.floors = 0
         self.bins = None
         self.lev = None
+        self.frz = None
 
     def _pass(self, x, y, z, vx, vy, vz, u, m=None, lmin=None):
         st = dict(x=x, y=y, z=z, m=self.st["m"] if m is None else m, vx=vx, vy=vy, vz=vz, u=u)
@@ -377,6 +382,38 @@ class Stepper:
         else:
             out = hydro_pass(self.s, st, self.H, bins=self.bins, lmin=lmin, lev=self.lev)
         self.H = out["H"]
+        self.frz = {k: out[k] for k in FROZEN}
+        return out
+
+    def _pass_active(self, x, y, z, vx, vy, vz, u, lmin):
+        """R26: the levelled pass of a sub-step boundary on which only the
+        particles of bin >= lmin are active.  An active particle's kernel
+        length (warm-started from its last one), number density, volume,
+        gradient matrix and limited gradients are recomputed at the current
+        positions and predicted state; an inactive particle keeps those of its
+        last active boundary.  Every particle enters with its current position
+        and predicted velocity and energy, its density m n and pressure
+        (gamma - 1) rho u taken from its (recomputed or kept) n.  The flux set
+        is r_ij < max(H_i, H_j) with these kernel lengths, and only the pairs
+        of level >= lmin are evaluated, as in R25."""
+        s, m, frz = self.s, self.st["m"], self.frz
+        act = self.bins >= lmin
+        st = dict(x=x, y=y, z=z, m=m, vx=vx, vy=vy, vz=vz, u=u)
+        Hn, nkn, Vn, it = solve_h(s, x, y, z, frz["H"], mask=act)
+        H = np.where(act, Hn, frz["H"])
+        nk = np.where(act, nkn, frz["nk"])
+        V = np.where(act, Vn, frz["V"])
+        g = gradients(s, st, H, nk, V, mask=act)
+        B = np.where(act, g["B"], frz["B"])
+        grad = np.where(act, g["grad"], frz["grad"])
+        rho = m * nk
+        P = (s.gamma - 1.0) * rho * u
+        f = fluxes(s, st, H, V, dict(B=B, grad=grad, rho=rho, P=P), bins=self.bins, lmin=lmin, lev=self.lev)
+        out = dict(H=H, nk=nk, V=V, iters=it, B=B, grad=grad, rho=rho, P=P, active=act)
+        out.update(f)
+        out["pairs"] = f["pair_entries"] // 2
+        self.H = H
+        self.frz = {k: out[k] for k in FROZEN}
         return out
 
     # ---------------------------------------------------------------- R25
@@ -393,9 +430,13 @@ class Stepper:
         self.last = self._pass(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"], lmin=0)
         return self.last
 
-    def hier_step(self, T):
+    def hier_step(self, T, active=False, trace=None):
         """One system step of length T with hierarchical power-of-two steps
-        (R25).  With B the largest bin, time advances in 2^B sub-steps of
+        (R25; with active, R26: each sub-step's pass recomputes only the
+        particles of the due bins, the others keeping what they had; with a
+        list as trace, each sub-step's pass output is appended to it together
+        with its boundary k, lmin and the positions and predicted state it
+        ran on).  With B the largest bin, time advances in 2^B sub-steps of
         T / 2^B; every particle drifts with its current velocity on each.  A
         pair {i, j} has level l = max(bins) and step T / 2^l; at a sub-step
         boundary the levels whose step divides the time elapsed are due.  At
@@ -438,7 +479,13 @@ class Stepper:
             vp, Ep = kick(v, E, due)
             up = Ep / m - 0.5 * (vp[0] ** 2 + vp[1] ** 2 + vp[2] ** 2)
             up = np.maximum(up, self.u_floor)
-            out = self._pass(x[0], x[1], x[2], vp[0], vp[1], vp[2], up, lmin=lmin)
+            if active and lmin > 0:
+                out = self._pass_active(x[0], x[1], x[2], vp[0], vp[1], vp[2], up, lmin)
+            else:
+                out = self._pass(x[0], x[1], x[2], vp[0], vp[1], vp[2], up, lmin=lmin)
+            if trace is not None:
+                trace.append(dict(out, k=k, lmin=lmin, x=x[0], y=x[1], z=x[2], vx=vp[0], vy=vp[1], vz=vp[2],
+                                  u=up))
             # closing half kicks of the due levels, then the opening ones of their next step
             v, E = kick(v, E, due)
             if k < K:
