@@ -226,16 +226,28 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * rates close its pair step with a half kick and, before the end of T, open
  * the next one with another, applied with opposite signs to the two
  * particles of a pair (momentum and energy are conserved to rounding).
- * Kernel lengths and gradients are recomputed for every particle at each
- * boundary.  The per-level rates live in the context (allocated on the first
- * call, 32 doubles per particle); they are computed by a pass over the
- * current state with every level due when rebin != 0, on the first call, when
+ * flags: MFM_HIER_REBIN, MFM_HIER_ACTIVE or both (other bits: MFM_E_INVALID).
+ * Without MFM_HIER_ACTIVE kernel lengths and gradients are recomputed for
+ * every particle at each boundary.  With it (reading R26, active subsets)
+ * only the particles whose own bin is due at a boundary get new kernel
+ * lengths, densities, volumes, gradient matrices and limited gradients; the
+ * others keep those of their last active boundary, in nk, V, B and grad
+ * (which the call then reorders with the particles on every sub-step), and
+ * enter the due pairs with their current positions and predicted state.
+ * At the last boundary of T every level is due either way.  The per-level
+ * rates live in the context (allocated on the first call, 32 doubles per
+ * particle; with MFM_HIER_ACTIVE also one byte per particle and one bit per
+ * cell-table entry); they are computed by a pass over the current state with
+ * every level due when flags has MFM_HIER_REBIN, on the first call, when
  * max_bin changes, or after any other pass on the context.  With max_bin = 0
  * the call performs mfm_step's operations for a fixed dt = T (in separate
  * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64
- * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE hold the rates of the
- * last boundary (every level due) and the counters those of its pass. */
-mfm_status mfm_step_hier(mfm_ctx *ctx, mfm_particles *p, int64_t *bins, int32_t max_bin, double T, int32_t rebin,
+ * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE and vsig hold the
+ * rates and signal speeds of the last boundary (every level due) and the
+ * counters those of its pass. */
+#define MFM_HIER_REBIN 1
+#define MFM_HIER_ACTIVE 2
+mfm_status mfm_step_hier(mfm_ctx *ctx, mfm_particles *p, int64_t *bins, int32_t max_bin, double T, int32_t flags,
                          void *stream);
 
 /* Copy the per-level rates that the last mfm_step_hier left (those of its last

@@ -49,6 +49,8 @@ struct mfm_ctx {
     double* adj = nullptr;                // adjoint scratch, kAdjSlots x cap, allocated on first use
     double* lev = nullptr;                // per-level rates of hierarchical steps, 4 (kMaxBin+1) x cap, on first use
     int have_levels = 0, lev_nlev = 0;    // lev holds the rates of the current order, for lev_nlev levels
+    unsigned char* hmode = nullptr;       // per-particle modes of active-subset sub-steps, on first use
+    unsigned* hmarks = nullptr;           // one bit per cell-table entry: cells holding a due particle
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
@@ -236,7 +238,8 @@ void mfm_destroy(mfm_ctx* c) {
         }
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
-                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj, c->lev};
+                    c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj, c->lev,
+                    c->hmode, c->hmarks};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -940,8 +943,26 @@ static mfm_status do_fluxes_levels(mfm_ctx* c, mfm_particles* p, const long long
     return launched(c, "hydro_fluxes (levels)");
 }
 
+// A sub-step boundary's pass with active subsets (reading R26): kernel
+// lengths and gradients of the due particles only, the others keeping theirs.
+static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* bins, int lmin, int nlev,
+                                 hipStream_t s) {
+    const long long n = q->n;
+    PassArrays a = arrays_of(q);
+    launch_hier_modes((int)n, q->x, q->y, q->z, q->H, bins, lmin, c->td, c->tab_len, c->hmarks, c->hmode,
+                      c->gcount, c->counts, s);
+    launch_solve_h_active(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->hmode, c->rl, c->list, c->gcount, c->counts,
+                          c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, s);
+    launch_gradients_active(a, c->ph, c->hmode, c->gcount, c->counts, c->list, c->tails, c->prim, c->rec, c->cnt, s);
+    c->have_h = c->have_grad = 1;
+    c->rec_mixed = 0;
+    c->last = s;
+    if (mfm_status st = launched(c, "hydro_pass (active subsets)")) return st;
+    return do_fluxes_levels(c, q, bins, lmin, nlev, s);
+}
+
 extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins, int32_t max_bin, double T,
-                                    int32_t rebin, void* stream) {
+                                    int32_t flags, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
     if (c->p.scheme != MFM_SCHEME_MFM || c->p.precision != MFM_FP64)
@@ -951,18 +972,35 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
     if (!(T > 0.0) || !isfinite(T)) return fail(c, MFM_E_INVALID, "T must be positive and finite");
     if (!p->dp || !p->dE || !p->vsig || !p->nk || !p->V || !p->B || !p->rho || !p->P || !p->grad)
         return fail(c, MFM_E_INVALID, "hierarchical steps need every pass output array");
+    if (flags & ~(MFM_HIER_REBIN | MFM_HIER_ACTIVE)) return fail(c, MFM_E_INVALID, "unknown hierarchical step flag");
+    const bool rebin = flags & MFM_HIER_REBIN, active = flags & MFM_HIER_ACTIVE;
     (void)hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     const long long n = p->n;
     if (!c->lev && (st = hip_check(c, hipMalloc((void**)&c->lev, sizeof(double) * 4 * (kMaxBin + 1) * c->cap),
                                    "level rates")))
         return st;
+    if (active && !c->hmode) {
+        if ((st = hip_check(c, hipMalloc((void**)&c->hmode, c->cap), "sub-step modes"))) return st;
+        if ((st = hip_check(c, hipMalloc((void**)&c->hmarks, 8 * ((c->tab_len + 63) / 64)), "cell marks")))
+            return st;
+    }
     const int nlev = max_bin + 1;
     long long* b = (long long*)bins;
-    double* extra[kGatherMax * 2];
+    // reordered with the particles on each sub-step: the predicted state, the
+    // bins and the per-level rates; with active subsets also what an inactive
+    // particle keeps (n, V, B and the limited gradients; H always travels)
+    constexpr int kExtraMax = 6 + 4 * (kMaxBin + 1) + 23;
+    double* extra[kExtraMax];
     auto levels_extra = [&](int first) {
         int k = first;
         for (int q = 0; q < 4 * nlev; q++) extra[k++] = c->lev + (long long)q * n;
+        if (active) {
+            extra[k++] = p->nk;
+            extra[k++] = p->V;
+            for (int q = 0; q < 6; q++) extra[k++] = p->B + (long long)q * n;
+            for (int q = 0; q < 15; q++) extra[k++] = p->grad + (long long)q * n;
+        }
         return k;
     };
     reset_counters(c, s);
@@ -999,9 +1037,13 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         q.vy = c->vp + n;
         q.vz = c->vp + 2 * n;
         q.u = c->up;
-        if ((st = do_solve_h(c, &q, s))) return st;
-        if ((st = do_gradients(c, &q, s))) return st;
-        if ((st = do_fluxes_levels(c, &q, b, lmin, nlev, s))) return st;
+        if (active && lmin > 0) {
+            if ((st = do_pass_active(c, &q, b, lmin, nlev, s))) return st;
+        } else {
+            if ((st = do_solve_h(c, &q, s))) return st;
+            if ((st = do_gradients(c, &q, s))) return st;
+            if ((st = do_fluxes_levels(c, &q, b, lmin, nlev, s))) return st;
+        }
         a = arrays_of(p);
         launch_hier_kick((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, lmin, nlev, T, k < K ? 2 : 1, s);
     }

@@ -61,6 +61,20 @@ constexpr int kMaxBin = 7;
 void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts, const int* list, const void* rec,
                           Counters* cnt, const long long* bin, int lmin, int nlev, double* lev, hipStream_t s);
 
+// hierarchical steps with active subsets (FP64 records, MFM): a particle's
+// mode at a sub-step boundary is kModeSolve when its bin is due (new kernel
+// length and gradients), kModeKept when it keeps them but an active particle
+// may lie within its kernel length (it lists its gather set), kModeNone
+// otherwise (no gather list; it enters only the lists of active particles
+// that reach it)
+constexpr unsigned char kModeNone = 0, kModeSolve = 1, kModeKept = 2;
+void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* tab, const double4* pos,
+                           const Phys& ph, Counters* cnt, const unsigned char* mode, double* rl, int* list,
+                           int* gcount, int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
+                           unsigned long long* fb2_count, hipStream_t s);
+void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const int* gcount,
+                             int* counts, int* list, int* tails, double4* prim, void* rec, Counters* cnt,
+                             hipStream_t s);
 // step.hip
 void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor,
                        double* vp, double* up, double* Ehalf, hipStream_t s);
@@ -86,6 +100,14 @@ void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream
 void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
                          const double* E, const double* lev, int lmin, int nlev, double T, double u_floor,
                          double* vp, double* up, hipStream_t s);
+// the modes of one sub-step boundary: the cells (every level) of the due
+// particles are marked in marks (one bit per table entry, cleared here), and
+// a particle that is not due is kModeKept when the 3x3x3 cells around it, on
+// the finest level whose cells are at least its H wide, hold a mark; a
+// kModeNone particle's gather and list counts are set to zero
+void launch_hier_modes(int n, const double* x, const double* y, const double* z, const double* H,
+                       const long long* bins, int lmin, const TreeDesc& td, long long tab_len, unsigned* marks,
+                       unsigned char* mode, int* gcount, int* counts, hipStream_t s);
 void launch_hier_finish(int n, const double* m, const double* vx, const double* vy, const double* vz,
                         const double* E, double u_floor, double* u, Counters* cnt, hipStream_t s);
 

@@ -228,18 +228,22 @@ constexpr double kClassWindow = 2.0;
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
+// With HIER (hierarchical steps with active subsets) only the particles of
+// mode 1 solve; the others keep their kernel length.
 constexpr int kSolveWaves = 5;
+template <bool HIER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSolveWaves))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                   const double4* __restrict__ pos, Phys ph, Counters* cnt,
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
-                                                  int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count) {
+                                                  int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count,
+                                                  const unsigned char* __restrict__ mode) {
     cnt = counter_copy(cnt);
     __shared__ ScanLds lds[256 / kWave];
     ScanLds& S = lds[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int i = xcd_block() * 256 + threadIdx.x;
-    const bool act = i < a.n;
+    const bool act = i < a.n && (!HIER || mode[i] == kModeSolve);
     const long long n = a.n;
     const int cap = min(kRCap, ph.max_ngb);
     const double c32 = 32.0 / 3.0;
@@ -719,6 +723,55 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
     }
 }
 
+// Hierarchical steps with active subsets: a particle that keeps its kernel
+// length and has an active particle within reach (mode kModeKept) lists its
+// gather set r < H at the current positions with the scan and the distance
+// test of the kernel-length solve, so that both particles of a pair decide on
+// the same distance.  The lanes of a wave (Morton neighbours) scan together
+// over the largest of their radii.
+__global__ __launch_bounds__(256) void k_gather_kept(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
+                                                     const double4* __restrict__ pos, Phys ph,
+                                                     const unsigned char* __restrict__ mode, int* __restrict__ jl,
+                                                     int* __restrict__ gcount, int* __restrict__ counts) {
+    __shared__ ScanLds lds[256 / kWave];
+    ScanLds& S = lds[threadIdx.x / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int i = xcd_block() * 256 + threadIdx.x;
+    const bool sel = i < a.n && mode[i] == kModeKept;
+    if (__ballot(sel) == 0) return;   // uniform over the wave
+    const long long n = a.n;
+    double xi[3] = {0.0, 0.0, 0.0};
+    double H = 0.0;
+    if (sel) {
+        const double4 p = pos[i];
+        xi[0] = p.x;
+        xi[1] = p.y;
+        xi[2] = p.z;
+        H = a.H[i];
+    }
+    // scanned a little beyond H, so that no r < H is lost to the rounding of r^2
+    const double Rs = H * (1.0 + 1e-9);
+    const double Rq = uniform_d(wave_max_d(sel ? Rs : 0.0));
+    double bmin[3], bmax[3];
+    for (int d = 0; d < 3; d++) {
+        bmin[d] = uniform_d(wave_min_d(sel ? xi[d] : INFINITY));
+        bmax[d] = uniform_d(wave_max_d(sel ? xi[d] : -INFINITY));
+    }
+    const int cap = ph.max_ngb;
+    int c = 0;
+    group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, Rs * Rs, sel, [&](int j, double r2) {
+        const double r = sqrt(r2);
+        if (r < H && j != i) {
+            if (c < cap) jl[(long long)c * n + i] = j;
+            c++;
+        }
+    });
+    if (sel) {
+        gcount[i] = min(c, cap);
+        counts[i] = c;   // beyond cap: an overflow, counted when the tails are sorted
+    }
+}
+
 // --------------------------------------------------------------- flux lists
 // The flux set r < max(H_i, H_j) is the gather set of i plus every j that has
 // i in its gather set with r >= H_i.  The gradient kernel, which walks every
@@ -868,28 +921,61 @@ __global__ __launch_bounds__(256) void k_sort_tails(int n, int cap, const int* _
 enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G = 16, R_C = 31 };
 
 // What the gradient kernel reads of a neighbour, packed into one 128-byte line
-// per particle: (x, y, z, H), (rho, vx, vy, vz), (P, gather count, -, -), unused.
-__global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcount, double4* __restrict__ prim) {
+// per particle: (x, y, z, H), (rho, vx, vy, vz), (P, gather count, mode, -),
+// unused; the mode (hierarchical steps with active subsets) is 0 without one.
+__global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                            const unsigned char* __restrict__ mode, double4* __restrict__ prim) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const double rho = a.m[i] * a.nk[i];
     prim[4 * (long long)i + 0] = make_double4(a.x[i], a.y[i], a.z[i], a.H[i]);
     prim[4 * (long long)i + 1] = make_double4(rho, a.vx[i], a.vy[i], a.vz[i]);
-    prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], (double)gcount[i], 0.0, 0.0);
+    prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], (double)gcount[i],
+                                              mode ? (double)mode[i] : 0.0, 0.0);
+}
+
+// i is outside j's gather set: the pair enters j's flux list as a tail entry
+// (slots past the gather part, sorted afterwards); the first kTailNet go to
+// j's contiguous tail buffer, so the appends to one particle share a cache
+// line, the rest to the list itself
+__device__ __forceinline__ void append_tail(int* __restrict__ counts, int* __restrict__ tails,
+                                            int* __restrict__ list, int cap, long long n, int j, int jgather, int i) {
+    const int slot = atomicAdd(&counts[j], 1);
+    const int st = slot - jgather;
+    if (st < kTailNet) tails[(long long)j * kTailNet + st] = i;
+    else if (slot < cap) list[(long long)slot * n + j] = i;
 }
 
 // Four waves per SIMD (128 VGPRs, no spills): the kernel waits on the gathers
 // of its neighbours' records, and a fourth wave hides more of that than the
 // register budget it takes costs.
+// With HIER (hierarchical steps with active subsets) only the particles of
+// mode kModeSolve get new gradients; a kept particle with a gather list only
+// appends itself to the lists of its active neighbours that do not reach it.
 constexpr int kGradWaves = 4;
-template <bool MIXED>
+template <bool MIXED, bool HIER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
                                                     int* __restrict__ counts, int* __restrict__ list, int* __restrict__ tails,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
-                                                    Counters* cnt) {
+                                                    Counters* cnt, const unsigned char* __restrict__ mode) {
     cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
-    const bool act = i < a.n;
+    if (HIER && i < a.n && mode[i] == kModeKept) {
+        const long long n = a.n;
+        const double xi[3] = {a.x[i], a.y[i], a.z[i]};
+        const int cnum = gcount[i];
+        for (int k = 0; k < cnum; k++) {
+            const int j = list[(long long)k * n + i];
+            const double4 pj = prim[4 * (long long)j + 0];
+            const double4 pg = prim[4 * (long long)j + 2];
+            if (pg.z != (double)kModeSolve) continue;   // the pair is not due
+            double d[3];
+            displacement(ph, xi, pj.x, pj.y, pj.z, d);
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < pj.w)) append_tail(counts, tails, list, ph.max_ngb, n, j, (int)pg.y, i);
+        }
+    }
+    const bool act = i < a.n && (!HIER || mode[i] == kModeSolve);
     unsigned long long ill = 0, nonfin = 0, condbits = 0;
     if (act) {
         const long long n = a.n;
@@ -923,16 +1009,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves)
             double d[3];
             displacement(ph, xi, pj.x, pj.y, pj.z, d);
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < pj.w)) {
-                // i is outside j's gather set: the pair enters j's flux list as a
-                // tail entry (slots past the gather part, sorted afterwards); the
-                // first kTailNet go to j's contiguous tail buffer, so the appends to
-                // one particle share a cache line, the rest to the list itself
-                const int slot = atomicAdd(&counts[j], 1);
-                const int st = slot - (int)pg.y;
-                if (st < kTailNet) tails[(long long)j * kTailNet + st] = i;
-                else if (slot < cap) list[(long long)slot * n + j] = i;
-            }
+            if (!(r < pj.w)) append_tail(counts, tails, list, cap, n, j, (int)pg.y, i);
             const double phi_j[5] = {qj.x, qj.y, qj.z, qj.w, Pj};
             if (!MIXED) {
                 const double psi = norm * spline_w(r * iH) * Vi;
@@ -1102,6 +1179,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves)
     count_add(&cnt->illcond, ill);
     count_add(&cnt->nonfinite, nonfin);
     count_max(&cnt->cond_bits, condbits);
+}
+
+// Hierarchical steps with active subsets: the records of the particles that
+// keep their kernel length and gradients and take part in a due pair (a flux
+// list), from their kept H, V, n, B and limited gradients with the current
+// position and predicted state, as the gradient kernel writes them.
+__global__ void k_pack_rec_kept(PassArrays a, Phys ph, const unsigned char* __restrict__ mode,
+                                const int* __restrict__ counts, double* __restrict__ recp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n || mode[i] == kModeSolve || counts[i] == 0) return;
+    const long long n = a.n;
+    const double Hi = a.H[i], Vi = a.V[i];
+    const double rho_i = a.m[i] * a.nk[i];
+    const double P_i = (ph.gamma - 1.0) * rho_i * a.u[i];
+    double v[32];
+    v[0] = a.x[i];
+    v[1] = a.y[i];
+    v[2] = a.z[i];
+    v[R_IH] = 1.0 / Hi;
+    v[R_K] = Vi * Vi * kernel_norm(Hi);
+    v[R_RHO] = rho_i;
+    v[R_P] = P_i;
+    v[R_V0 + 0] = a.vx[i];
+    v[R_V0 + 1] = a.vy[i];
+    v[R_V0 + 2] = a.vz[i];
+#pragma unroll
+    for (int k = 0; k < 6; k++) v[R_B + k] = a.B[k * n + i];
+#pragma unroll
+    for (int k = 0; k < 15; k++) v[R_G + k] = a.grad[k * n + i];
+    v[R_C] = sqrt(ph.gamma * P_i / rho_i);
+    double2* r2 = (double2*)(recp + (long long)i * 32);
+#pragma unroll
+    for (int k = 0; k < 16; k++) r2[k] = make_double2(v[2 * k], v[2 * k + 1]);
 }
 
 // ------------------------------------------------------------------- fluxes
@@ -1403,7 +1513,14 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
     if (act) {
         const long long n = a.n;
         T ri[32];
-        load_rec<T>(rec, i, ri);
+        // in the levelled pass most particles of a partial boundary have no
+        // list: their record is not read (its values only enter pairs)
+        if (LEV && counts[i] == 0) {
+#pragma unroll
+            for (int q = 0; q < 32; q++) ri[q] = T(0);
+        } else {
+            load_rec<T>(rec, i, ri);
+        }
         const double xi[3] = {a.x[i], a.y[i], a.z[i]};
         const double vi[3] = {(double)ri[R_V0], (double)ri[R_V0 + 1], (double)ri[R_V0 + 2]};
         const double ci = (double)ri[R_C];
@@ -1429,6 +1546,14 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         for (int k = 0; k < cnum; k++) {
             const int j = jn;
             if (k + 1 < cnum) jn = list[(long long)(k + 1) * n + i];
+            int lj = 0;
+            if (LEV) {
+                // a pair that is not due costs its bin alone: no record, no flux,
+                // no signal speed (the last boundary of a system step has every
+                // pair due, so the signal speeds it leaves are complete)
+                lj = max(bi, (int)lv.bin[j]);
+                if (lj < lv.lmin) continue;
+            }
             T rj[32];
             load_rec<T>(rec, j, rj);
             double xj[3];
@@ -1445,21 +1570,13 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             displacement(ph, xi, xj[0], xj[1], xj[2], dij);   // x_j - x_i
             const double r = sqrt(dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2]);
             const bool iL = i < j;
-            // signal speed over every flux neighbour, due or not
+            // signal speed over the flux neighbours (the due ones in the levelled pass)
             auto signal = [&]() {
                 const double cj = (double)rj[R_C];
                 const double proj = -((vi[0] - (double)rj[R_V0]) * dij[0] + (vi[1] - (double)rj[R_V0 + 1]) * dij[1] +
                                       (vi[2] - (double)rj[R_V0 + 2]) * dij[2]) / r;
                 vs = fmax(vs, ci + cj - fmin(proj, 0.0));
             };
-            int lj = 0;
-            if (LEV) {
-                lj = max(bi, (int)lv.bin[j]);
-                if (lj < lv.lmin) {   // the pair is not due
-                    signal();
-                    continue;
-                }
-            }
             // canonical displacement x_R - x_L: the minimum image commutes with
             // negation exactly, so both owners of the pair hold the same bits
             const double sg = iL ? 1.0 : -1.0;
@@ -1573,8 +1690,8 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
     launch_fill_u64(1, fb_count, 0ull, s);
     launch_fill_u64(1, fb2_count, 0ull, s);
     if (t0) hipEventRecord(t0, s);
-    k_solve_h<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
-                                                  fb_list, fb_count);
+    k_solve_h<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
+                                                         fb_list, fb_count, nullptr);
     // one wave per handed-over particle, striding over the count left on the device
     k_solve_h_wave<<<kWaveBlocks, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, rl, list, gcount,
                                               counts, fb2_list, fb2_count);
@@ -1586,13 +1703,40 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
 void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, int* counts, int* list, int* tails,
                       int mixed, double4* prim, void* rec, Counters* cnt, hipEvent_t t0, hipEvent_t t1,
                       hipStream_t s) {
-    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, prim);
+    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, nullptr, prim);
     if (t0) hipEventRecord(t0, s);
     if (mixed)
-        k_gradients<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt);
+        k_gradients<true, false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec,
+                                                                     cnt, nullptr);
     else
-        k_gradients<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt);
+        k_gradients<false, false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec,
+                                                                      cnt, nullptr);
     if (t1) hipEventRecord(t1, s);
+    k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
+}
+
+void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* tab, const double4* pos,
+                           const Phys& ph, Counters* cnt, const unsigned char* mode, double* rl, int* list,
+                           int* gcount, int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
+                           unsigned long long* fb2_count, hipStream_t s) {
+    launch_fill_u64(1, fb_count, 0ull, s);
+    launch_fill_u64(1, fb2_count, 0ull, s);
+    k_solve_h<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
+                                                        fb_list, fb_count, mode);
+    k_solve_h_wave<<<kWaveBlocks, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, rl, list, gcount,
+                                              counts, fb2_list, fb2_count);
+    k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb2_list, fb2_count, list, gcount,
+                                                     counts);
+    k_gather_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, mode, list, gcount, counts);
+}
+
+void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const int* gcount,
+                             int* counts, int* list, int* tails, double4* prim, void* rec, Counters* cnt,
+                             hipStream_t s) {
+    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, mode, prim);
+    k_gradients<false, true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt,
+                                                                 mode);
+    k_pack_rec_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, mode, counts, (double*)rec);
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
 

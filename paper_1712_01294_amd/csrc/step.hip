@@ -337,6 +337,143 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
     k_hier_predict<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, lmin, nlev, T, u_floor, vp, up);
 }
 
+// ------------------------------------------- active subsets of hierarchical steps
+// deposited key of the level-l cell holding x (per axis floor(x / side),
+// clamped to the level's cells): the index of that cell's table entry past
+// the level's offset
+__device__ __forceinline__ unsigned long long cell_key(const TreeDesc& td, int l, const double x[3]) {
+    unsigned long long key = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int c = min(td.ncell[l][d] - 1, max(0, (int)floor(x[d] / td.cs[l][d])));
+        key |= deposit_bits((unsigned)c, td.mask[l][d]);
+    }
+    return key;
+}
+
+// A due particle marks its cell on every level.  Morton neighbours share their
+// coarse cells, so within a wave only the first lane of a run of equal cells
+// marks, and only when the bit is not already set.
+__global__ void k_hier_mark(int n, const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, const long long* __restrict__ bins, int lmin, TreeDesc td,
+                            unsigned* __restrict__ marks) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool act = i < n && bins[i] >= lmin;
+    if (__ballot(act) == 0) return;   // uniform over the wave
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (act) {
+        xi[0] = x[i];
+        xi[1] = y[i];
+        xi[2] = z[i];
+    }
+    for (int l = 0; l <= td.bmax; l++) {
+        const unsigned long long e = act ? (unsigned long long)td.tab_off[l] + cell_key(td, l, xi) : ~0ull;
+        const unsigned lo = __shfl_up((unsigned)(e & 0xffffffffull), 1, kWave);
+        const unsigned hi = __shfl_up((unsigned)(e >> 32), 1, kWave);
+        const unsigned long long prev = ((unsigned long long)hi << 32) | lo;
+        if (act && (lane == 0 || prev != e)) {
+            const unsigned bit = 1u << (e & 31);
+            if (!(marks[e >> 5] & bit)) atomicOr(&marks[e >> 5], bit);
+        }
+    }
+}
+
+// Every point within H of x lies in the 3x3x3 cells around x's cell on a level
+// whose cells are at least H wide (per axis the cells c - 1 .. c + 1, wrapping
+// on periodic axes of three or more cells; an axis of fewer cells is taken
+// whole), and so does its cell by the same clamped floor; of those, only the
+// cells whose box comes within H of x can hold it (on an open axis the edge
+// cells reach out to infinity, as the clamp puts everything beyond them
+// there).  A particle that is not due is kept with a gather list when one of
+// them is marked.
+__global__ void k_hier_mode(int n, const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, const double* __restrict__ H,
+                            const long long* __restrict__ bins, int lmin, TreeDesc td,
+                            const unsigned* __restrict__ marks, unsigned char* __restrict__ mode,
+                            int* __restrict__ gcount, int* __restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (bins[i] >= lmin) {
+        mode[i] = kModeSolve;
+        return;
+    }
+    const double xi[3] = {x[i], y[i], z[i]};
+    const double h = H[i];
+    const double h2 = (h * (1.0 + 1e-9)) * (h * (1.0 + 1e-9));
+    int l = td.bmax;
+    while (l > 0 && fmin(td.cs[l][0], fmin(td.cs[l][1], td.cs[l][2])) < h) l--;
+    int u0[3], cnt[3];
+    unsigned long long dc[3], one[3];
+    double g2[3][3];   // squared distance from x to the box of the o-th cell of the axis
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int nc = td.ncell[l][d];
+        const double cs = td.cs[l][d];
+        const int c = min(nc - 1, max(0, (int)floor(xi[d] / cs)));
+        const unsigned long long m = td.mask[l][d];
+        one[d] = m & (~m + 1);
+        if (nc < 3) {
+            u0[d] = 0;
+            cnt[d] = nc;
+            dc[d] = 0;
+        } else if (td.periodic[d]) {
+            u0[d] = c - 1;
+            cnt[d] = 3;
+            dc[d] = dilated_sub(deposit_bits((unsigned)c, m), one[d], m);
+        } else {
+            u0[d] = max(c - 1, 0);
+            cnt[d] = min(c + 1, nc - 1) - u0[d] + 1;
+            dc[d] = deposit_bits((unsigned)u0[d], m);
+        }
+#pragma unroll
+        for (int o = 0; o < 3; o++) {
+            const int u = u0[d] + o;   // unwrapped on periodic axes
+            double lo = u * cs, hi = (u + 1) * cs;
+            if (nc < 3) {
+                lo = -INFINITY;
+                hi = INFINITY;
+            } else if (!td.periodic[d]) {
+                if (u == 0) lo = -INFINITY;
+                if (u == nc - 1) hi = INFINITY;
+            }
+            const double g = fmax(0.0, fmax(lo - xi[d], xi[d] - hi));
+            g2[d][o] = g * g;
+        }
+    }
+    const long long off = td.tab_off[l];
+    bool hit = false;
+    unsigned long long kx = dc[0];
+    for (int ox = 0; ox < cnt[0] && !hit; ox++) {
+        unsigned long long ky = dc[1];
+        for (int oy = 0; oy < cnt[1] && !hit; oy++) {
+            unsigned long long kz = dc[2];
+            for (int oz = 0; oz < cnt[2] && !hit; oz++) {
+                if (g2[0][ox] + g2[1][oy] + g2[2][oz] < h2) {
+                    const unsigned long long e = (unsigned long long)off + (kx | ky | kz);
+                    hit = (marks[e >> 5] >> (e & 31)) & 1u;
+                }
+                kz = dilated_add(kz, one[2], td.mask[l][2]);
+            }
+            ky = dilated_add(ky, one[1], td.mask[l][1]);
+        }
+        kx = dilated_add(kx, one[0], td.mask[l][0]);
+    }
+    mode[i] = hit ? kModeKept : kModeNone;
+    if (!hit) {
+        gcount[i] = 0;
+        counts[i] = 0;
+    }
+}
+
+void launch_hier_modes(int n, const double* x, const double* y, const double* z, const double* H,
+                       const long long* bins, int lmin, const TreeDesc& td, long long tab_len, unsigned* marks,
+                       unsigned char* mode, int* gcount, int* counts, hipStream_t s) {
+    launch_fill_u64((tab_len + 63) / 64, (unsigned long long*)marks, 0ull, s);
+    k_hier_mark<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, z, bins, lmin, td, marks);
+    k_hier_mode<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, z, H, bins, lmin, td, marks, mode, gcount, counts);
+}
+
 void launch_hier_finish(int n, const double* m, const double* vx, const double* vy, const double* vz,
                         const double* E, double u_floor, double* u, Counters* cnt, hipStream_t s) {
     k_hier_finish<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, u_floor, u, cnt);

@@ -261,14 +261,17 @@ class Context:
         self._rc(self._L.mfm_step(self.h, C.byref(p), C.c_double(dt), C.byref(used), _stream(stream)))
         return used.value
 
-    def step_hier(self, st: State, bins, max_bin: int, T: float, rebin: bool = False, stream=None):
+    def step_hier(self, st: State, bins, max_bin: int, T: float, rebin: bool = False, active: bool = False,
+                  stream=None):
         """One system step of length T with hierarchical power-of-two steps
-        (mfm_step_hier); bins (int64 device tensor, n) is reordered with st."""
+        (mfm_step_hier); bins (int64 device tensor, n) is reordered with st.
+        rebin: MFM_HIER_REBIN; active: MFM_HIER_ACTIVE (active subsets)."""
         if bins.dtype != torch.int64 or not bins.is_cuda or not bins.is_contiguous():
             raise ValueError("bins must be a contiguous int64 device tensor")
         p = st.struct()
         self._rc(self._L.mfm_step_hier(self.h, C.byref(p), C.c_void_p(bins.data_ptr()), C.c_int32(max_bin),
-                                       C.c_double(T), C.c_int32(1 if rebin else 0), _stream(stream)))
+                                       C.c_double(T), C.c_int32((HIER_REBIN if rebin else 0) | (HIER_ACTIVE if active else 0)),
+                                       _stream(stream)))
 
     def levels(self, n: int, nlev: int, stream=None):
         """The per-level rates of the last hierarchical step's last boundary,
@@ -345,6 +348,9 @@ class Context:
         self._rc(self._L.mfm_copy_flux_lists(self.h, C.c_void_p(counts.data_ptr()),
                                              C.c_void_p(lst.data_ptr()), _stream(stream)))
         return counts, lst
+
+
+HIER_REBIN, HIER_ACTIVE = 1, 2   # mfm_step_hier flags (MFM_HIER_REBIN, MFM_HIER_ACTIVE)
 
 
 NOALLOC_MAX_N = 8192   # particles per mfm_hydro_pass_noalloc call

@@ -187,3 +187,162 @@ def test_hierarchical_step_argument_checks():
     with pytest.raises(mfm.MFMError) as e:
         cm.step_hier(sm, b, 1, 1e-3)
     assert e.value.status == -1
+
+
+# ---------------------------------------------------------------- R26
+def _compare_with_oracle(st, ref, ctx, w, nlev, tol=1e-10):
+    L = np.array(w.box)
+    for c, k in enumerate(("x", "y", "z")):
+        d = in_input_order(st, k) - ref.st[k]
+        d -= L[c] * np.round(d / L[c])
+        assert np.abs(d).max() <= tol * L[c], k
+    vmax = max(np.abs(ref.st[k]).max() for k in ("vx", "vy", "vz"))
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= tol * vmax, k
+    assert nerr(in_input_order(st, "u"), ref.st["u"]) <= tol
+    ids = st.id.cpu().numpy()
+    lv = ctx.levels(w.n, nlev).cpu().numpy()
+    lio = np.empty_like(lv)
+    lio[..., ids] = lv
+    assert nerr(lio, ref.lev[:, :4]) <= tol
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_active_subsets_match_oracle(levels):
+    """Active subsets (R26): two system steps with particles binned by x, the
+    inactive particles keeping their kernel lengths and gradients; state and
+    per-level rates within 1e-10 of the oracle's R26 stepper, and the last
+    boundary's rates (every level due) too."""
+    import torch
+    w = _smooth(16, W.SEED_BASE + 171)
+    bins = np.minimum((w.x * levels).astype(np.int64), levels - 1)
+    T = 0.004
+    ref = O.Stepper(w, u_floor=0.0)
+    ref.set_bins(bins)
+    for _ in range(2):
+        ref.hier_step(T, active=True)
+    ctx, st = _gpu(w)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    for k in range(2):
+        ctx.step_hier(st, b, levels - 1, T, rebin=(k == 0), active=True)
+    ctx.check()
+    _compare_with_oracle(st, ref, ctx, w, levels)
+    assert nerr(in_input_order(st, "dp"), ref.last["dp"]) <= 1e-10
+    assert nerr(in_input_order(st, "dE"), ref.last["dE"]) <= 1e-10
+    assert np.array_equal(b.cpu().numpy(), bins[st.id.cpu().numpy()])
+
+
+def test_active_subsets_with_random_bins_across_six_levels():
+    """Random bins 0..5 on a 2,744-particle box, one system step of 32
+    sub-steps with active subsets: at most boundaries the active particles are
+    scattered through inactive ones, so kept particles list their gather sets,
+    tails cross between active and kept particles, and particles without a
+    list enter only through tails.  Within 1e-10 of the oracle; momentum
+    conserved to rounding."""
+    import torch
+    w = _smooth(14, W.SEED_BASE + 172)
+    rng = np.random.default_rng(W.SEED_BASE + 173)
+    bins = rng.integers(0, 6, size=w.n).astype(np.int64)
+    T = 0.004
+    ref = O.Stepper(w, u_floor=0.0)
+    ref.set_bins(bins)
+    ref.hier_step(T, active=True)
+    ctx, st = _gpu(w)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    ctx.step_hier(st, b, 5, T, rebin=True, active=True)
+    ctx.check()
+    _compare_with_oracle(st, ref, ctx, w, 6)
+    m = st.m.cpu().numpy()
+    v = [getattr(st, k).cpu().numpy() for k in ("vx", "vy", "vz")]
+    p0 = [float((w.m * getattr(w, k)).sum()) for k in ("vx", "vy", "vz")]
+    scale = float(np.abs(m * v[0]).sum())
+    for c in range(3):
+        assert abs(float((m * v[c]).sum()) - p0[c]) <= 1e-13 * scale
+
+
+def test_active_subsets_on_a_clustered_set():
+    """A clustered log-normal set of 32,768 particles binned from each
+    particle's Courant step (four levels, the finer bins in the dense clumps;
+    1,124 to 5,325 particles active on the partial boundaries).  The set starts
+    far from equilibrium and the Courant step does not bound its
+    accelerations, so the system step is the smallest Courant step (the bins
+    then step by 1/8 to 1 of it).  One system step with active subsets within
+    1e-10 of the oracle."""
+    import torch
+    w = W.clustered(n_side=32, seed=W.SEED_BASE + 174)
+    ref = O.Stepper(w, u_floor=0.0)
+    with O.openmp():
+        out = ref.start()
+        dti = w.cfl * out["H"] / out["vsig"]
+        dtmin = float(dti.min())
+        bins = np.clip(3 - np.floor(np.log2(dti / dtmin)), 0, 3).astype(np.int64)
+        hist = np.bincount(bins, minlength=4)
+        print("clustered bins", hist, flush=True)
+        assert hist[0] > 0 and hist[3] > 0
+        T = dtmin
+        ref.set_bins(bins, max_bin=3)
+        ref.hier_step(T, active=True)
+    from paper_1712_01294_amd import mfm
+    # flux lists of up to about 320 entries on this set
+    ctx = mfm.Context(mfm.config_of(w, u_floor=0.0, max_ngb=1024), w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    ctx.step_hier(st, b, 3, T, rebin=True, active=True)
+    ctx.check(allow_illcond=True)
+    _compare_with_oracle(st, ref, ctx, w, 4)
+
+
+def test_active_subsets_with_every_particle_due_equal_full_passes_bitwise():
+    """Every particle in bin 1 of two levels: every boundary has all particles
+    active, and the active-subset kernels (all of mode solve) give the full
+    passes' results bit for bit."""
+    import torch
+    w = _smooth(12, W.SEED_BASE + 175)
+    c1, s1 = _gpu(w)
+    c2, s2 = _gpu(w)
+    b1 = torch.ones(w.n, dtype=torch.int64, device="cuda")
+    b2 = b1.clone()
+    for k in range(2):
+        c1.step_hier(s1, b1, 1, 0.004, rebin=(k == 0))
+        c2.step_hier(s2, b2, 1, 0.004, rebin=(k == 0), active=True)
+    c1.check()
+    c2.check()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "H", "dp", "dE", "id"):
+        assert torch.equal(getattr(s1, k), getattr(s2, k)), k
+    assert torch.equal(c1.levels(w.n, 2), c2.levels(w.n, 2))
+
+
+def test_active_subsets_conserve_on_the_shock_tube():
+    import torch
+    w = W.shock_tube(n_yz=12, l_yz=12 / 64)
+    bins = (w.x < 1.0).astype(np.int64)
+    T = 0.004
+    ref = O.Stepper(w)
+    ref.set_bins(bins)
+    for _ in range(3):
+        ref.hier_step(T, active=True)
+    from paper_1712_01294_amd import mfm
+    ctx = mfm.Context(mfm.config_of(w), w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+    for k in range(3):
+        ctx.step_hier(st, b, 1, T, rebin=(k == 0), active=True)
+    ctx.check()
+    m = st.m.cpu().numpy()
+    v = [getattr(st, k).cpu().numpy() for k in ("vx", "vy", "vz")]
+    u = st.u.cpu().numpy()
+    p0 = [float((w.m * getattr(w, k)).sum()) for k in ("vx", "vy", "vz")]
+    E0 = float((w.m * (w.u + 0.5 * (w.vx ** 2 + w.vy ** 2 + w.vz ** 2))).sum())
+    E = float((m * (u + 0.5 * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2))).sum())
+    scale = float(np.abs(m * v[0]).sum())
+    for c in range(3):
+        assert abs(float((m * v[c]).sum()) - p0[c]) <= 1e-13 * scale
+    assert E == pytest.approx(E0, rel=1e-13)
+    vmax = np.abs(ref.st["vx"]).max()
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= 1e-10 * vmax, k
+    assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
