@@ -232,8 +232,10 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * only the particles whose own bin is due at a boundary get new kernel
  * lengths, densities, volumes, gradient matrices and limited gradients; the
  * others keep those of their last active boundary, in nk, V, B and grad
- * (which the call then reorders with the particles on every sub-step), and
- * enter the due pairs with their current positions and predicted state.
+ * (during the call B and grad hold each particle's values in the column where
+ * it stood at the call's start; on return every array is in the particles'
+ * current order), and enter the due pairs with their current positions and
+ * predicted state.
  * At the last boundary of T every level is due either way.  The per-level
  * rates live in the context (allocated on the first call, 32 doubles per
  * particle; with MFM_HIER_ACTIVE also one byte per particle and one bit per

@@ -51,6 +51,7 @@ struct mfm_ctx {
     int have_levels = 0, lev_nlev = 0;    // lev holds the rates of the current order, for lev_nlev levels
     unsigned char* hmode = nullptr;       // per-particle modes of active-subset sub-steps, on first use
     unsigned* hmarks = nullptr;           // one bit per cell-table entry: cells holding a due particle
+    long long* hhome = nullptr;           // per particle: its column of the rates within a system step
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
@@ -239,7 +240,7 @@ void mfm_destroy(mfm_ctx* c) {
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
                     c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj, c->lev,
-                    c->hmode, c->hmarks};
+                    c->hmode, c->hmarks, c->hhome};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -934,10 +935,10 @@ extern "C" mfm_status mfm_step_adjoint_taped(mfm_ctx* c, const mfm_particles* ck
 
 // ------------------------------------------------------------ hierarchical steps
 static mfm_status do_fluxes_levels(mfm_ctx* c, mfm_particles* p, const long long* bins, int lmin, int nlev,
-                                   hipStream_t s) {
+                                   const long long* home, hipStream_t s) {
     if (!c->have_grad || c->n_tree != p->n) return fail(c, MFM_E_STATE, "mfm_gradients must run first");
     PassArrays a = arrays_of(p);
-    launch_fluxes_levels(a, c->ph, c->counts, c->list, c->rec, c->cnt, bins, lmin, nlev, c->lev, s);
+    launch_fluxes_levels(a, c->ph, c->counts, c->list, c->rec, c->cnt, bins, lmin, nlev, c->lev, home, s);
     c->have_flux = 1;
     c->last = s;
     return launched(c, "hydro_fluxes (levels)");
@@ -953,12 +954,13 @@ static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* 
                       c->gcount, c->counts, s);
     launch_solve_h_active(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->hmode, c->rl, c->list, c->gcount, c->counts,
                           c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, s);
-    launch_gradients_active(a, c->ph, c->hmode, c->gcount, c->counts, c->list, c->tails, c->prim, c->rec, c->cnt, s);
+    launch_gradients_active(a, c->ph, c->hmode, c->hhome, c->gcount, c->counts, c->list, c->tails, c->prim, c->rec,
+                            c->cnt, s);
     c->have_h = c->have_grad = 1;
     c->rec_mixed = 0;
     c->last = s;
     if (mfm_status st = launched(c, "hydro_pass (active subsets)")) return st;
-    return do_fluxes_levels(c, q, bins, lmin, nlev, s);
+    return do_fluxes_levels(c, q, bins, lmin, nlev, c->hhome, s);
 }
 
 extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins, int32_t max_bin, double T,
@@ -985,53 +987,43 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         if ((st = hip_check(c, hipMalloc((void**)&c->hmarks, 8 * ((c->tab_len + 63) / 64)), "cell marks")))
             return st;
     }
+    if (!c->hhome && (st = hip_check(c, hipMalloc((void**)&c->hhome, sizeof(long long) * c->cap), "home columns")))
+        return st;
     const int nlev = max_bin + 1;
     long long* b = (long long*)bins;
-    // reordered with the particles on each sub-step: the predicted state, the
-    // bins and the per-level rates; with active subsets also what an inactive
-    // particle keeps (n, V, B and the limited gradients; H always travels)
-    constexpr int kExtraMax = 6 + 4 * (kMaxBin + 1) + 23;
-    double* extra[kExtraMax];
-    auto levels_extra = [&](int first) {
-        int k = first;
-        for (int q = 0; q < 4 * nlev; q++) extra[k++] = c->lev + (long long)q * n;
-        if (active) {
-            extra[k++] = p->nk;
-            extra[k++] = p->V;
-            for (int q = 0; q < 6; q++) extra[k++] = p->B + (long long)q * n;
-            for (int q = 0; q < 15; q++) extra[k++] = p->grad + (long long)q * n;
-        }
-        return k;
-    };
     reset_counters(c, s);
     if (rebin || !c->have_levels || c->lev_nlev != nlev || c->n_tree != p->n) {
         // the per-level rates of the current state, every level due
-        extra[0] = (double*)b;
-        if ((st = build(c, p, s, extra, 1))) return st;
+        double* e1[1] = {(double*)b};
+        if ((st = build(c, p, s, e1, 1))) return st;
         if ((st = do_solve_h(c, p, s))) return st;
         if ((st = do_gradients(c, p, s))) return st;
-        if ((st = do_fluxes_levels(c, p, b, 0, nlev, s))) return st;
+        if ((st = do_fluxes_levels(c, p, b, 0, nlev, nullptr, s))) return st;
     } else if (!c->have_flux) {
         return fail(c, MFM_E_STATE, "hierarchical steps continue from a hierarchical step on this state");
     }
     const int K = 1 << max_bin;
     const double delta = T / (double)K;
     launch_hier_begin((int)n, p->m, p->vx, p->vy, p->vz, p->u, c->Ehalf, c->lev, nlev, T, s);
-    PassArrays a = arrays_of(p);
+    // Within the system step a particle's per-level rates (and, with active
+    // subsets, its kept gradient matrix and limited gradients) stay in the column
+    // where it stood at the start, home[i]; each sub-step's reorder carries the
+    // particle state, E, the bins and home (with active subsets also the kept n
+    // and V), but not the pass outputs and u, which are written anew, nor the
+    // predicted state, which is predicted after the reorder.
+    launch_iota((int)n, c->hhome, s);
+    mfm_particles pb = *p;
+    pb.dp = pb.dE = pb.vsig = pb.u = pb.dm = nullptr;
     for (int k = 1; k <= K; k++) {
-        launch_hier_drift(a, c->ph, delta, s);
+        launch_hier_drift(arrays_of(p), c->ph, delta, s);
         const int tz = __builtin_ctz((unsigned)k);
         const int lmin = max_bin - tz > 0 ? max_bin - tz : 0;
-        launch_hier_predict((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, lmin, nlev, T, c->p.u_floor, c->vp,
-                            c->up, s);
-        extra[0] = c->vp;
-        extra[1] = c->vp + n;
-        extra[2] = c->vp + 2 * n;
-        extra[3] = c->up;
-        extra[4] = c->Ehalf;
-        extra[5] = (double*)b;
-        const int ne = levels_extra(6);
-        if ((st = build(c, p, s, extra, ne))) return st;
+        double* extra[5] = {c->Ehalf, (double*)b, (double*)c->hhome, p->nk, p->V};
+        if ((st = build(c, &pb, s, extra, active ? 5 : 3))) return st;
+        launch_hier_predict((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, c->hhome, lmin, nlev, T,
+                            c->p.u_floor, c->vp, c->up, s);
+        // the last boundary rewrites every level, in the current order
+        if (lmin == 0) launch_iota((int)n, c->hhome, s);
         mfm_particles q = *p;
         q.vx = c->vp;
         q.vy = c->vp + n;
@@ -1042,10 +1034,10 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         } else {
             if ((st = do_solve_h(c, &q, s))) return st;
             if ((st = do_gradients(c, &q, s))) return st;
-            if ((st = do_fluxes_levels(c, &q, b, lmin, nlev, s))) return st;
+            if ((st = do_fluxes_levels(c, &q, b, lmin, nlev, c->hhome, s))) return st;
         }
-        a = arrays_of(p);
-        launch_hier_kick((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, lmin, nlev, T, k < K ? 2 : 1, s);
+        launch_hier_kick((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, c->hhome, lmin, nlev, T,
+                         k < K ? 2 : 1, s);
     }
     launch_hier_finish((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->p.u_floor, p->u, c->cnt, s);
     c->have_levels = 1;

@@ -58,8 +58,10 @@ void launch_fluxes(const PassArrays& a, const Phys& ph, const int* counts, const
 // hierarchical steps: the pairs of level >= lmin (level = the finer bin of the
 // two), their per-level sums into lev[(l * 4 + c) * n + i] (FP64 records, MFM)
 constexpr int kMaxBin = 7;
+// (particle i's sums at column home[i] of lev; home null: column i)
 void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts, const int* list, const void* rec,
-                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev, hipStream_t s);
+                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev,
+                          const long long* home, hipStream_t s);
 
 // hierarchical steps with active subsets (FP64 records, MFM): a particle's
 // mode at a sub-step boundary is kModeSolve when its bin is due (new kernel
@@ -72,9 +74,11 @@ void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* 
                            const Phys& ph, Counters* cnt, const unsigned char* mode, double* rl, int* list,
                            int* gcount, int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
                            unsigned long long* fb2_count, hipStream_t s);
-void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const int* gcount,
-                             int* counts, int* list, int* tails, double4* prim, void* rec, Counters* cnt,
-                             hipStream_t s);
+// (the new gradient matrices and limited gradients of the active particles, and
+// the kept ones read for the records, at column home[i] of B and grad)
+void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const long long* home,
+                             const int* gcount, int* counts, int* list, int* tails, double4* prim, void* rec,
+                             Counters* cnt, hipStream_t s);
 // step.hip
 void launch_kick_drift(const PassArrays& a, const Phys& ph, double dt, double u_floor,
                        double* vp, double* up, double* Ehalf, hipStream_t s);
@@ -88,18 +92,21 @@ void launch_dt_min(int n, const double* H, const double* vsig, double* partial, 
                    double* out, hipStream_t s);
 int dt_min_parts(int n);
 // hierarchical steps: E = m (u + |v|^2/2) into E and the opening kicks of every
-// level (begin); kicks of the levels >= lmin with their sums in lev, each of
-// weight T / 2^(l+1), applied `times` times (v and E in place); drift
-// x += dt v; predicted v, u of the pass; the recovery u = E/m - |v|^2/2
-// (floored) at the end
+// level (begin, rates in the particles' order); kicks of the levels >= lmin
+// with their sums in lev, each of weight T / 2^(l+1), applied `times` times
+// (v and E in place); drift x += dt v; predicted v, u of the pass; the
+// recovery u = E/m - |v|^2/2 (floored) at the end.  Within a system step a
+// particle's rates stay in the column of lev where it stood at the step's
+// start, home[i], which travels with the particle (launch_iota sets it).
 void launch_hier_begin(int n, const double* m, double* vx, double* vy, double* vz, const double* u, double* E,
                        const double* lev, int nlev, double T, hipStream_t s);
 void launch_hier_kick(int n, const double* m, double* vx, double* vy, double* vz, double* E, const double* lev,
-                      int lmin, int nlev, double T, int times, hipStream_t s);
+                      const long long* home, int lmin, int nlev, double T, int times, hipStream_t s);
 void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s);
 void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
-                         const double* E, const double* lev, int lmin, int nlev, double T, double u_floor,
-                         double* vp, double* up, hipStream_t s);
+                         const double* E, const double* lev, const long long* home, int lmin, int nlev, double T,
+                         double u_floor, double* vp, double* up, hipStream_t s);
+void launch_iota(int n, long long* v, hipStream_t s);
 // the modes of one sub-step boundary: the cells (every level) of the due
 // particles are marked in marks (one bit per table entry, cleared here), and
 // a particle that is not due is kModeKept when the 3x3x3 cells around it, on

@@ -957,7 +957,8 @@ template <bool MIXED, bool HIER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves))) void k_gradients(PassArrays a, Phys ph, const int* __restrict__ gcount,
                                                     int* __restrict__ counts, int* __restrict__ list, int* __restrict__ tails,
                                                     const double4* __restrict__ prim, void* __restrict__ recp,
-                                                    Counters* cnt, const unsigned char* __restrict__ mode) {
+                                                    Counters* cnt, const unsigned char* __restrict__ mode,
+                                                    const long long* __restrict__ home) {
     cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
     if (HIER && i < a.n && mode[i] == kModeKept) {
@@ -1115,16 +1116,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves)
             g[3 * f + 1] = alpha * g1;
             g[3 * f + 2] = alpha * g2;
         }
+        const long long io = HIER ? home[i] : i;   // column of B, grad and alpha
 #pragma unroll
-        for (int k = 0; k < 6; k++) a.B[k * n + i] = B[k];
+        for (int k = 0; k < 6; k++) a.B[k * n + io] = B[k];
 #pragma unroll
         for (int k = 0; k < 15; k++) {
-            a.grad[k * n + i] = g[k];
+            a.grad[k * n + io] = g[k];
             if (!isfinite(g[k])) nonfin = 1;
         }
         if (a.alpha) {
 #pragma unroll
-            for (int f = 0; f < 5; f++) a.alpha[f * n + i] = al[f];
+            for (int f = 0; f < 5; f++) a.alpha[f * n + io] = al[f];
         }
         a.rho[i] = rho_i;
         a.P[i] = P_i;
@@ -1183,13 +1185,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves)
 
 // Hierarchical steps with active subsets: the records of the particles that
 // keep their kernel length and gradients and take part in a due pair (a flux
-// list), from their kept H, V, n, B and limited gradients with the current
-// position and predicted state, as the gradient kernel writes them.
+// list), from their kept H, V, n, B and limited gradients (B and grad at
+// column home[i]) with the current position and predicted state, as the
+// gradient kernel writes them.
 __global__ void k_pack_rec_kept(PassArrays a, Phys ph, const unsigned char* __restrict__ mode,
-                                const int* __restrict__ counts, double* __restrict__ recp) {
+                                const long long* __restrict__ home, const int* __restrict__ counts,
+                                double* __restrict__ recp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n || mode[i] == kModeSolve || counts[i] == 0) return;
     const long long n = a.n;
+    const long long h = home[i];
     const double Hi = a.H[i], Vi = a.V[i];
     const double rho_i = a.m[i] * a.nk[i];
     const double P_i = (ph.gamma - 1.0) * rho_i * a.u[i];
@@ -1205,9 +1210,9 @@ __global__ void k_pack_rec_kept(PassArrays a, Phys ph, const unsigned char* __re
     v[R_V0 + 1] = a.vy[i];
     v[R_V0 + 2] = a.vz[i];
 #pragma unroll
-    for (int k = 0; k < 6; k++) v[R_B + k] = a.B[k * n + i];
+    for (int k = 0; k < 6; k++) v[R_B + k] = a.B[k * n + h];
 #pragma unroll
-    for (int k = 0; k < 15; k++) v[R_G + k] = a.grad[k * n + i];
+    for (int k = 0; k < 15; k++) v[R_G + k] = a.grad[k * n + h];
     v[R_C] = sqrt(ph.gamma * P_i / rho_i);
     double2* r2 = (double2*)(recp + (long long)i * 32);
 #pragma unroll
@@ -1500,12 +1505,13 @@ struct Levels {
     const long long* bin;
     int lmin, nlev;
     double* lev;
+    const long long* home;   // column of lev per particle (null: the particle's index)
 };
 
 template <typename T, bool MFV, bool LIM, bool LEV = false>
 __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph, const int* __restrict__ counts,
                                             const int* __restrict__ list, const T* __restrict__ rec,
-                                            Counters* cnt, Levels lv = Levels{nullptr, 0, 0, nullptr}) {
+                                            Counters* cnt, Levels lv = Levels{nullptr, 0, 0, nullptr, nullptr}) {
     cnt = counter_copy(cnt);
     const int i = xcd_block() * 256 + threadIdx.x;
     const bool act = i < a.n;
@@ -1530,15 +1536,17 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
         const T gam = (T)ph.gamma;
         const int cnum = counts[i];
         int bi = 0;
+        long long li = i;
         double lacc[kLevWin][4];
         if (LEV) {
             bi = (int)lv.bin[i];
+            if (lv.home) li = lv.home[i];
 #pragma unroll
             for (int w = 0; w < kLevWin; w++)
 #pragma unroll
                 for (int c = 0; c < 4; c++) lacc[w][c] = 0.0;
             for (int l = max(lv.lmin, bi + kLevWin); l < lv.nlev; l++)
-                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = 0.0;
+                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + li] = 0.0;
         }
         // the next list entry is loaded one pair ahead, so the record loads of
         // a pair do not wait for its index
@@ -1600,7 +1608,7 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
 #pragma unroll
                         for (int c = 0; c < 4; c++) lacc[q][c] = (q == w) ? lacc[q][c] - s * F[c] : lacc[q][c];
                 } else {
-                    for (int c = 0; c < 4; c++) lv.lev[((long long)lj * 4 + c) * n + i] -= s * F[c];
+                    for (int c = 0; c < 4; c++) lv.lev[((long long)lj * 4 + c) * n + li] -= s * F[c];
                 }
             }
         }
@@ -1610,11 +1618,11 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
                 const int l = bi + w;
                 if (l >= lv.lmin && l < lv.nlev)
 #pragma unroll
-                    for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = lacc[w][c];
+                    for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + li] = lacc[w][c];
             }
             // due levels coarser than the particle's own bin hold no pair of it
             for (int l = lv.lmin; l < min(bi, lv.nlev); l++)
-                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + i] = 0.0;
+                for (int c = 0; c < 4; c++) lv.lev[((long long)l * 4 + c) * n + li] = 0.0;
         }
         a.dp[i] = acc[0];
         a.dp[n + i] = acc[1];
@@ -1707,10 +1715,10 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
     if (t0) hipEventRecord(t0, s);
     if (mixed)
         k_gradients<true, false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec,
-                                                                     cnt, nullptr);
+                                                                     cnt, nullptr, nullptr);
     else
         k_gradients<false, false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec,
-                                                                      cnt, nullptr);
+                                                                      cnt, nullptr, nullptr);
     if (t1) hipEventRecord(t1, s);
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
@@ -1730,13 +1738,13 @@ void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* 
     k_gather_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, mode, list, gcount, counts);
 }
 
-void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const int* gcount,
-                             int* counts, int* list, int* tails, double4* prim, void* rec, Counters* cnt,
-                             hipStream_t s) {
+void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const long long* home,
+                             const int* gcount, int* counts, int* list, int* tails, double4* prim, void* rec,
+                             Counters* cnt, hipStream_t s) {
     k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, mode, prim);
     k_gradients<false, true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt,
-                                                                 mode);
-    k_pack_rec_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, mode, counts, (double*)rec);
+                                                                 mode, home);
+    k_pack_rec_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, mode, home, counts, (double*)rec);
     k_sort_tails<<<blocks_of(a.n, 256), 256, 0, s>>>(a.n, ph.max_ngb, gcount, counts, list, tails, cnt);
 }
 
@@ -1754,8 +1762,9 @@ static void launch_fluxes_lim(const PassArrays& a, const Phys& ph, const int* co
 }
 
 void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts, const int* list, const void* rec,
-                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev, hipStream_t s) {
-    const Levels lv{bin, lmin, nlev, lev};
+                          Counters* cnt, const long long* bin, int lmin, int nlev, double* lev,
+                          const long long* home, hipStream_t s) {
+    const Levels lv{bin, lmin, nlev, lev, home};
     if (ph.limiter)
         k_fluxes_levels<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, counts, list, (const double*)rec, cnt, lv);
     else

@@ -177,21 +177,23 @@ __global__ void k_hier_begin(int n, const double* __restrict__ m, double* __rest
     E[i] = e;
 }
 
-// half kicks of the levels lmin .. nlev-1, `times` times over (a closing and an opening kick)
+// half kicks of the levels lmin .. nlev-1, `times` times over (a closing and an
+// opening kick); particle i's rates sit at column home[i] of lev
 __global__ void k_hier_kick(int n, const double* __restrict__ m, double* __restrict__ vx, double* __restrict__ vy,
-                            double* __restrict__ vz, double* __restrict__ E, const double* __restrict__ lev, int lmin,
-                            int nlev, double T, int times) {
+                            double* __restrict__ vz, double* __restrict__ E, const double* __restrict__ lev,
+                            const long long* __restrict__ home, int lmin, int nlev, double T, int times) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long nn = n;
+    const long long h = home[i];
     const double mi = m[i];
     double v[3] = {vx[i], vy[i], vz[i]};
     double e = E[i];
     for (int t = 0; t < times; t++)
         for (int l = lmin; l < nlev; l++) {
             const double dt = T / (double)(1ll << l);
-            for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + i] / mi;
-            e = e + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + i];
+            for (int c = 0; c < 3; c++) v[c] = v[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + h] / mi;
+            e = e + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + h];
         }
     vx[i] = v[0];
     vy[i] = v[1];
@@ -219,18 +221,20 @@ __global__ void k_hier_drift(PassArrays a, Phys ph, double dt) {
 // predicted velocity and u for the pass: the due levels' kicks with their previous rates
 __global__ void k_hier_predict(int n, const double* __restrict__ m, const double* __restrict__ vx,
                                const double* __restrict__ vy, const double* __restrict__ vz,
-                               const double* __restrict__ E, const double* __restrict__ lev, int lmin, int nlev,
-                               double T, double u_floor, double* __restrict__ vp, double* __restrict__ up) {
+                               const double* __restrict__ E, const double* __restrict__ lev,
+                               const long long* __restrict__ home, int lmin, int nlev, double T, double u_floor,
+                               double* __restrict__ vp, double* __restrict__ up) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long nn = n;
+    const long long h = home[i];
     const double mi = m[i];
     double q[3] = {vx[i], vy[i], vz[i]};
     double Ep = E[i];
     for (int l = lmin; l < nlev; l++) {
         const double dt = T / (double)(1ll << l);
-        for (int c = 0; c < 3; c++) q[c] = q[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + i] / mi;
-        Ep = Ep + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + i];
+        for (int c = 0; c < 3; c++) q[c] = q[c] + 0.5 * dt * lev[((long long)l * 4 + c) * nn + h] / mi;
+        Ep = Ep + 0.5 * dt * lev[((long long)l * 4 + 3) * nn + h];
     }
     double uu = Ep / mi - 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
     uu = fmax(uu, u_floor);
@@ -323,18 +327,26 @@ void launch_hier_begin(int n, const double* m, double* vx, double* vy, double* v
 }
 
 void launch_hier_kick(int n, const double* m, double* vx, double* vy, double* vz, double* E, const double* lev,
-                      int lmin, int nlev, double T, int times, hipStream_t s) {
-    k_hier_kick<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, lmin, nlev, T, times);
+                      const long long* home, int lmin, int nlev, double T, int times, hipStream_t s) {
+    k_hier_kick<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, home, lmin, nlev, T, times);
 }
+
+__global__ void k_iota(int n, long long* __restrict__ v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+void launch_iota(int n, long long* v, hipStream_t s) { k_iota<<<(n + 255) / 256, 256, 0, s>>>(n, v); }
 
 void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s) {
     k_hier_drift<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt);
 }
 
 void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
-                         const double* E, const double* lev, int lmin, int nlev, double T, double u_floor,
-                         double* vp, double* up, hipStream_t s) {
-    k_hier_predict<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, lmin, nlev, T, u_floor, vp, up);
+                         const double* E, const double* lev, const long long* home, int lmin, int nlev, double T,
+                         double u_floor, double* vp, double* up, hipStream_t s) {
+    k_hier_predict<<<(n + 255) / 256, 256, 0, s>>>(n, m, vx, vy, vz, E, lev, home, lmin, nlev, T, u_floor, vp,
+                                                   up);
 }
 
 // ------------------------------------------- active subsets of hierarchical steps
