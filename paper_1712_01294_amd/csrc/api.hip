@@ -963,6 +963,21 @@ static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* 
     return do_fluxes_levels(c, q, bins, lmin, nlev, c->hhome, s);
 }
 
+// Whether the last gradient pass on the context ran on these particles as they
+// stand (same order, positions and kernel lengths, bit for bit, checked on the
+// device against its packed neighbour records): then the kernel lengths,
+// densities, volumes and gather lists of that pass hold for them.  Synchronises
+// the stream.
+static bool unmoved_since_last_pass(mfm_ctx* c, const mfm_particles* p, hipStream_t s) {
+    if (!c->have_grad || c->n_tree != p->n || !p->H) return false;
+    launch_fill_u64(1, c->fb_count, 0ull, s);
+    launch_same_positions((int)p->n, p->x, p->y, p->z, p->H, c->prim, c->fb_count, s);
+    unsigned long long diff = 1;
+    if (hipMemcpyAsync(&diff, c->fb_count, sizeof diff, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    return diff == 0;
+}
+
 extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins, int32_t max_bin, double T,
                                     int32_t flags, void* stream) {
     mfm_status st = check_particles(c, p);
@@ -993,10 +1008,18 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
     long long* b = (long long*)bins;
     reset_counters(c, s);
     if (rebin || !c->have_levels || c->lev_nlev != nlev || c->n_tree != p->n) {
-        // the per-level rates of the current state, every level due
-        double* e1[1] = {(double*)b};
-        if ((st = build(c, p, s, e1, 1))) return st;
-        if ((st = do_solve_h(c, p, s))) return st;
+        // the per-level rates of the current state, every level due; when the
+        // particles have not moved since the last pass (as after a hierarchical
+        // step, whose last boundary passes over every particle), that pass's
+        // kernel lengths, densities, volumes and gather lists still hold, and
+        // only the gradients and the fluxes are evaluated again
+        if (unmoved_since_last_pass(c, p, s)) {
+            launch_reset_counts((int)n, c->gcount, c->counts, s);
+        } else {
+            double* e1[1] = {(double*)b};
+            if ((st = build(c, p, s, e1, 1))) return st;
+            if ((st = do_solve_h(c, p, s))) return st;
+        }
         if ((st = do_gradients(c, p, s))) return st;
         if ((st = do_fluxes_levels(c, p, b, 0, nlev, nullptr, s))) return st;
     } else if (!c->have_flux) {

@@ -107,6 +107,11 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
                          const double* E, const double* lev, const long long* home, int lmin, int nlev, double T,
                          double u_floor, double* vp, double* up, hipStream_t s);
 void launch_iota(int n, long long* v, hipStream_t s);
+// *diff |= 1 when some particle's (x, y, z, H) differs bit for bit from
+// prim[4 i] (the packed neighbour record of the last gradient pass)
+void launch_same_positions(int n, const double* x, const double* y, const double* z, const double* H,
+                           const double4* prim, unsigned long long* diff, hipStream_t s);
+void launch_reset_counts(int n, const int* gcount, int* counts, hipStream_t s);
 // the modes of one sub-step boundary: the cells (every level) of the due
 // particles are marked in marks (one bit per table entry, cleared here), and
 // a particle that is not due is kModeKept when the 3x3x3 cells around it, on

@@ -349,6 +349,40 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
                                                    up);
 }
 
+// Whether the particles still stand where the last gradient pass packed them:
+// *diff (zeroed by the caller) becomes nonzero when any position or kernel
+// length differs bit for bit from the packed neighbour record (x, y, z, H).
+__global__ void k_same_positions(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                 const double* __restrict__ z, const double* __restrict__ H,
+                                 const double4* __restrict__ prim, unsigned long long* __restrict__ diff) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool d = false;
+    if (i < n) {
+        const double4 q = prim[4 * (long long)i];
+        d = !(__double_as_longlong(q.x) == __double_as_longlong(x[i]) &&
+              __double_as_longlong(q.y) == __double_as_longlong(y[i]) &&
+              __double_as_longlong(q.z) == __double_as_longlong(z[i]) &&
+              __double_as_longlong(q.w) == __double_as_longlong(H[i]));
+    }
+    if (__ballot(d) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(diff, 1ull);
+}
+
+void launch_same_positions(int n, const double* x, const double* y, const double* z, const double* H,
+                           const double4* prim, unsigned long long* diff, hipStream_t s) {
+    k_same_positions<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, z, H, prim, diff);
+}
+
+// the flux lists back to their gather parts (counts = gcount), for a gradient
+// pass that appends the tails again over the lists of an earlier solve
+__global__ void k_reset_counts(int n, const int* __restrict__ gcount, int* __restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counts[i] = gcount[i];
+}
+
+void launch_reset_counts(int n, const int* gcount, int* counts, hipStream_t s) {
+    k_reset_counts<<<(n + 255) / 256, 256, 0, s>>>(n, gcount, counts);
+}
+
 // ------------------------------------------- active subsets of hierarchical steps
 // deposited key of the level-l cell holding x (per axis floor(x / side),
 // clamped to the level's cells): the index of that cell's table entry past

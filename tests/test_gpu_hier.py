@@ -346,3 +346,35 @@ def test_active_subsets_conserve_on_the_shock_tube():
     for k in ("vx", "vy", "vz"):
         assert np.abs(in_input_order(st, k) - ref.st[k]).max() <= 1e-10 * vmax, k
     assert nerr(in_input_order(st, "u"), ref.st["u"]) <= 1e-10
+
+
+def test_rebin_of_unmoved_particles_reuses_the_last_pass():
+    """A rebin right after a hierarchical step finds the particles where the
+    step's last boundary passed over them, keeps that pass's kernel lengths and
+    lists and runs only the gradients and fluxes.  After a rebuild of the
+    neighbour order (the same order: the particles are already sorted) the
+    rebin solves again.  Both give the same next step to 1e-12, and the reused
+    rebin runs fewer kernel-length iterations."""
+    import torch
+    w = _smooth(12, W.SEED_BASE + 176)
+    rng = np.random.default_rng(W.SEED_BASE + 177)
+    bins = rng.integers(0, 3, size=w.n).astype(np.int64)
+    T = 0.004
+    runs = []
+    for rebuild in (False, True):
+        ctx, st = _gpu(w)
+        b = torch.as_tensor(bins[st.id.cpu().numpy()], device="cuda")
+        ctx.step_hier(st, b, 2, T, rebin=True, active=True)
+        if rebuild:
+            ids = st.id.clone()
+            ctx.build_neighbours(st)
+            assert torch.equal(ids, st.id)
+        ctx.step_hier(st, b, 2, T, rebin=True, active=True)
+        ctx.check()
+        runs.append((st, ctx.counters()["h_iters"]))
+    (s1, it1), (s2, it2) = runs
+    assert torch.equal(s1.id, s2.id)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "dp", "dE"):
+        a, c = getattr(s1, k), getattr(s2, k)
+        assert float((a - c).abs().max() / c.abs().max()) <= 1e-12, k
+    assert it1 < it2, (it1, it2)
