@@ -241,12 +241,14 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * particle; with MFM_HIER_ACTIVE also one byte per particle and one bit per
  * cell-table entry); they are computed by a pass over the current state with
  * every level due when flags has MFM_HIER_REBIN, on the first call, when
- * max_bin changes, or after any other pass on the context.  That pass
- * synchronises the stream once: when the particles stand bit for bit where
- * the last pass on the context left them (order, positions and H, as after a
- * hierarchical step, or after mfm_hydro_pass with nothing moved since), it
- * keeps that pass's kernel lengths, nk, V and gather lists and evaluates only
- * the gradients and the fluxes.  With max_bin = 0
+ * max_bin changes, or after any other pass on the context.  When the
+ * particles stand bit for bit where the last pass on the context left them
+ * (order, positions and H, as after a hierarchical step, or after
+ * mfm_hydro_pass with nothing moved since), that pass keeps the last pass's
+ * kernel lengths, nk, V and gather lists and evaluates only the gradients and
+ * the fluxes.  The call synchronises the stream once, at its start, to check
+ * on the device that every bin lies in 0 .. max_bin (else MFM_E_INVALID,
+ * before anything runs) and whether the particles moved.  With max_bin = 0
  * the call performs mfm_step's operations for a fixed dt = T (in separate
  * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64
  * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE and vsig hold the

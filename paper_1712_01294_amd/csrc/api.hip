@@ -963,19 +963,29 @@ static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* 
     return do_fluxes_levels(c, q, bins, lmin, nlev, c->hhome, s);
 }
 
-// Whether the last gradient pass on the context ran on these particles as they
-// stand (same order, positions and kernel lengths, bit for bit, checked on the
-// device against its packed neighbour records): then the kernel lengths,
-// densities, volumes and gather lists of that pass hold for them.  Synchronises
-// the stream.
-static bool unmoved_since_last_pass(mfm_ctx* c, const mfm_particles* p, hipStream_t s) {
-    if (!c->have_grad || c->n_tree != p->n || !p->H) return false;
+// The one host synchronisation of a hierarchical step: whether every bin lies in
+// 0 .. max_bin and whether the last gradient pass on the context ran on these
+// particles as they stand (same order, positions and kernel lengths, bit for
+// bit, checked on the device against its packed neighbour records; then the
+// kernel lengths, densities, volumes and gather lists of that pass hold for
+// them).
+struct HierChecks {
+    bool bins_ok, unmoved;
+};
+static mfm_status hier_checks(mfm_ctx* c, const mfm_particles* p, const long long* bins, int max_bin,
+                              hipStream_t s, HierChecks* out) {
+    const bool can_reuse = c->have_grad && c->n_tree == p->n;
     launch_fill_u64(1, c->fb_count, 0ull, s);
-    launch_same_positions((int)p->n, p->x, p->y, p->z, p->H, c->prim, c->fb_count, s);
-    unsigned long long diff = 1;
-    if (hipMemcpyAsync(&diff, c->fb_count, sizeof diff, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
-    if (hipStreamSynchronize(s) != hipSuccess) return false;
-    return diff == 0;
+    launch_check_bins((int)p->n, bins, max_bin, c->fb_count, s);
+    if (can_reuse) launch_same_positions((int)p->n, p->x, p->y, p->z, p->H, c->prim, c->fb_count, s);
+    unsigned long long flags = 0;
+    mfm_status st = hip_check(c, hipMemcpyAsync(&flags, c->fb_count, sizeof flags, hipMemcpyDeviceToHost, s),
+                              "hierarchical step checks");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "hierarchical step checks");
+    if (st) return st;
+    out->bins_ok = !(flags & 1ull);
+    out->unmoved = can_reuse && !(flags & 2ull);
+    return MFM_OK;
 }
 
 extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins, int32_t max_bin, double T,
@@ -1006,6 +1016,9 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         return st;
     const int nlev = max_bin + 1;
     long long* b = (long long*)bins;
+    HierChecks chk;
+    if ((st = hier_checks(c, p, b, max_bin, s, &chk))) return st;
+    if (!chk.bins_ok) return fail(c, MFM_E_INVALID, "bins outside 0 .. max_bin");
     reset_counters(c, s);
     if (rebin || !c->have_levels || c->lev_nlev != nlev || c->n_tree != p->n) {
         // the per-level rates of the current state, every level due; when the
@@ -1013,7 +1026,7 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         // step, whose last boundary passes over every particle), that pass's
         // kernel lengths, densities, volumes and gather lists still hold, and
         // only the gradients and the fluxes are evaluated again
-        if (unmoved_since_last_pass(c, p, s)) {
+        if (chk.unmoved) {
             launch_reset_counts((int)n, c->gcount, c->counts, s);
         } else {
             double* e1[1] = {(double*)b};

@@ -107,7 +107,9 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
                          const double* E, const double* lev, const long long* home, int lmin, int nlev, double T,
                          double u_floor, double* vp, double* up, hipStream_t s);
 void launch_iota(int n, long long* v, hipStream_t s);
-// *diff |= 1 when some particle's (x, y, z, H) differs bit for bit from
+// *bad |= 1 when some bin lies outside 0 .. max_bin
+void launch_check_bins(int n, const long long* bins, int max_bin, unsigned long long* bad, hipStream_t s);
+// *diff |= 2 when some particle's (x, y, z, H) differs bit for bit from
 // prim[4 i] (the packed neighbour record of the last gradient pass)
 void launch_same_positions(int n, const double* x, const double* y, const double* z, const double* H,
                            const double4* prim, unsigned long long* diff, hipStream_t s);

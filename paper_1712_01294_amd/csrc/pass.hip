@@ -1558,9 +1558,10 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             if (LEV) {
                 // a pair that is not due costs its bin alone: no record, no flux,
                 // no signal speed (the last boundary of a system step has every
-                // pair due, so the signal speeds it leaves are complete)
+                // pair due, so the signal speeds it leaves are complete); with
+                // every level due the record load does not wait for the bin
                 lj = max(bi, (int)lv.bin[j]);
-                if (lj < lv.lmin) continue;
+                if (lv.lmin > 0 && lj < lv.lmin) continue;
             }
             T rj[32];
             load_rec<T>(rec, j, rj);
@@ -1602,9 +1603,12 @@ __device__ __forceinline__ void fluxes_body(const PassArrays& a, const Phys& ph,
             if (LEV) {
                 const double F[4] = {(double)o.Fp[0], (double)o.Fp[1], (double)o.Fp[2], (double)o.FE};
                 const int w = lj - bi;
-                if (w < kLevWin) {
+                if (w == 0) {   // both particles in one bin: most pairs
 #pragma unroll
-                    for (int q = 0; q < kLevWin; q++)
+                    for (int c = 0; c < 4; c++) lacc[0][c] = lacc[0][c] - s * F[c];
+                } else if (w < kLevWin) {
+#pragma unroll
+                    for (int q = 1; q < kLevWin; q++)
 #pragma unroll
                         for (int c = 0; c < 4; c++) lacc[q][c] = (q == w) ? lacc[q][c] - s * F[c] : lacc[q][c];
                 } else {

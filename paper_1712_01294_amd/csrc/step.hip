@@ -350,8 +350,8 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
 }
 
 // Whether the particles still stand where the last gradient pass packed them:
-// *diff (zeroed by the caller) becomes nonzero when any position or kernel
-// length differs bit for bit from the packed neighbour record (x, y, z, H).
+// *diff (zeroed by the caller) takes bit 1 when any position or kernel length
+// differs bit for bit from the packed neighbour record (x, y, z, H).
 __global__ void k_same_positions(int n, const double* __restrict__ x, const double* __restrict__ y,
                                  const double* __restrict__ z, const double* __restrict__ H,
                                  const double4* __restrict__ prim, unsigned long long* __restrict__ diff) {
@@ -364,12 +364,24 @@ __global__ void k_same_positions(int n, const double* __restrict__ x, const doub
               __double_as_longlong(q.z) == __double_as_longlong(z[i]) &&
               __double_as_longlong(q.w) == __double_as_longlong(H[i]));
     }
-    if (__ballot(d) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(diff, 1ull);
+    if (__ballot(d) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(diff, 2ull);
 }
 
 void launch_same_positions(int n, const double* x, const double* y, const double* z, const double* H,
                            const double4* prim, unsigned long long* diff, hipStream_t s) {
     k_same_positions<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, z, H, prim, diff);
+}
+
+// *bad |= 1 when some bin lies outside 0 .. max_bin
+__global__ void k_check_bins(int n, const long long* __restrict__ bins, int max_bin,
+                             unsigned long long* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool b = i < n && (bins[i] < 0 || bins[i] > max_bin);
+    if (__ballot(b) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(bad, 1ull);
+}
+
+void launch_check_bins(int n, const long long* bins, int max_bin, unsigned long long* bad, hipStream_t s) {
+    k_check_bins<<<(n + 255) / 256, 256, 0, s>>>(n, bins, max_bin, bad);
 }
 
 // the flux lists back to their gather parts (counts = gcount), for a gradient

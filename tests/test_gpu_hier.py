@@ -187,6 +187,18 @@ def test_hierarchical_step_argument_checks():
     with pytest.raises(mfm.MFMError) as e:
         cm.step_hier(sm, b, 1, 1e-3)
     assert e.value.status == -1
+    # bins outside 0 .. max_bin are refused on the device before anything runs
+    x0 = st.x.clone()
+    for v in (3, -1):
+        bad = b.clone()
+        bad[w.n // 2] = v
+        for active in (False, True):
+            with pytest.raises(mfm.MFMError) as e:
+                ctx.step_hier(st, bad, 2, 1e-3, rebin=True, active=active)
+            assert e.value.status == -1 and "bins" in str(e.value)
+    assert torch.equal(st.x, x0)
+    ctx.step_hier(st, b, 2, 1e-3, rebin=True)
+    ctx.check()
 
 
 # ---------------------------------------------------------------- R26
