@@ -361,8 +361,10 @@ def run_precision(mfm, w, prec, kw, args, stream, scheme=0):
 
 def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
     """Hierarchical power-of-two steps on the same set.  Each particle's bin
-    comes from its Courant step dt_i = cfl H_i / vsig_i of an initial pass
-    (the step the library takes when dt <= 0): with dt_min the smallest,
+    comes from its step of an initial pass, the smaller of the Courant step
+    cfl H_i / vsig_i (the step the library takes when dt <= 0) and the step in
+    which its acceleration a_i = dp_i / m_i alone moves it by cfl H_i,
+    sqrt(2 cfl H_i / |a_i|): with dt_min the smallest,
     bin_i = max_bin - floor(log2(dt_i / dt_min)), clamped to [0, max_bin], so
     it steps by T / 2^bin_i <= dt_i within the system step T = 2^max_bin dt_min.
     One system step (2^max_bin sub-steps, each pass evaluating only the due
@@ -377,10 +379,11 @@ def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
     st = mfm.State.from_arrays(w.arrays())
     ctx.build_neighbours(st)
     ctx.hydro_pass(st)
-    dti = cfg.cfl * (st.H / st.vsig).double()
+    acc = torch.sqrt((st.dp * st.dp).sum(0)) / st.m
+    dti = torch.minimum(cfg.cfl * st.H / st.vsig, torch.sqrt(2.0 * cfg.cfl * st.H / acc)).double()
     dtmin = float(dti.min())
     if not (dtmin > 0.0 and np.isfinite(dtmin)):
-        raise RuntimeError(f"hierarchical leg: no finite Courant step (min {dtmin})")
+        raise RuntimeError(f"hierarchical leg: no finite step (min {dtmin})")
     bins = (max_bin - torch.floor(torch.log2(dti / dtmin))).clamp(0, max_bin).to(torch.int64).contiguous()
     T = dtmin * (1 << max_bin)
     hist = torch.bincount(bins, minlength=max_bin + 1).tolist()
@@ -422,7 +425,7 @@ def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
             "ms_per_system_step_active": act, "ms_per_system_step": hier, "global_ms": glob,
             "speedup_vs_global_active": glob / act, "speedup_vs_global": glob / hier,
             "note": "wall clock of one system step (the levelled pass of every level at its start included) "
-                    "against the global steps of the smallest Courant step over the same time; with active "
+                    "against the global steps of the smallest step over the same time; with active "
                     "subsets a sub-step recomputes kernel lengths and gradients of the due bins' particles "
                     "only, without them of every particle; either way the flux kernel skips the pairs not due"}
 

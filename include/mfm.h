@@ -246,9 +246,13 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * (order, positions and H, as after a hierarchical step, or after
  * mfm_hydro_pass with nothing moved since), that pass keeps the last pass's
  * kernel lengths, nk, V and gather lists and evaluates only the gradients and
- * the fluxes.  The call synchronises the stream once, at its start, to check
+ * the fluxes.  The call synchronises the stream once at its start, to check
  * on the device that every bin lies in 0 .. max_bin (else MFM_E_INVALID,
- * before anything runs) and whether the particles moved.  With max_bin = 0
+ * before anything runs) and whether the particles moved; with
+ * MFM_HIER_ACTIVE also once per boundary that not every level is due, where
+ * it keeps the cell tables of the last build while no particle has travelled
+ * a quarter of the finest cell since (positions may then stand just outside
+ * a periodic box until the next build wraps them).  With max_bin = 0
  * the call performs mfm_step's operations for a fixed dt = T (in separate
  * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64
  * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE and vsig hold the

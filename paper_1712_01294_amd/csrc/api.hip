@@ -52,6 +52,7 @@ struct mfm_ctx {
     unsigned char* hmode = nullptr;       // per-particle modes of active-subset sub-steps, on first use
     unsigned* hmarks = nullptr;           // one bit per cell-table entry: cells holding a due particle
     long long* hhome = nullptr;           // per particle: its column of the rates within a system step
+    double* hmoved = nullptr;             // path length since the last build, per particle, and its largest
     int64_t n_tree = -1;
     int have_h = 0, have_grad = 0, have_flux = 0, rec_mixed = 0;
     hipStream_t last = nullptr;
@@ -240,7 +241,7 @@ void mfm_destroy(mfm_ctx* c) {
     }
     void* bufs[] = {c->keys, c->ktmp, c->idx, c->vtmp, c->hist, c->scan_tmp, c->gtmp, c->tab, c->pos, c->rl,
                     c->counts, c->gcount, c->list, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, c->tails, c->rec, c->prim, c->vp, c->up, c->Ehalf, c->mp, c->dt_part, c->dt_out, c->cnt, c->adj, c->lev,
-                    c->hmode, c->hmarks, c->hhome};
+                    c->hmode, c->hmarks, c->hhome, c->hmoved};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete c;
@@ -944,6 +945,10 @@ static mfm_status do_fluxes_levels(mfm_ctx* c, mfm_particles* p, const long long
     return launched(c, "hydro_fluxes (levels)");
 }
 
+// Largest path length since the last build, in finest cells, up to which a
+// partial boundary of a hierarchical step keeps the cell tables.
+constexpr double kSkinCells = 0.25;
+
 // A sub-step boundary's pass with active subsets (reading R26): kernel
 // lengths and gradients of the due particles only, the others keeping theirs.
 static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* bins, int lmin, int nlev,
@@ -952,8 +957,8 @@ static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* 
     PassArrays a = arrays_of(q);
     launch_hier_modes((int)n, q->x, q->y, q->z, q->H, bins, lmin, c->td, c->tab_len, c->hmarks, c->hmode,
                       c->gcount, c->counts, s);
-    launch_solve_h_active(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->hmode, c->rl, c->list, c->gcount, c->counts,
-                          c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, s);
+    launch_solve_h_active(a, c->td, c->tab, c->pos, c->ph, c->cnt, c->hmode, c->hmoved + n, c->rl, c->list,
+                          c->gcount, c->counts, c->fb_list, c->fb_count, c->fb2_list, c->fb2_count, s);
     launch_gradients_active(a, c->ph, c->hmode, c->hhome, c->gcount, c->counts, c->list, c->tails, c->prim, c->rec,
                             c->cnt, s);
     c->have_h = c->have_grad = 1;
@@ -1011,6 +1016,8 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         if ((st = hip_check(c, hipMalloc((void**)&c->hmode, c->cap), "sub-step modes"))) return st;
         if ((st = hip_check(c, hipMalloc((void**)&c->hmarks, 8 * ((c->tab_len + 63) / 64)), "cell marks")))
             return st;
+        if ((st = hip_check(c, hipMalloc((void**)&c->hmoved, sizeof(double) * (c->cap + 1)), "moved distances")))
+            return st;
     }
     if (!c->hhome && (st = hip_check(c, hipMalloc((void**)&c->hhome, sizeof(long long) * c->cap), "home columns")))
         return st;
@@ -1047,15 +1054,46 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
     // particle state, E, the bins and home (with active subsets also the kept n
     // and V), but not the pass outputs and u, which are written anew, nor the
     // predicted state, which is predicted after the reorder.
+    //
+    // With active subsets a boundary with lmin > 0 keeps the cell tables and
+    // the particle order of the last build, as long as no particle has moved
+    // more than kSkinCells of the finest cell since (one synchronised read per
+    // such boundary): the particles drift without being wrapped into the box,
+    // their packed positions are refreshed, and every scan reaches further by
+    // the largest path length since that build (moved[n]).  The boundaries with
+    // every level due build anew.
     launch_iota((int)n, c->hhome, s);
+    if (active) launch_fill_u64(n + 1, (unsigned long long*)c->hmoved, 0ull, s);
     mfm_particles pb = *p;
     pb.dp = pb.dE = pb.vsig = pb.u = pb.dm = nullptr;
     for (int k = 1; k <= K; k++) {
-        launch_hier_drift(arrays_of(p), c->ph, delta, s);
         const int tz = __builtin_ctz((unsigned)k);
         const int lmin = max_bin - tz > 0 ? max_bin - tz : 0;
-        double* extra[5] = {c->Ehalf, (double*)b, (double*)c->hhome, p->nk, p->V};
-        if ((st = build(c, &pb, s, extra, active ? 5 : 3))) return st;
+        bool rebuild = !(active && lmin > 0);
+        launch_hier_drift(arrays_of(p), c->ph, delta, rebuild ? 1 : 0, rebuild ? nullptr : c->hmoved, s);
+        if (!rebuild) {
+            // keep the tables while no particle has moved a quarter of the finest
+            // cell since the build (the scans reach that much further); else
+            // wrap the positions and build anew
+            double moved = 0.0;
+            if ((st = hip_check(c, hipMemcpyAsync(&moved, c->hmoved + n, sizeof moved, hipMemcpyDeviceToHost, s),
+                                "moved distance")))
+                return st;
+            if ((st = hip_check(c, hipStreamSynchronize(s), "moved distance"))) return st;
+            const double finest = std::min(c->td.cs[c->td.bmax][0], std::min(c->td.cs[c->td.bmax][1],
+                                                                               c->td.cs[c->td.bmax][2]));
+            if (!(moved <= kSkinCells * finest)) {
+                rebuild = true;
+                launch_hier_drift(arrays_of(p), c->ph, 0.0, 1, nullptr, s);   // wraps only
+            }
+        }
+        if (rebuild) {
+            double* extra[5] = {c->Ehalf, (double*)b, (double*)c->hhome, p->nk, p->V};
+            if ((st = build(c, &pb, s, extra, active ? 5 : 3))) return st;
+            if (active) launch_fill_u64(n + 1, (unsigned long long*)c->hmoved, 0ull, s);
+        } else {
+            launch_pos4((int)n, p->x, p->y, p->z, c->pos, s);
+        }
         launch_hier_predict((int)n, p->m, p->vx, p->vy, p->vz, c->Ehalf, c->lev, c->hhome, lmin, nlev, T,
                             c->p.u_floor, c->vp, c->up, s);
         // the last boundary rewrites every level, in the current order

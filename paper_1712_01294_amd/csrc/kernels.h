@@ -70,10 +70,12 @@ void launch_fluxes_levels(const PassArrays& a, const Phys& ph, const int* counts
 // otherwise (no gather list; it enters only the lists of active particles
 // that reach it)
 constexpr unsigned char kModeNone = 0, kModeSolve = 1, kModeKept = 2;
+// (the cell tables may be those of an earlier build, with particles moved by
+// at most *pad since: every scan reaches that much further)
 void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* tab, const double4* pos,
-                           const Phys& ph, Counters* cnt, const unsigned char* mode, double* rl, int* list,
-                           int* gcount, int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
-                           unsigned long long* fb2_count, hipStream_t s);
+                           const Phys& ph, Counters* cnt, const unsigned char* mode, const double* pad, double* rl,
+                           int* list, int* gcount, int* counts, int* fb_list, unsigned long long* fb_count,
+                           int* fb2_list, unsigned long long* fb2_count, hipStream_t s);
 // (the new gradient matrices and limited gradients of the active particles, and
 // the kept ones read for the records, at column home[i] of B and grad)
 void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const long long* home,
@@ -102,7 +104,10 @@ void launch_hier_begin(int n, const double* m, double* vx, double* vy, double* v
                        const double* lev, int nlev, double T, hipStream_t s);
 void launch_hier_kick(int n, const double* m, double* vx, double* vy, double* vz, double* E, const double* lev,
                       const long long* home, int lmin, int nlev, double T, int times, hipStream_t s);
-void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s);
+// drift: with wrap the positions are wrapped into the box; with moved (n + 1
+// doubles) each particle's path length since the last build accumulates in
+// moved[i] and their largest in moved[n] (positive doubles ordered as integers)
+void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, int wrap, double* moved, hipStream_t s);
 void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
                          const double* E, const double* lev, const long long* home, int lmin, int nlev, double T,
                          double u_floor, double* vp, double* up, hipStream_t s);

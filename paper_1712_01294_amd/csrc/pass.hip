@@ -229,7 +229,9 @@ constexpr double kClassWindow = 2.0;
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
 // outweighs the few loop-invariant values this budget spills to scratch.
 // With HIER (hierarchical steps with active subsets) only the particles of
-// mode 1 solve; the others keep their kernel length.
+// mode 1 solve; the others keep their kernel length.  The cell tables may then
+// be those of an earlier build: every scan reaches *pad further, the largest
+// distance a particle has moved since.
 constexpr int kSolveWaves = 5;
 template <bool HIER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSolveWaves))) void k_solve_h(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSolveWaves
                                                   double* __restrict__ rl, int* __restrict__ jl,
                                                   int* __restrict__ gcount, int* __restrict__ counts,
                                                   int* __restrict__ fb_list, unsigned long long* __restrict__ fb_count,
-                                                  const unsigned char* __restrict__ mode) {
+                                                  const unsigned char* __restrict__ mode, const double* __restrict__ pad) {
     cnt = counter_copy(cnt);
     __shared__ ScanLds lds[256 / kWave];
     ScanLds& S = lds[threadIdx.x / kWave];
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSolveWaves
             rounds++;
             m = 0;
         }
-        group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, R2, cls, [&](int j, double r2) {
+        group_scan(td, tab, pos, S, lane, bmin, bmax, HIER ? Rq + *pad : Rq, xi, R2, cls, [&](int j, double r2) {
             const double r = sqrt(r2);
             if (r < Sl) {
                 if (m < cap) {
@@ -439,11 +441,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveSolveWa
                                                       const double* __restrict__ hand, int* __restrict__ jl,
                                                       int* __restrict__ gcount, int* __restrict__ counts,
                                                       int* __restrict__ fb2_list,
-                                                      unsigned long long* __restrict__ fb2_count) {
+                                                      unsigned long long* __restrict__ fb2_count,
+                                                      const double* __restrict__ pad) {
     cnt = counter_copy(cnt);
     __shared__ ScanLds S;
     const int lane = threadIdx.x;
     const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
+    const double pd = pad ? *pad : 0.0;
     if (blockIdx.x == 0 && lane == 0) cnt->h_fallback = *fb_count;
     const long long n = a.n;
     constexpr int kKeep = kWaveSlots * kWave;
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveSolveWa
             m = 0;
             ra = rb = rc = INFINITY;
             ja = jb = jc = -1;
-            scan_cells(td, tab, pos, S, lane, xi, xi, R, [&](const double4& q, bool valid, int, int wrap) {
+            scan_cells(td, tab, pos, S, lane, xi, xi, R + pd, [&](const double4& q, bool valid, int, int wrap) {
                 const double r2 = sq_disp(q, xi, wrap, td.box);
                 const bool in = valid && r2 < R2;
                 const double r = sqrt(r2);
@@ -615,10 +619,11 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
                                                           const int* __restrict__ fb_list,
                                                           const unsigned long long* __restrict__ fb_count,
                                                           int* __restrict__ jl, int* __restrict__ gcount,
-                                                          int* __restrict__ counts) {
+                                                          int* __restrict__ counts, const double* __restrict__ pad) {
     cnt = counter_copy(cnt);
     __shared__ ScanLds S;
     const int lane = threadIdx.x;
+    const double pd = pad ? *pad : 0.0;
     const unsigned long long nfb = min(*fb_count, (unsigned long long)a.n);
     if (blockIdx.x == 0 && lane == 0) cnt->h_rescan = *fb_count;
     const long long n = a.n;
@@ -636,7 +641,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
         auto eval = [&](double H, double& f, double& fp, double& nk) {
             const double H2 = H * H, iH = 1.0 / H;
             double s = 0.0, sq = 0.0;
-            scan_cells(td, tab, pos, S, lane, xi, xi, H, [&](const double4& q, bool valid, int, int wrap) {
+            scan_cells(td, tab, pos, S, lane, xi, xi, H + pd, [&](const double4& q, bool valid, int, int wrap) {
                 const double r2 = sq_disp(q, xi, wrap, td.box);
                 if (valid && r2 < H2) {
                     const double qq = sqrt(r2) * iH;
@@ -685,7 +690,7 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
             const double H2 = Hc * Hc;
             const int cap = ph.max_ngb;
             // every gather neighbour but the particle itself, in scan order
-            scan_cells(td, tab, pos, S, lane, xi, xi, Hc, [&](const double4& q, bool valid, int, int wrap) {
+            scan_cells(td, tab, pos, S, lane, xi, xi, Hc + pd, [&](const double4& q, bool valid, int, int wrap) {
                 const double r2 = sq_disp(q, xi, wrap, td.box);
                 const int j = (int)__double_as_longlong(q.w);
                 const bool in = valid && r2 < H2 && j != i && sqrt(r2) < Hc;
@@ -731,8 +736,9 @@ __global__ __launch_bounds__(64) void k_solve_h_fallback(PassArrays a, TreeDesc 
 // over the largest of their radii.
 __global__ __launch_bounds__(256) void k_gather_kept(PassArrays a, TreeDesc td, const int2* __restrict__ tab,
                                                      const double4* __restrict__ pos, Phys ph,
-                                                     const unsigned char* __restrict__ mode, int* __restrict__ jl,
-                                                     int* __restrict__ gcount, int* __restrict__ counts) {
+                                                     const unsigned char* __restrict__ mode, const double* __restrict__ pad,
+                                                     int* __restrict__ jl, int* __restrict__ gcount,
+                                                     int* __restrict__ counts) {
     __shared__ ScanLds lds[256 / kWave];
     ScanLds& S = lds[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -759,7 +765,7 @@ __global__ __launch_bounds__(256) void k_gather_kept(PassArrays a, TreeDesc td, 
     }
     const int cap = ph.max_ngb;
     int c = 0;
-    group_scan(td, tab, pos, S, lane, bmin, bmax, Rq, xi, Rs * Rs, sel, [&](int j, double r2) {
+    group_scan(td, tab, pos, S, lane, bmin, bmax, Rq + *pad, xi, Rs * Rs, sel, [&](int j, double r2) {
         const double r = sqrt(r2);
         if (r < H && j != i) {
             if (c < cap) jl[(long long)c * n + i] = j;
@@ -1703,12 +1709,12 @@ void launch_solve_h(const PassArrays& a, const TreeDesc& td, const int2* tab,
     launch_fill_u64(1, fb2_count, 0ull, s);
     if (t0) hipEventRecord(t0, s);
     k_solve_h<false><<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
-                                                         fb_list, fb_count, nullptr);
+                                                         fb_list, fb_count, nullptr, nullptr);
     // one wave per handed-over particle, striding over the count left on the device
     k_solve_h_wave<<<kWaveBlocks, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, rl, list, gcount,
-                                              counts, fb2_list, fb2_count);
+                                              counts, fb2_list, fb2_count, nullptr);
     k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb2_list, fb2_count, list, gcount,
-                                                     counts);
+                                                     counts, nullptr);
     if (t1) hipEventRecord(t1, s);
 }
 
@@ -1728,18 +1734,18 @@ void launch_gradients(const PassArrays& a, const Phys& ph, const int* gcount, in
 }
 
 void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* tab, const double4* pos,
-                           const Phys& ph, Counters* cnt, const unsigned char* mode, double* rl, int* list,
-                           int* gcount, int* counts, int* fb_list, unsigned long long* fb_count, int* fb2_list,
-                           unsigned long long* fb2_count, hipStream_t s) {
+                           const Phys& ph, Counters* cnt, const unsigned char* mode, const double* pad, double* rl,
+                           int* list, int* gcount, int* counts, int* fb_list, unsigned long long* fb_count,
+                           int* fb2_list, unsigned long long* fb2_count, hipStream_t s) {
     launch_fill_u64(1, fb_count, 0ull, s);
     launch_fill_u64(1, fb2_count, 0ull, s);
     k_solve_h<true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, cnt, rl, list, gcount, counts,
-                                                        fb_list, fb_count, mode);
+                                                        fb_list, fb_count, mode, pad);
     k_solve_h_wave<<<kWaveBlocks, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb_list, fb_count, rl, list, gcount,
-                                              counts, fb2_list, fb2_count);
+                                              counts, fb2_list, fb2_count, pad);
     k_solve_h_fallback<<<kFallbackWaves, 64, 0, s>>>(a, td, tab, pos, ph, cnt, fb2_list, fb2_count, list, gcount,
-                                                     counts);
-    k_gather_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, mode, list, gcount, counts);
+                                                     counts, pad);
+    k_gather_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, td, tab, pos, ph, mode, pad, list, gcount, counts);
 }
 
 void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const long long* home,

@@ -201,20 +201,36 @@ __global__ void k_hier_kick(int n, const double* __restrict__ m, double* __restr
     E[i] = e;
 }
 
-// drift by dt with the current velocity, wrapped into the box
-__global__ void k_hier_drift(PassArrays a, Phys ph, double dt) {
+// drift by dt with the current velocity, wrapped into the box (with wrap);
+// with moved, the path length since the last build accumulates per particle
+// and its largest over the particles in moved[n]
+__global__ void k_hier_drift(PassArrays a, Phys ph, double dt, int wrap, double* __restrict__ moved) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const double v[3] = {a.vx[i], a.vy[i], a.vz[i]};
-    double* xs[3] = {(double*)a.x, (double*)a.y, (double*)a.z};
-    for (int c = 0; c < 3; c++) {
-        double xc = xs[c][i] + dt * v[c];
-        if (ph.periodic[c]) {
-            const double L = ph.box[c];
-            xc = xc - L * floor(xc / L);
-            if (xc >= L) xc = 0.0;
+    double path = 0.0;
+    if (i < a.n) {
+        const double v[3] = {a.vx[i], a.vy[i], a.vz[i]};
+        double* xs[3] = {(double*)a.x, (double*)a.y, (double*)a.z};
+        for (int c = 0; c < 3; c++) {
+            double xc = xs[c][i] + dt * v[c];
+            if (wrap && ph.periodic[c]) {
+                const double L = ph.box[c];
+                xc = xc - L * floor(xc / L);
+                if (xc >= L) xc = 0.0;
+            }
+            xs[c][i] = xc;
         }
-        xs[c][i] = xc;
+        if (moved) {
+            path = moved[i] + fabs(dt) * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            moved[i] = path;
+        }
+    }
+    if (moved) {
+        // one atomic per wave whose largest path exceeds the largest seen so far
+        // (a stale read only costs an atomic that changes nothing)
+        for (int o = 32; o > 0; o >>= 1) path = fmax(path, __shfl_xor(path, o, kWave));
+        unsigned long long* top = (unsigned long long*)(moved + a.n);
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(path);
+        if ((threadIdx.x & (kWave - 1)) == 0 && bits > *(volatile unsigned long long*)top) atomicMax(top, bits);
     }
 }
 
@@ -338,8 +354,8 @@ __global__ void k_iota(int n, long long* __restrict__ v) {
 
 void launch_iota(int n, long long* v, hipStream_t s) { k_iota<<<(n + 255) / 256, 256, 0, s>>>(n, v); }
 
-void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, hipStream_t s) {
-    k_hier_drift<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt);
+void launch_hier_drift(const PassArrays& a, const Phys& ph, double dt, int wrap, double* moved, hipStream_t s) {
+    k_hier_drift<<<(a.n + 255) / 256, 256, 0, s>>>(a, ph, dt, wrap, moved);
 }
 
 void launch_hier_predict(int n, const double* m, const double* vx, const double* vy, const double* vz,
@@ -396,9 +412,23 @@ void launch_reset_counts(int n, const int* gcount, int* counts, hipStream_t s) {
 }
 
 // ------------------------------------------- active subsets of hierarchical steps
-// deposited key of the level-l cell holding x (per axis floor(x / side),
-// clamped to the level's cells): the index of that cell's table entry past
-// the level's offset
+// x wrapped into the box on periodic axes (positions between builds of a
+// hierarchical step may stand just outside it)
+__device__ __forceinline__ void wrap_box(const TreeDesc& td, const double x[3], double w[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        double v = x[d];
+        if (td.periodic[d]) {
+            v = v - td.box[d] * floor(v / td.box[d]);
+            if (v >= td.box[d]) v = 0.0;
+        }
+        w[d] = v;
+    }
+}
+
+// deposited key of the level-l cell holding x (x wrapped on periodic axes, per
+// axis floor(x / side), clamped to the level's cells): the index of that
+// cell's table entry past the level's offset
 __device__ __forceinline__ unsigned long long cell_key(const TreeDesc& td, int l, const double x[3]) {
     unsigned long long key = 0;
 #pragma unroll
@@ -421,9 +451,8 @@ __global__ void k_hier_mark(int n, const double* __restrict__ x, const double* _
     if (__ballot(act) == 0) return;   // uniform over the wave
     double xi[3] = {0.0, 0.0, 0.0};
     if (act) {
-        xi[0] = x[i];
-        xi[1] = y[i];
-        xi[2] = z[i];
+        const double xr[3] = {x[i], y[i], z[i]};
+        wrap_box(td, xr, xi);
     }
     for (int l = 0; l <= td.bmax; l++) {
         const unsigned long long e = act ? (unsigned long long)td.tab_off[l] + cell_key(td, l, xi) : ~0ull;
@@ -437,7 +466,8 @@ __global__ void k_hier_mark(int n, const double* __restrict__ x, const double* _
     }
 }
 
-// Every point within H of x lies in the 3x3x3 cells around x's cell on a level
+// Every point within H of x (x wrapped into the box on periodic axes, as the
+// marks are) lies in the 3x3x3 cells around x's cell on a level
 // whose cells are at least H wide (per axis the cells c - 1 .. c + 1, wrapping
 // on periodic axes of three or more cells; an axis of fewer cells is taken
 // whole), and so does its cell by the same clamped floor; of those, only the
@@ -456,7 +486,9 @@ __global__ void k_hier_mode(int n, const double* __restrict__ x, const double* _
         mode[i] = kModeSolve;
         return;
     }
-    const double xi[3] = {x[i], y[i], z[i]};
+    const double xr[3] = {x[i], y[i], z[i]};
+    double xi[3];
+    wrap_box(td, xr, xi);
     const double h = H[i];
     const double h2 = (h * (1.0 + 1e-9)) * (h * (1.0 + 1e-9));
     int l = td.bmax;
