@@ -197,6 +197,12 @@ def test_hierarchical_step_argument_checks():
                 ctx.step_hier(st, bad, 2, 1e-3, rebin=True, active=active)
             assert e.value.status == -1 and "bins" in str(e.value)
     assert torch.equal(st.x, x0)
+    # an unknown flag bit, through the C ABI directly
+    import ctypes as C
+    pr = st.struct()
+    rc = ctx._L.mfm_step_hier(ctx.h, C.byref(pr), C.c_void_p(b.data_ptr()), C.c_int32(2), C.c_double(1e-3),
+                              C.c_int32(mfm.HIER_REBIN | 4), None)
+    assert rc == -1
     ctx.step_hier(st, b, 2, 1e-3, rebin=True)
     ctx.check()
 
