@@ -50,3 +50,12 @@ def test_algorithmic_units_and_fingerprint():
     for table in (bench.TRAFFIC, bench.COUNTERS):
         for (wl, k), v in table.items():
             assert len(v["fingerprint"]) == 16
+
+
+def test_recorded_counters_belong_to_the_current_kernel_sources():
+    """The traffic and VALU tables were taken on the kernel sources as they
+    stand (the bench reports them as null otherwise)."""
+    import bench
+    fp = bench.source_fingerprint()
+    for table in (bench.TRAFFIC, bench.COUNTERS):
+        assert table and all(v["fingerprint"] == fp for v in table.values())
