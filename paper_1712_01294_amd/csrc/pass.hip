@@ -222,8 +222,10 @@ constexpr double kColdPad = 1.05;   // first scan radius over a cold guess
 constexpr double kWarmPad = 1.03;   // first scan radius over the previous H
 constexpr double kStoreCold = 1.05;   // radii listed by a cold first scan, over the guess
 // a scan pass takes the lanes with R >= kClassRatio Rref within kClassWindow Rref
-// of the first of them on every axis (Rref: the largest trial radius pending)
-constexpr double kClassRatio = 0.5;
+// of the first of them on every axis (Rref: the largest trial radius pending).
+// Fewer, wider classes pay down to a quarter: each pass scans the union once,
+// and its narrow lanes' extra candidates cost less than passes of their own.
+constexpr double kClassRatio = 0.25;
 constexpr double kClassWindow = 2.0;
 
 // Five waves per SIMD (96 VGPRs): the scan is latency-bound, and the extra wave
