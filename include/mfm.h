@@ -251,7 +251,7 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * before anything runs) and whether the particles moved; with
  * MFM_HIER_ACTIVE also once per boundary that not every level is due, where
  * it keeps the cell tables of the last build while no particle has travelled
- * a quarter of the finest cell since (positions may then stand just outside
+ * half of the finest cell since (positions may then stand just outside
  * a periodic box until the next build wraps them).  With max_bin = 0
  * the call performs mfm_step's operations for a fixed dt = T (in separate
  * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64

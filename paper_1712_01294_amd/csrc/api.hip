@@ -947,7 +947,7 @@ static mfm_status do_fluxes_levels(mfm_ctx* c, mfm_particles* p, const long long
 
 // Largest path length since the last build, in finest cells, up to which a
 // partial boundary of a hierarchical step keeps the cell tables.
-constexpr double kSkinCells = 0.25;
+constexpr double kSkinCells = 0.5;
 
 // A sub-step boundary's pass with active subsets (reading R26): kernel
 // lengths and gradients of the due particles only, the others keeping theirs.
@@ -1072,7 +1072,7 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
         bool rebuild = !(active && lmin > 0);
         launch_hier_drift(arrays_of(p), c->ph, delta, rebuild ? 1 : 0, rebuild ? nullptr : c->hmoved, s);
         if (!rebuild) {
-            // keep the tables while no particle has moved a quarter of the finest
+            // keep the tables while no particle has moved half of the finest
             // cell since the build (the scans reach that much further); else
             // wrap the positions and build anew
             double moved = 0.0;
