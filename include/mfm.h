@@ -257,7 +257,9 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * kernels, equal to mfm_step's results to rounding).  MFM scheme, FP64
  * (MFM_MIXED or MFV: MFM_E_INVALID).  On return dp, dE and vsig hold the
  * rates and signal speeds of the last boundary (every level due) and the
- * counters those of its pass. */
+ * counters those of its pass.  An error returned after the checks at the
+ * start leaves the particles and their arrays in an unspecified state (part
+ * of the system step done). */
 #define MFM_HIER_REBIN 1
 #define MFM_HIER_ACTIVE 2
 mfm_status mfm_step_hier(mfm_ctx *ctx, mfm_particles *p, int64_t *bins, int32_t max_bin, double T, int32_t flags,
