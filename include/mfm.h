@@ -150,6 +150,22 @@ void mfm_destroy(mfm_ctx *ctx);
  * arrays are left stale and are rewritten by the next pass. */
 mfm_status mfm_build_neighbours(mfm_ctx *ctx, mfm_particles *p, void *stream);
 
+/* Undo the library's reorderings: puts the particles back in the order the
+ * caller gave them in, for callers that want their results in that order.
+ * Particle k moves to position id[k] in every non-NULL array of p (all rows
+ * of B, grad, alpha and dp), so that afterwards id[i] = i.  id is required
+ * (MFM_E_INVALID if NULL) and must hold every value 0 .. n-1 exactly once,
+ * as it does if the caller set id[i] = i before the first reordering call;
+ * the call checks this on the device and synchronises the stream once, and
+ * returns MFM_E_INVALID with nothing moved if it does not.
+ * The values are moved bit for bit.  Arrays outside p, such as the bins of
+ * mfm_step_hier, are the caller's to move alike (new[id[k]] = old[k], with
+ * id as it stood before the call).  The context's cell tables, lists and
+ * per-level rates belong to the old order afterwards: the passes then
+ * return MFM_E_STATE until mfm_build_neighbours runs, and the next
+ * mfm_step_hier starts with a full pass. */
+mfm_status mfm_unpermute(mfm_ctx *ctx, mfm_particles *p, void *stream);
+
 /* Kernel length (readings R1, R3-R5): H_i is the unique root of
  * (4 pi/3) H^3 n_i(H) = n_ngb, n_i(H) = sum_{r_ij < H} W(r_ij, H) with the
  * cubic spline of support H; nk = n_i(H_i), V = 1/nk.  FP64 in both

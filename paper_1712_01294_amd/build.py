@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmfm.so")
-SOURCES = ["api.hip", "tree.hip", "pass.hip", "step.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "tree.hip", "pass.hip", "step.hip", "adjoint.hip", "order.hip"]
 OBJDIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

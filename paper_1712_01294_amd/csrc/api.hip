@@ -10,6 +10,7 @@
 #include "../../include/mfm.h"
 #include "device.h"
 #include "kernels.h"
+#include "order.h"
 
 using namespace mfm;
 
@@ -396,6 +397,75 @@ mfm_status mfm_build_neighbours(mfm_ctx* c, mfm_particles* p, void* stream) {
     mfm_status st = check_particles(c, p);
     if (st) return st;
     return build(c, p, (hipStream_t)stream, nullptr, 0);
+}
+
+// The particles back in the order they were given in: particle k moves to
+// position id[k] in every array that is set, after a device check (one
+// synchronisation) that id is a permutation of 0 .. n-1.  The context's cell
+// tables, lists and per-level rates belong to the old order afterwards.
+mfm_status mfm_unpermute(mfm_ctx* c, mfm_particles* p, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (!p->id) return fail(c, MFM_E_INVALID, "id is required to restore the input order");
+    const int n = (int)p->n;
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipSetDevice(c->device);
+    launch_fill_u64(1, c->fb_count, 0ull, s);
+    launch_check_perm(n, (const long long*)p->id, c->vtmp, c->fb_count, s);
+    unsigned long long bad = 0;
+    st = hip_check(c, hipMemcpyAsync(&bad, c->fb_count, sizeof bad, hipMemcpyDeviceToHost, s), "id check");
+    if (!st) st = hip_check(c, hipStreamSynchronize(s), "id check");
+    if (st) return st;
+    if (bad) return fail(c, MFM_E_INVALID, "id is not a permutation of 0 .. n-1");
+    launch_narrow_ids(n, (const long long*)p->id, c->idx, s);
+    // each batch: one launch copies its arrays to the staging, one scatters them back
+    GatherBatch sb, cb;
+    sb.count = cb.count = 0;
+    auto flush = [&]() {
+        launch_copy_batch(n, cb, s);
+        launch_unpermute(n, sb, c->idx, s);
+        sb.count = cb.count = 0;
+    };
+    auto add = [&](void* ptr, int rows) {
+        if (!ptr) return;
+        for (int r = 0; r < rows; r++) {
+            if (sb.count == kGatherMax) flush();
+            unsigned long long* stage = c->gtmp + (long long)sb.count * n;
+            cb.src[cb.count] = (const unsigned long long*)ptr + (long long)r * n;
+            cb.dst[cb.count] = stage;
+            cb.count++;
+            sb.src[sb.count] = stage;
+            sb.dst[sb.count] = (unsigned long long*)ptr + (long long)r * n;
+            sb.count++;
+        }
+    };
+    add(p->x, 1);
+    add(p->y, 1);
+    add(p->z, 1);
+    add(p->m, 1);
+    add(p->vx, 1);
+    add(p->vy, 1);
+    add(p->vz, 1);
+    add(p->u, 1);
+    add(p->H, 1);
+    add(p->nk, 1);
+    add(p->V, 1);
+    add(p->B, 6);
+    add(p->rho, 1);
+    add(p->P, 1);
+    add(p->grad, 15);
+    add(p->alpha, 5);
+    add(p->dp, 3);
+    add(p->dE, 1);
+    add(p->vsig, 1);
+    add(p->dm, 1);
+    add(p->id, 1);
+    flush();
+    c->n_tree = -1;
+    c->have_h = c->have_grad = c->have_flux = 0;
+    c->have_levels = 0;
+    c->last = s;
+    return launched(c, "unpermute");
 }
 
 static mfm_status do_solve_h(mfm_ctx* c, mfm_particles* p, hipStream_t s) {

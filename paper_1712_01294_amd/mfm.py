@@ -26,7 +26,7 @@ EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
            "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_tape_bytes", "mfm_step_taped",
            "mfm_step_adjoint_taped", "mfm_set_kernel_timing", "mfm_kernel_time",
-           "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels")
+           "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels", "mfm_unpermute")
 
 # kernels that mfm_kernel_time can report (mfm_kernel)
 KERNELS = {"solve_h": 0, "gradients": 1, "hydro_fluxes": 2}
@@ -83,7 +83,7 @@ def lib() -> C.CDLL:
         L.mfm_destroy.argtypes = [vp]
         L.mfm_destroy.restype = None
         for f in ("mfm_build_neighbours", "mfm_solve_h", "mfm_gradients", "mfm_hydro_fluxes",
-                  "mfm_hydro_pass"):
+                  "mfm_hydro_pass", "mfm_unpermute"):
             getattr(L, f).argtypes = [vp, C.POINTER(Particles), vp]
         L.mfm_step.argtypes = [vp, C.POINTER(Particles), C.c_double, C.POINTER(C.c_double), vp]
         L.mfm_get_counters.argtypes = [vp, C.POINTER(Counters)]
@@ -242,6 +242,12 @@ class Context:
 
     def build_neighbours(self, st: State, stream=None):
         self._call("mfm_build_neighbours", st, stream)
+
+    def unpermute(self, st: State, stream=None):
+        """Move every array of st back to the order the particles were given in
+        (particle k to position st.id[k]); afterwards st.id is 0 .. n-1.  The
+        next pass needs build_neighbours first."""
+        self._call("mfm_unpermute", st, stream)
 
     def solve_h(self, st: State, stream=None):
         self._call("mfm_solve_h", st, stream)
