@@ -79,6 +79,7 @@ int main() {
     mfm_counters cnt;
     expect("build_neighbours: null context", mfm_build_neighbours(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("solve_h: null context", mfm_solve_h(nullptr, &none, nullptr), MFM_E_INVALID);
+    expect("unpermute: null context", mfm_unpermute(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("hydro_pass: null context", mfm_hydro_pass(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("get_counters: null context", mfm_get_counters(nullptr, &cnt), MFM_E_INVALID);
     if (mfm_tape_bytes(nullptr) != -1) {
@@ -108,6 +109,15 @@ int main() {
         none.n = 10;
         expect("build_neighbours: null arrays", mfm_build_neighbours(ctx, &none, nullptr), MFM_E_INVALID);
         expect("solve_h: null arrays", mfm_solve_h(ctx, &none, nullptr), MFM_E_INVALID);
+        expect("unpermute: null arrays", mfm_unpermute(ctx, &none, nullptr), MFM_E_INVALID);
+        {
+            // every required array set (never read: the call stops at the missing id)
+            double dummy[10] = {0};
+            mfm_particles q = none;
+            q.x = q.y = q.z = q.m = q.vx = q.vy = q.vz = q.u = q.H = dummy;
+            q.id = nullptr;
+            expect("unpermute: null id", mfm_unpermute(ctx, &q, nullptr), MFM_E_INVALID);
+        }
         expect("step: null arrays", mfm_step(ctx, &none, 1e-3, nullptr, nullptr), MFM_E_INVALID);
         int64_t bins[1] = {0};
         expect("step_hier: null arrays", mfm_step_hier(ctx, &none, bins, 1, 1e-3, 1, nullptr), MFM_E_INVALID);
