@@ -1035,7 +1035,11 @@ static mfm_status do_pass_active(mfm_ctx* c, mfm_particles* q, const long long* 
     c->rec_mixed = 0;
     c->last = s;
     if (mfm_status st = launched(c, "hydro_pass (active subsets)")) return st;
-    return do_fluxes_levels(c, q, bins, lmin, nlev, c->hhome, s);
+    mfm_status st = do_fluxes_levels(c, q, bins, lmin, nlev, c->hhome, s);
+    // the lists and packed records now hold the due subset only: no later
+    // call may take them for those of a whole pass
+    c->have_h = c->have_grad = c->have_flux = 0;
+    return st;
 }
 
 // The one host synchronisation of a hierarchical step: whether every bin lies in

@@ -931,15 +931,37 @@ enum { R_X = 0, R_IH = 3, R_K = 4, R_RHO = 5, R_P = 6, R_V0 = 7, R_B = 10, R_G =
 // What the gradient kernel reads of a neighbour, packed into one 128-byte line
 // per particle: (x, y, z, H), (rho, vx, vy, vz), (P, gather count, mode, -),
 // unused; the mode (hierarchical steps with active subsets) is 0 without one.
-__global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcount,
-                            const unsigned char* __restrict__ mode, double4* __restrict__ prim) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+__device__ __forceinline__ void pack_one(const PassArrays& a, const Phys& ph, const int* __restrict__ gcount,
+                                         const unsigned char* __restrict__ mode, double4* __restrict__ prim, int i) {
     const double rho = a.m[i] * a.nk[i];
     prim[4 * (long long)i + 0] = make_double4(a.x[i], a.y[i], a.z[i], a.H[i]);
     prim[4 * (long long)i + 1] = make_double4(rho, a.vx[i], a.vy[i], a.vz[i]);
     prim[4 * (long long)i + 2] = make_double4((ph.gamma - 1.0) * rho * a.u[i], (double)gcount[i],
                                               mode ? (double)mode[i] : 0.0, 0.0);
+}
+
+__global__ void k_pack_prim(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                            const unsigned char* __restrict__ mode, double4* __restrict__ prim) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    pack_one(a, ph, gcount, mode, prim, i);
+}
+
+// A boundary with active subsets reads the records of the active particles'
+// gather neighbours (their gradients) and of the active particles themselves
+// (the kept particles' tail appends) only: each active particle packs its own
+// and its gather neighbours' records.  A record packed by several of them gets
+// the same values from each.  The others keep stale records, which no kernel
+// of that boundary reads.
+__global__ void k_pack_prim_active(PassArrays a, Phys ph, const int* __restrict__ gcount,
+                                   const unsigned char* __restrict__ mode, const int* __restrict__ list,
+                                   double4* __restrict__ prim) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n || mode[i] != kModeSolve) return;
+    const long long n = a.n;
+    pack_one(a, ph, gcount, mode, prim, i);
+    const int cnum = gcount[i];
+    for (int k = 0; k < cnum; k++) pack_one(a, ph, gcount, mode, prim, list[(long long)k * n + i]);
 }
 
 // i is outside j's gather set: the pair enters j's flux list as a tail entry
@@ -975,9 +997,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGradWaves)
         const int cnum = gcount[i];
         for (int k = 0; k < cnum; k++) {
             const int j = list[(long long)k * n + i];
+            if (mode[j] != kModeSolve) continue;   // the pair is not due (and j's record may be stale)
             const double4 pj = prim[4 * (long long)j + 0];
             const double4 pg = prim[4 * (long long)j + 2];
-            if (pg.z != (double)kModeSolve) continue;   // the pair is not due
             double d[3];
             displacement(ph, xi, pj.x, pj.y, pj.z, d);
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -1753,7 +1775,7 @@ void launch_solve_h_active(const PassArrays& a, const TreeDesc& td, const int2* 
 void launch_gradients_active(const PassArrays& a, const Phys& ph, const unsigned char* mode, const long long* home,
                              const int* gcount, int* counts, int* list, int* tails, double4* prim, void* rec,
                              Counters* cnt, hipStream_t s) {
-    k_pack_prim<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, mode, prim);
+    k_pack_prim_active<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, mode, list, prim);
     k_gradients<false, true><<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, gcount, counts, list, tails, prim, rec, cnt,
                                                                  mode, home);
     k_pack_rec_kept<<<blocks_of(a.n, 256), 256, 0, s>>>(a, ph, mode, home, counts, (double*)rec);
