@@ -83,14 +83,14 @@ KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/cs
 # known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
 # only for the kernel sources whose fingerprint is recorded with it.
 TRAFFIC = {
-    ("clustered", "solve_h"): {"bytes_per_launch": 1.2381e+11, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "gradients"): {"bytes_per_launch": 3.0490e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 1.3777e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "solve_h_mixed"): {"bytes_per_launch": 1.2381e+11, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "gradients_mixed"): {"bytes_per_launch": 2.7621e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mixed"): {"bytes_per_launch": 1.5467e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 1.4171e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mfv_mixed"): {"bytes_per_launch": 1.5369e+10, "fingerprint": "75d13d2182c22f14"},
+    ("clustered", "solve_h"): {"bytes_per_launch": 1.2371e+11, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "gradients"): {"bytes_per_launch": 3.0493e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 1.3788e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "solve_h_mixed"): {"bytes_per_launch": 1.2371e+11, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "gradients_mixed"): {"bytes_per_launch": 2.7642e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mixed"): {"bytes_per_launch": 1.5475e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 1.4163e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mfv_mixed"): {"bytes_per_launch": 1.5405e+10, "fingerprint": "9c6fa2269ac9ec8c"},
 }
 
 # VALU counters per launch from rocprofv3 --pmc passes over this benchmark:
@@ -98,14 +98,14 @@ TRAFFIC = {
 # percentage (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE, 256 CUs) and VALU
 # instructions issued.  Keyed and fingerprinted like TRAFFIC.
 COUNTERS = {
-    ("clustered", "solve_h"): {"valu_busy_pct": 70.6, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "gradients"): {"valu_busy_pct": 27.7, "fp64_flops_per_launch": 1.0868e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 2.1952e+09, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes"): {"valu_busy_pct": 52.3, "fp64_flops_per_launch": 3.6667e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 5.7054e+09, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "solve_h_mixed"): {"valu_busy_pct": 70.6, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "gradients_mixed"): {"valu_busy_pct": 31.0, "fp64_flops_per_launch": 9.3961e+10, "fp32_flops_per_launch": 1.4820e+10, "valu_insts_per_launch": 2.2503e+09, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mixed"): {"valu_busy_pct": 77.5, "fp64_flops_per_launch": 6.8311e+10, "fp32_flops_per_launch": 2.7785e+11, "valu_insts_per_launch": 5.8521e+09, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mfv"): {"valu_busy_pct": 61.5, "fp64_flops_per_launch": 4.8855e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 7.2402e+09, "fingerprint": "75d13d2182c22f14"},
-    ("clustered", "hydro_fluxes_mfv_mixed"): {"valu_busy_pct": 95.5, "fp64_flops_per_launch": 7.0260e+10, "fp32_flops_per_launch": 3.9681e+11, "valu_insts_per_launch": 7.3923e+09, "fingerprint": "75d13d2182c22f14"},
+    ("clustered", "solve_h"): {"valu_busy_pct": 70.8, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "gradients"): {"valu_busy_pct": 27.7, "fp64_flops_per_launch": 1.0868e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 2.1952e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes"): {"valu_busy_pct": 52.5, "fp64_flops_per_launch": 3.6667e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 5.7054e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "solve_h_mixed"): {"valu_busy_pct": 70.8, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "gradients_mixed"): {"valu_busy_pct": 31.3, "fp64_flops_per_launch": 9.3961e+10, "fp32_flops_per_launch": 1.4820e+10, "valu_insts_per_launch": 2.2503e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mixed"): {"valu_busy_pct": 77.2, "fp64_flops_per_launch": 6.8311e+10, "fp32_flops_per_launch": 2.7785e+11, "valu_insts_per_launch": 5.8521e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mfv"): {"valu_busy_pct": 61.6, "fp64_flops_per_launch": 4.8855e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 7.2402e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "hydro_fluxes_mfv_mixed"): {"valu_busy_pct": 95.5, "fp64_flops_per_launch": 7.0260e+10, "fp32_flops_per_launch": 3.9681e+11, "valu_insts_per_launch": 7.3923e+09, "fingerprint": "9c6fa2269ac9ec8c"},
 }
 
 

@@ -29,6 +29,9 @@ struct mfm_ctx {
     TreeDesc td;
     Phys ph;
     long long tab_len = 0;
+    // tab holds exactly the cells of the first tab_keys_n sorted keys in
+    // keys (-1: not known, so the next build clears the whole table)
+    long long tab_keys_n = -1;
     unsigned long long *keys = nullptr, *ktmp = nullptr;
     int *idx = nullptr, *vtmp = nullptr, *hist = nullptr, *scan_tmp = nullptr;
     unsigned long long* gtmp = nullptr;   // kGatherMax x cap staging for in-place reordering
@@ -343,6 +346,10 @@ static PassArrays arrays_of(const mfm_particles* p) {
 static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* const* extra, int nextra) {
     const int n = (int)p->n;
     (void)hipSetDevice(c->device);
+    // clear the last build's cells while its sorted keys are still there
+    if (c->tab_keys_n > 0) launch_untables((int)c->tab_keys_n, c->keys, c->td, c->tab, s);
+    else launch_fill_u64(c->tab_len, (unsigned long long*)c->tab, 0ull, s);
+    c->tab_keys_n = -1;
     launch_keys(n, p->x, p->y, p->z, c->td, c->keys, c->idx, s);
     radix_sort(n, c->td.ktot, c->keys, c->idx, c->ktmp, c->vtmp, c->hist, c->scan_tmp, s);
     // each batch: one launch copies its arrays to the staging, one gathers them back in key order
@@ -384,13 +391,14 @@ static mfm_status build(mfm_ctx* c, mfm_particles* p, hipStream_t s, double* con
     add(p->id);
     for (int k = 0; k < nextra; k++) add(extra[k]);
     flush();
-    launch_fill_u64(c->tab_len, (unsigned long long*)c->tab, 0ull, s);
     launch_tables(n, c->keys, c->td, c->tab, s);
     launch_pos4(n, p->x, p->y, p->z, c->pos, s);
     c->n_tree = n;
     c->have_h = c->have_grad = c->have_flux = 0;
     c->last = s;
-    return launched(c, "build_neighbours");
+    mfm_status st = launched(c, "build_neighbours");
+    if (!st) c->tab_keys_n = n;
+    return st;
 }
 
 mfm_status mfm_build_neighbours(mfm_ctx* c, mfm_particles* p, void* stream) {
@@ -1310,6 +1318,7 @@ extern "C" mfm_status mfm_hydro_pass_noalloc(const mfm_params* params, mfm_parti
                                         kNoAllocScanInts)
         return fail(c, MFM_E_CAPACITY, "cell tables or scan scratch exceed the no-allocation scratch");
     noalloc_carve(c, (unsigned char*)g_noalloc_ptr[dev]);
+    c->tab_keys_n = -1;   // the shared array may hold another call's tables
     c->n_tree = -1;
     c->have_h = c->have_grad = c->have_flux = 0;
     c->err[0] = 0;

@@ -41,6 +41,8 @@ void launch_reset_counters(Counters* c, hipStream_t s);
 // dst[a][k] = src[a][k], k < n, for the arrays of the batch in one launch
 void launch_copy_batch(int n, const GatherBatch& gb, hipStream_t s);
 void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s);
+// clears the entries that launch_tables wrote for the same n sorted keys
+void launch_untables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s);
 void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s);
 
 // pass.hip

@@ -257,6 +257,23 @@ __global__ void k_tables(int n, const unsigned long long* __restrict__ keys, Tre
     }
 }
 
+// Undo k_tables for the same sorted keys: the first particle of each cell
+// clears that cell's entry on every level, so a build clears only the entries
+// the last one wrote instead of the whole table.
+__global__ void k_untables(int n, const unsigned long long* __restrict__ keys, TreeDesc td,
+                           int2* __restrict__ tab) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    unsigned long long key = keys[k];
+    if (key >> td.ktot) return;   // k_tables wrote nothing for it
+    unsigned long long prev = k > 0 ? keys[k - 1] : 0;
+    for (int l = 0; l <= td.bmax; l++) {
+        int sh = td.ktot - td.kbits[l];
+        unsigned long long c = key >> sh;
+        if (k == 0 || (prev >> sh) != c) tab[td.tab_off[l] + (long long)c] = make_int2(0, 0);
+    }
+}
+
 // positions packed per particle for the neighbour scans (one 32-byte load)
 __global__ void k_pos4(int n, const double* __restrict__ x, const double* __restrict__ y,
                        const double* __restrict__ z, double4* __restrict__ pos) {
@@ -292,6 +309,10 @@ void launch_fill_u64(long long m, unsigned long long* p, unsigned long long v, h
 
 void launch_tables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s) {
     k_tables<<<(n + 255) / 256, 256, 0, s>>>(n, keys, td, tab);
+}
+
+void launch_untables(int n, const unsigned long long* keys, const TreeDesc& td, int2* tab, hipStream_t s) {
+    k_untables<<<(n + 255) / 256, 256, 0, s>>>(n, keys, td, tab);
 }
 
 void launch_pos4(int n, const double* x, const double* y, const double* z, double4* pos, hipStream_t s) {
