@@ -359,6 +359,38 @@ def run_precision(mfm, w, prec, kw, args, stream, scheme=0):
     return ctx, st, tm, kern, cnt
 
 
+def hier_bins(cfg, st, max_bin, ctx):
+    """Time bins from the state's last pass on ctx (the hierarchical leg's
+    binning), in the particles' current order:
+    dt_i = min(cfl H_i / vsig_i, sqrt(2 cfl H_i / |a_i|)) with a_i = dp_i / m_i,
+    bin_i = max_bin - floor(log2(dt_i / dt_min)) clamped to [0, max_bin];
+    then the neighbour limiter of individual time-step schemes: each bin is
+    raised to at least its flux neighbours' bins minus one, until no bin
+    changes, so neighbours step at most a factor 2 apart.  Returns (bins,
+    T = 2^max_bin dt_min, dt_min, number of bins the limiter raised)."""
+    import torch
+    acc = torch.sqrt((st.dp * st.dp).sum(0)) / st.m
+    dti = torch.minimum(cfg.cfl * st.H / st.vsig, torch.sqrt(2.0 * cfg.cfl * st.H / acc)).double()
+    dtmin = float(dti.min())
+    if not (dtmin > 0.0 and np.isfinite(dtmin)):
+        raise RuntimeError(f"hierarchical leg: no finite step (min {dtmin})")
+    bins = (max_bin - torch.floor(torch.log2(dti / dtmin))).clamp(0, max_bin).to(torch.int64).contiguous()
+    counts, lst = ctx.flux_lists(st.n)
+    raised = 0
+    for _ in range(max_bin + 1):
+        nb = torch.full_like(bins, -1)
+        for k in range(int(counts.max())):
+            nb = torch.maximum(nb, torch.where(counts > k, bins[lst[k].long()], -1))
+        new = torch.maximum(bins, nb - 1)
+        changed = int((new != bins).sum())
+        bins = new
+        raised += changed
+        if changed == 0:
+            break
+    del counts, lst
+    return bins.contiguous(), dtmin * (1 << max_bin), dtmin, raised
+
+
 def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
     """Hierarchical power-of-two steps on the same set.  Each particle's bin
     comes from its step of an initial pass, the smaller of the Courant step
@@ -366,28 +398,23 @@ def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
     which its acceleration a_i = dp_i / m_i alone moves it by cfl H_i,
     sqrt(2 cfl H_i / |a_i|): with dt_min the smallest,
     bin_i = max_bin - floor(log2(dt_i / dt_min)), clamped to [0, max_bin], so
-    it steps by T / 2^bin_i <= dt_i within the system step T = 2^max_bin dt_min.
-    One system step (2^max_bin sub-steps, each pass evaluating only the due
+    it steps by T / 2^bin_i <= dt_i within the system step T = 2^max_bin dt_min;
+    the neighbour limiter then keeps flux neighbours within one bin of each
+    other (hier_bins).  One system step (2^max_bin sub-steps, each pass evaluating only the due
     pairs' fluxes) is timed against the 2^max_bin global steps of dt_min that
     cover the same time from the same state; every timed call is logged and
     followed by the counters' check, so a state that went non-finite ends the
     leg with an error instead of slowing the solves."""
-    import numpy as np
     import torch
     cfg = mfm.config_of(w, **kw)
     ctx = mfm.Context(cfg, w.n)
     st = mfm.State.from_arrays(w.arrays())
     ctx.build_neighbours(st)
     ctx.hydro_pass(st)
-    acc = torch.sqrt((st.dp * st.dp).sum(0)) / st.m
-    dti = torch.minimum(cfg.cfl * st.H / st.vsig, torch.sqrt(2.0 * cfg.cfl * st.H / acc)).double()
-    dtmin = float(dti.min())
-    if not (dtmin > 0.0 and np.isfinite(dtmin)):
-        raise RuntimeError(f"hierarchical leg: no finite step (min {dtmin})")
-    bins = (max_bin - torch.floor(torch.log2(dti / dtmin))).clamp(0, max_bin).to(torch.int64).contiguous()
-    T = dtmin * (1 << max_bin)
+    bins, T, dtmin, raised = hier_bins(cfg, st, max_bin, ctx)
     hist = torch.bincount(bins, minlength=max_bin + 1).tolist()
-    log(f"hierarchical: cfl {cfg.cfl}, dt_min {dtmin:.3e}, T {T:.3e}, particles per bin {hist}")
+    log(f"hierarchical: cfl {cfg.cfl}, dt_min {dtmin:.3e}, T {T:.3e}, particles per bin {hist} "
+        f"({raised} raised by the neighbour limiter)")
     start = {k: getattr(st, k).clone() for k in ("x", "y", "z", "vx", "vy", "vz", "u", "id")}
     b0 = bins.clone()
 
@@ -416,12 +443,13 @@ def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):
 
     act = timed("system step, active subsets", lambda: ctx.step_hier(st, bins, max_bin, T, rebin=True, active=True))
     if active_only:
-        return {"max_bin": max_bin, "bin_counts": hist, "ms_per_system_step_active": act}
+        return {"max_bin": max_bin, "bin_counts": hist, "limiter_raised": raised, "ms_per_system_step_active": act}
     hier = timed("system step, every particle", lambda: ctx.step_hier(st, bins, max_bin, T, rebin=True))
     glob = timed(f"{1 << max_bin} global steps", lambda: [ctx.step(st, dtmin) for _ in range(1 << max_bin)])
     del ctx, st
     torch.cuda.empty_cache()
-    return {"max_bin": max_bin, "sub_steps": 1 << max_bin, "bin_counts": hist, "T": T, "dt_min": dtmin,
+    return {"max_bin": max_bin, "sub_steps": 1 << max_bin, "bin_counts": hist, "limiter_raised": raised,
+            "T": T, "dt_min": dtmin,
             "ms_per_system_step_active": act, "ms_per_system_step": hier, "global_ms": glob,
             "speedup_vs_global_active": glob / act, "speedup_vs_global": glob / hier,
             "note": "wall clock of one system step (the levelled pass of every level at its start included) "

@@ -251,7 +251,11 @@ mfm_status mfm_step(mfm_ctx *ctx, mfm_particles *p, double dt, double *dt_used, 
  * (during the call B and grad hold each particle's values in the column where
  * it stood at the call's start; on return every array is in the particles'
  * current order), and enter the due pairs with their current positions and
- * predicted state.
+ * predicted state.  Choosing the bins is the caller's part: with active
+ * subsets, a kept particle whose flux neighbours sit several levels finer
+ * keeps its geometry and coarse rates while they move, and can run away;
+ * bins where flux neighbours differ by at most one level (the usual
+ * neighbour time-step limiter) avoid that.
  * At the last boundary of T every level is due either way.  The per-level
  * rates live in the context (allocated on the first call, 32 doubles per
  * particle; with MFM_HIER_ACTIVE also one byte per particle and one bit per

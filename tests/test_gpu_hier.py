@@ -501,3 +501,76 @@ def test_active_subsets_on_an_open_box():
     ctx.step_hier(st, b, 2, T, rebin=True, active=True)
     ctx.check()
     _compare_with_oracle(st, ref, ctx, w, 3)
+
+
+def test_active_subsets_at_the_benchmark_size_conserve():
+    """The benchmark's own configuration, where no oracle runs: the clustered
+    16,777,216-particle set, binned over four levels as the hierarchical leg
+    bins it (with the neighbour limiter), one system step with a rebin and
+    active subsets.  What holds at any size: momentum conserved to rounding,
+    masses untouched, every kernel length converged and every output finite,
+    and the bins carried along with the particles; the largest speed within
+    1.5 times that of the 8 global steps of dt_min over the same time, from
+    the same state (both reach about 35 times the initial one as the dense
+    clumps expand).  Total energy is conserved
+    to rounding but for the floor on u, which only adds energy: a few hundred
+    particles of this far-from-equilibrium set reach it, in global steps as
+    well (the 8 global steps over the same time add 1.5e-4 of E, this step
+    3.7e-4).  So no energy may be lost beyond rounding, and the gain stays
+    below 1e-3 of E: without the neighbour limiter a kept particle beside
+    much finer ones runs away to 50 times the largest speed, and the floors
+    then add 6.9e-2."""
+    import torch
+
+    import bench
+    from paper_1712_01294_amd import mfm
+    w = W.clustered()
+    cfg = mfm.config_of(w)
+    ctx = mfm.Context(cfg, w.n)
+    st = mfm.State.from_arrays(w.arrays())
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    bins, T, dtmin, raised = bench.hier_bins(cfg, st, 3, ctx)
+    hist = torch.bincount(bins, minlength=4).tolist()
+    print("bins", hist, "raised by the limiter", raised, flush=True)
+    assert all(c > 0 for c in hist)
+    bin_of = torch.empty_like(bins)
+    bin_of[st.id] = bins
+
+    def totals():
+        m = st.m
+        p = [float((m * getattr(st, k)).sum()) for k in ("vx", "vy", "vz")]
+        E = float((m * (st.u + 0.5 * (st.vx ** 2 + st.vy ** 2 + st.vz ** 2))).sum())
+        return p, E, float((m * st.vx).abs().sum()), float(m.sum())
+
+    def vmax():
+        return float(torch.sqrt(st.vx ** 2 + st.vy ** 2 + st.vz ** 2).max())
+
+    start = {k: getattr(st, k).clone() for k in ("x", "y", "z", "vx", "vy", "vz", "u", "H", "id")}
+    p0, E0, scale, M0 = totals()
+    ctx.step_hier(st, bins, 3, T, rebin=True, active=True)
+    ctx.check(allow_illcond=True)
+    cnt = ctx.counters()
+    assert cnt["noconv"] == 0 and cnt["nonfinite"] == 0, cnt
+    p1, E1, _, M1 = totals()
+    print("momentum drift", [abs(a - b) / scale for a, b in zip(p1, p0)], "energy", (E1 - E0) / E0,
+          "floors", cnt["floors"], flush=True)
+    assert M1 == M0
+    for c in range(3):
+        assert abs(p1[c] - p0[c]) <= 1e-13 * scale, c
+    if cnt["floors"] == 0:
+        assert E1 == pytest.approx(E0, rel=1e-13)
+    else:
+        assert E0 * (1.0 - 1e-13) <= E1 <= E0 * (1.0 + 1e-3)
+    assert torch.equal(bins, bin_of[st.id])
+    v_hier = vmax()
+    for k, v in start.items():
+        getattr(st, k).copy_(v)
+    ctx.build_neighbours(st)
+    ctx.hydro_pass(st)
+    for _ in range(8):
+        ctx.step(st, dtmin)
+    ctx.check(allow_illcond=True)
+    v_glob = vmax()
+    print("largest speed: hierarchical", v_hier, "global", v_glob, flush=True)
+    assert v_hier <= 1.5 * v_glob
