@@ -284,7 +284,10 @@ def test_active_subsets_on_a_clustered_set():
     1,124 to 5,325 particles active on the partial boundaries).  The set starts
     far from equilibrium and the Courant step does not bound its
     accelerations, so the system step is the smallest Courant step (the bins
-    then step by 1/8 to 1 of it).  One system step with active subsets within
+    then step by 1/8 to 1 of it).  (With the benchmark's binning, bounded by
+    the accelerations and limited between neighbours, and T = 8 dt_min, the
+    oracle's own step stops at this resolution: a kernel length reaches half
+    the box within the step.)  One system step with active subsets within
     1e-10 of the oracle."""
     import torch
     w = W.clustered(n_side=32, seed=W.SEED_BASE + 174)
