@@ -83,14 +83,14 @@ KERNEL_SOURCES = ("paper_1712_01294_amd/csrc/pass.hip", "paper_1712_01294_amd/cs
 # known size (bench.py --copy-probe).  Keyed by workload and kernel, and valid
 # only for the kernel sources whose fingerprint is recorded with it.
 TRAFFIC = {
-    ("clustered", "solve_h"): {"bytes_per_launch": 1.2371e+11, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "gradients"): {"bytes_per_launch": 3.0493e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 1.3788e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "solve_h_mixed"): {"bytes_per_launch": 1.2371e+11, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "gradients_mixed"): {"bytes_per_launch": 2.7642e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mixed"): {"bytes_per_launch": 1.5475e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 1.4163e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mfv_mixed"): {"bytes_per_launch": 1.5405e+10, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "solve_h"): {"bytes_per_launch": 1.2331e+11, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "gradients"): {"bytes_per_launch": 3.0494e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes"): {"bytes_per_launch": 1.3791e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "solve_h_mixed"): {"bytes_per_launch": 1.2331e+11, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "gradients_mixed"): {"bytes_per_launch": 2.7638e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mixed"): {"bytes_per_launch": 1.5502e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mfv"): {"bytes_per_launch": 1.4172e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mfv_mixed"): {"bytes_per_launch": 1.5410e+10, "fingerprint": "4d9f0a385d8119e7"},
 }
 
 # VALU counters per launch from rocprofv3 --pmc passes over this benchmark:
@@ -98,14 +98,14 @@ TRAFFIC = {
 # percentage (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE, 256 CUs) and VALU
 # instructions issued.  Keyed and fingerprinted like TRAFFIC.
 COUNTERS = {
-    ("clustered", "solve_h"): {"valu_busy_pct": 70.8, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "gradients"): {"valu_busy_pct": 27.7, "fp64_flops_per_launch": 1.0868e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 2.1952e+09, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes"): {"valu_busy_pct": 52.5, "fp64_flops_per_launch": 3.6667e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 5.7054e+09, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "solve_h_mixed"): {"valu_busy_pct": 70.8, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "gradients_mixed"): {"valu_busy_pct": 31.3, "fp64_flops_per_launch": 9.3961e+10, "fp32_flops_per_launch": 1.4820e+10, "valu_insts_per_launch": 2.2503e+09, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mixed"): {"valu_busy_pct": 77.2, "fp64_flops_per_launch": 6.8311e+10, "fp32_flops_per_launch": 2.7785e+11, "valu_insts_per_launch": 5.8521e+09, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mfv"): {"valu_busy_pct": 61.6, "fp64_flops_per_launch": 4.8855e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 7.2402e+09, "fingerprint": "9c6fa2269ac9ec8c"},
-    ("clustered", "hydro_fluxes_mfv_mixed"): {"valu_busy_pct": 95.5, "fp64_flops_per_launch": 7.0260e+10, "fp32_flops_per_launch": 3.9681e+11, "valu_insts_per_launch": 7.3923e+09, "fingerprint": "9c6fa2269ac9ec8c"},
+    ("clustered", "solve_h"): {"valu_busy_pct": 70.6, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "gradients"): {"valu_busy_pct": 27.7, "fp64_flops_per_launch": 1.0868e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 2.1952e+09, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes"): {"valu_busy_pct": 52.4, "fp64_flops_per_launch": 3.6667e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 5.7054e+09, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "solve_h_mixed"): {"valu_busy_pct": 70.6, "fp64_flops_per_launch": 7.3894e+11, "fp32_flops_per_launch": 6.2724e+09, "valu_insts_per_launch": 1.7271e+10, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "gradients_mixed"): {"valu_busy_pct": 30.1, "fp64_flops_per_launch": 9.3961e+10, "fp32_flops_per_launch": 1.4820e+10, "valu_insts_per_launch": 2.2503e+09, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mixed"): {"valu_busy_pct": 77.4, "fp64_flops_per_launch": 6.8311e+10, "fp32_flops_per_launch": 2.7785e+11, "valu_insts_per_launch": 5.8521e+09, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mfv"): {"valu_busy_pct": 61.8, "fp64_flops_per_launch": 4.8855e+11, "fp32_flops_per_launch": 0.0000e+00, "valu_insts_per_launch": 7.2402e+09, "fingerprint": "4d9f0a385d8119e7"},
+    ("clustered", "hydro_fluxes_mfv_mixed"): {"valu_busy_pct": 95.6, "fp64_flops_per_launch": 7.0260e+10, "fp32_flops_per_launch": 3.9681e+11, "valu_insts_per_launch": 7.3923e+09, "fingerprint": "4d9f0a385d8119e7"},
 }
 
 
@@ -364,9 +364,10 @@ def hier_bins(cfg, st, max_bin, ctx):
     binning), in the particles' current order:
     dt_i = min(cfl H_i / vsig_i, sqrt(2 cfl H_i / |a_i|)) with a_i = dp_i / m_i,
     bin_i = max_bin - floor(log2(dt_i / dt_min)) clamped to [0, max_bin];
-    then the neighbour limiter of individual time-step schemes: each bin is
-    raised to at least its flux neighbours' bins minus one, until no bin
-    changes, so neighbours step at most a factor 2 apart.  Returns (bins,
+    then the neighbour limiter of individual time-step schemes
+    (mfm_limit_bins): each bin is raised to at least its flux neighbours' bins
+    minus one, until no bin changes, so neighbours step at most a factor 2
+    apart.  Returns (bins,
     T = 2^max_bin dt_min, dt_min, number of bins the limiter raised)."""
     import torch
     acc = torch.sqrt((st.dp * st.dp).sum(0)) / st.m
@@ -375,20 +376,8 @@ def hier_bins(cfg, st, max_bin, ctx):
     if not (dtmin > 0.0 and np.isfinite(dtmin)):
         raise RuntimeError(f"hierarchical leg: no finite step (min {dtmin})")
     bins = (max_bin - torch.floor(torch.log2(dti / dtmin))).clamp(0, max_bin).to(torch.int64).contiguous()
-    counts, lst = ctx.flux_lists(st.n)
-    raised = 0
-    for _ in range(max_bin + 1):
-        nb = torch.full_like(bins, -1)
-        for k in range(int(counts.max())):
-            nb = torch.maximum(nb, torch.where(counts > k, bins[lst[k].long()], -1))
-        new = torch.maximum(bins, nb - 1)
-        changed = int((new != bins).sum())
-        bins = new
-        raised += changed
-        if changed == 0:
-            break
-    del counts, lst
-    return bins.contiguous(), dtmin * (1 << max_bin), dtmin, raised
+    raised = ctx.limit_bins(st, bins, max_bin)
+    return bins, dtmin * (1 << max_bin), dtmin, raised
 
 
 def hierarchical_timing(mfm, w, kw, max_bin=3, reps=3, active_only=False):

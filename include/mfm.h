@@ -292,6 +292,19 @@ mfm_status mfm_step_hier(mfm_ctx *ctx, mfm_particles *p, int64_t *bins, int32_t 
  * step yet, or another pass since). */
 mfm_status mfm_copy_levels(mfm_ctx *ctx, double *out, void *stream);
 
+/* The neighbour time-step limiter for the bins of mfm_step_hier (section 3's
+ * individual time steps leave the choice of bins to the caller): raises each
+ * bins[i] (device, int64, n, current particle order, in place) to at least
+ * its flux neighbours' bins minus one, in sweeps until no bin changes, so
+ * that neighbours step at most a factor 2 apart.  Uses the flux lists of the
+ * last pass on these particles (MFM_E_STATE if there are none, as after
+ * mfm_build_neighbours alone).  Bins outside 0 .. max_bin (max_bin <= 7):
+ * MFM_E_INVALID, nothing changed.  *raised (host, nullable) receives the
+ * number of raises.  Synchronises the stream once per sweep, at most
+ * max_bin + 2 times. */
+mfm_status mfm_limit_bins(mfm_ctx *ctx, const mfm_particles *p, int64_t *bins, int32_t max_bin, int64_t *raised,
+                          void *stream);
+
 /* Adjoint of the pass (reading R20; MFM scheme with limiter 0 only, else
  * MFM_E_INVALID): given the adjoints adj_dp (3 x n) and
  * adj_dE (n) of the pass outputs, write the adjoints of its inputs adj_x

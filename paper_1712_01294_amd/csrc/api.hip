@@ -1202,6 +1202,46 @@ extern "C" mfm_status mfm_step_hier(mfm_ctx* c, mfm_particles* p, int64_t* bins,
     return launched(c, "step_hier");
 }
 
+// The neighbour time-step limiter on the last pass's flux lists, in sweeps
+// until no bin changes (one synchronisation each; a bin rises at most max_bin
+// times, so at most max_bin + 1 sweeps).
+extern "C" mfm_status mfm_limit_bins(mfm_ctx* c, const mfm_particles* p, int64_t* bins, int32_t max_bin,
+                                     int64_t* raised, void* stream) {
+    mfm_status st = check_particles(c, p);
+    if (st) return st;
+    if (!bins) return fail(c, MFM_E_INVALID, "bins is required");
+    if (max_bin < 0 || max_bin > kMaxBin) return fail(c, MFM_E_INVALID, "max_bin must lie in 0 .. 7");
+    if (!c->have_grad || c->n_tree != p->n)
+        return fail(c, MFM_E_STATE, "no flux lists of these particles (a pass must run first)");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)p->n;
+    long long* next = (long long*)c->ktmp;
+    unsigned long long word = 0, total = 0;
+    launch_fill_u64(1, c->fb_count, 0ull, s);
+    launch_check_bins(n, (const long long*)bins, max_bin, c->fb_count, s);
+    for (int sweep = 0; sweep <= max_bin + 1; sweep++) {
+        if ((st = hip_check(c, hipMemcpyAsync(&word, c->fb_count, sizeof word, hipMemcpyDeviceToHost, s),
+                            "limiter count")))
+            return st;
+        if ((st = hip_check(c, hipStreamSynchronize(s), "limiter count"))) return st;
+        if (sweep == 0) {
+            if (word & 1ull) return fail(c, MFM_E_INVALID, "a bin lies outside 0 .. max_bin");
+        } else {
+            total += word;
+            if (word == 0) break;
+        }
+        launch_fill_u64(1, c->fb_count, 0ull, s);
+        launch_limit_bins(n, c->ph.max_ngb, c->counts, c->list, (const long long*)bins, next, c->fb_count, s);
+        if ((st = hip_check(c, hipMemcpyAsync(bins, next, sizeof(long long) * n, hipMemcpyDeviceToDevice, s),
+                            "limited bins")))
+            return st;
+    }
+    if (raised) *raised = (int64_t)total;
+    c->last = s;
+    return launched(c, "limit_bins");
+}
+
 extern "C" mfm_status mfm_copy_levels(mfm_ctx* c, double* out, void* stream) {
     if (!c || !out) return MFM_E_INVALID;
     if (!c->have_levels || !c->lev) return fail(c, MFM_E_STATE, "no per-level rates (run mfm_step_hier first)");

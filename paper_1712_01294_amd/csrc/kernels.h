@@ -116,6 +116,11 @@ void launch_hier_predict(int n, const double* m, const double* vx, const double*
 void launch_iota(int n, long long* v, hipStream_t s);
 // *bad |= 1 when some bin lies outside 0 .. max_bin
 void launch_check_bins(int n, const long long* bins, int max_bin, unsigned long long* bad, hipStream_t s);
+// one sweep of the neighbour time-step limiter over the flux lists:
+// out[i] = max(bin[i], max over i's flux neighbours j of bin[j] - 1); *raised
+// += the number of bins it raised
+void launch_limit_bins(int n, int cap, const int* counts, const int* list, const long long* bin, long long* out,
+                       unsigned long long* raised, hipStream_t s);
 // *diff |= 2 when some particle's (x, y, z, H) differs bit for bit from
 // prim[4 i] (the packed neighbour record of the last gradient pass)
 void launch_same_positions(int n, const double* x, const double* y, const double* z, const double* H,

@@ -400,6 +400,31 @@ void launch_check_bins(int n, const long long* bins, int max_bin, unsigned long 
     k_check_bins<<<(n + 255) / 256, 256, 0, s>>>(n, bins, max_bin, bad);
 }
 
+// One sweep of the neighbour time-step limiter: each bin raised to at least
+// its flux neighbours' bins (as they stood before the sweep) minus one; the
+// number raised is added to *raised.
+__global__ void k_limit_bins(int n, int cap, const int* __restrict__ counts, const int* __restrict__ list,
+                             const long long* __restrict__ bin, long long* __restrict__ out,
+                             unsigned long long* __restrict__ raised) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool up = false;
+    if (i < n) {
+        const long long b = bin[i];
+        long long nb = b;
+        const int cnum = min(counts[i], cap);
+        for (int k = 0; k < cnum; k++) nb = max(nb, bin[list[(long long)k * n + i]] - 1);
+        out[i] = nb;
+        up = nb != b;
+    }
+    const unsigned long long cnt = __popcll(__ballot(up));
+    if (cnt && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(raised, cnt);
+}
+
+void launch_limit_bins(int n, int cap, const int* counts, const int* list, const long long* bin, long long* out,
+                       unsigned long long* raised, hipStream_t s) {
+    k_limit_bins<<<(n + 255) / 256, 256, 0, s>>>(n, cap, counts, list, bin, out, raised);
+}
+
 // the flux lists back to their gather parts (counts = gcount), for a gradient
 // pass that appends the tails again over the lists of an earlier solve
 __global__ void k_reset_counts(int n, const int* __restrict__ gcount, int* __restrict__ counts) {

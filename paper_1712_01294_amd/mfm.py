@@ -26,7 +26,8 @@ EXPORTS = ("mfm_create", "mfm_destroy", "mfm_build_neighbours", "mfm_solve_h", "
            "mfm_copy_flux_lists", "mfm_max_ngb", "mfm_status_str", "mfm_last_error",
            "mfm_hydro_pass_adjoint", "mfm_step_adjoint", "mfm_tape_bytes", "mfm_step_taped",
            "mfm_step_adjoint_taped", "mfm_set_kernel_timing", "mfm_kernel_time",
-           "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels", "mfm_unpermute")
+           "mfm_hydro_pass_noalloc", "mfm_step_hier", "mfm_copy_levels", "mfm_unpermute",
+           "mfm_limit_bins")
 
 # kernels that mfm_kernel_time can report (mfm_kernel)
 KERNELS = {"solve_h": 0, "gradients": 1, "hydro_fluxes": 2}
@@ -107,6 +108,7 @@ def lib() -> C.CDLL:
         L.mfm_hydro_pass_noalloc.argtypes = [C.POINTER(Params), C.POINTER(Particles), C.POINTER(Counters), vp]
         L.mfm_step_hier.argtypes = [vp, C.POINTER(Particles), vp, C.c_int32, C.c_double, C.c_int32, vp]
         L.mfm_copy_levels.argtypes = [vp, vp, vp]
+        L.mfm_limit_bins.argtypes = [vp, C.POINTER(Particles), vp, C.c_int32, C.POINTER(C.c_int64), vp]
         _lib = L
     return _lib
 
@@ -266,6 +268,18 @@ class Context:
         used = C.c_double(0.0)
         self._rc(self._L.mfm_step(self.h, C.byref(p), C.c_double(dt), C.byref(used), _stream(stream)))
         return used.value
+
+    def limit_bins(self, st: State, bins, max_bin: int, stream=None) -> int:
+        """The neighbour time-step limiter (mfm_limit_bins): raises bins (int64
+        device tensor, n, st's current order) in place so that flux neighbours
+        lie at most one bin apart; returns the number of raises."""
+        if bins.dtype != torch.int64 or not bins.is_cuda or not bins.is_contiguous():
+            raise ValueError("bins must be a contiguous int64 device tensor")
+        p = st.struct()
+        raised = C.c_int64(0)
+        self._rc(self._L.mfm_limit_bins(self.h, C.byref(p), C.c_void_p(bins.data_ptr()), C.c_int32(max_bin),
+                                        C.byref(raised), _stream(stream)))
+        return int(raised.value)
 
     def step_hier(self, st: State, bins, max_bin: int, T: float, rebin: bool = False, active: bool = False,
                   stream=None):

@@ -80,6 +80,7 @@ int main() {
     expect("build_neighbours: null context", mfm_build_neighbours(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("solve_h: null context", mfm_solve_h(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("unpermute: null context", mfm_unpermute(nullptr, &none, nullptr), MFM_E_INVALID);
+    expect("limit_bins: null context", mfm_limit_bins(nullptr, &none, nullptr, 3, nullptr, nullptr), MFM_E_INVALID);
     expect("hydro_pass: null context", mfm_hydro_pass(nullptr, &none, nullptr), MFM_E_INVALID);
     expect("get_counters: null context", mfm_get_counters(nullptr, &cnt), MFM_E_INVALID);
     if (mfm_tape_bytes(nullptr) != -1) {
@@ -110,6 +111,7 @@ int main() {
         expect("build_neighbours: null arrays", mfm_build_neighbours(ctx, &none, nullptr), MFM_E_INVALID);
         expect("solve_h: null arrays", mfm_solve_h(ctx, &none, nullptr), MFM_E_INVALID);
         expect("unpermute: null arrays", mfm_unpermute(ctx, &none, nullptr), MFM_E_INVALID);
+        expect("limit_bins: null arrays", mfm_limit_bins(ctx, &none, nullptr, 3, nullptr, nullptr), MFM_E_INVALID);
         {
             // every required array set (never read: the call stops at the missing id)
             double dummy[10] = {0};

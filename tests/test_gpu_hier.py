@@ -577,3 +577,52 @@ def test_active_subsets_at_the_benchmark_size_conserve():
     v_glob = vmax()
     print("largest speed: hierarchical", v_hier, "global", v_glob, flush=True)
     assert v_hier <= 1.5 * v_glob
+
+
+def test_limit_bins_against_the_flux_lists():
+    """mfm_limit_bins on a 4,096-particle box with random bins 0-5: the bins
+    equal a host sweep over the copied flux lists to its fixed point, bit for
+    bit, with the same count of raises; no bin fell and every flux pair lies
+    at most one bin apart.  A bin out of range is rejected with nothing
+    changed, and a context without flux lists with MFM_E_STATE."""
+    import torch
+
+    from paper_1712_01294_amd import mfm
+    w = _smooth(16, W.SEED_BASE + 182)
+    ctx, st = _gpu(w)
+    rng = np.random.default_rng(W.SEED_BASE + 183)
+    b0 = rng.integers(0, 6, size=w.n).astype(np.int64)
+    bins = torch.as_tensor(b0, device="cuda")
+    counts, lst = ctx.flux_lists(w.n)
+    counts, lst = counts.cpu().numpy(), lst.cpu().numpy()
+    b, want_raised = b0.copy(), 0
+    while True:
+        nb = b.copy()
+        for k in range(int(counts.max())):
+            nb = np.maximum(nb, np.where(counts > k, b[lst[k]] - 1, -1))
+        ch = int((nb != b).sum())
+        b = nb
+        want_raised += ch
+        if ch == 0:
+            break
+    raised = ctx.limit_bins(st, bins, 5)
+    got = bins.cpu().numpy()
+    print("raised", raised, flush=True)
+    assert raised == want_raised > 0
+    assert np.array_equal(got, b)
+    assert (got >= b0).all()
+    for k in range(int(counts.max())):
+        i = np.flatnonzero(counts > k)
+        assert (np.abs(got[i] - got[lst[k, i]]) <= 1).all()
+    bad = bins.clone()
+    bad[7] = 6
+    keep = bad.clone()
+    with pytest.raises(mfm.MFMError) as e:
+        ctx.limit_bins(st, bad, 5)
+    assert e.value.status == -1 and torch.equal(bad, keep)
+    fresh = mfm.Context(mfm.config_of(w), w.n)
+    sf = mfm.State.from_arrays(w.arrays())
+    fresh.build_neighbours(sf)
+    with pytest.raises(mfm.MFMError) as e:
+        fresh.limit_bins(sf, torch.zeros(w.n, dtype=torch.int64, device="cuda"), 5)
+    assert e.value.status == -8
